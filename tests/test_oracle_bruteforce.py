@@ -1,0 +1,185 @@
+"""4^3 brute force: an exact rational expansion of the step, written separately
+from the oracle, for every model and every boundary kind.
+
+Each neighbour of each cell is looked up through hand-listed ghost tables
+(below) and every quantity is an exact ``fractions.Fraction``.  The inputs
+are dyadic rationals and the parameters are the exact binary values of the
+doubles handed to the oracle, so the only difference left is the oracle's own
+FP64 rounding.
+"""
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+from paper_1004_0480_amd.workloads import GHOST, HELD, MIRROR, PERIODIC, ModelSpec
+
+N = 4   # cells per axis
+
+# Where the neighbour one step outside a 4-cell axis comes from.  Positions
+# -1 and 4 are the two ghosts; ("cell", q) means "the value of cell q",
+# ("value",) means "the face's fixed value".
+GHOST_TABLE = {
+    MIRROR:   {-1: ("cell", 0), 4: ("cell", 3)},
+    PERIODIC: {-1: ("cell", 3), 4: ("cell", 0)},
+    GHOST:    {-1: ("value",), 4: ("value",)},
+    HELD:     {-1: ("value",), 4: ("value",)},
+}
+FACE_OF = {(0, -1): 0, (0, 4): 1, (1, -1): 2, (1, 4): 3, (2, -1): 4, (2, 4): 5}
+# cell index 0 lies on the low face, 3 on the high face of its axis
+ON_FACE = [(0, 0), (0, 3), (1, 0), (1, 3), (2, 0), (2, 3)]
+
+
+def fr(x):
+    return F(float(x))
+
+
+class Exact:
+    """Exact value lookup for one species: field[(x, y, z)] -> Fraction."""
+
+    def __init__(self, field, bc):
+        self.field = field
+        self.bc = [(kind, fr(v)) for kind, v in bc]
+
+    def held(self, p):
+        for f, (axis, idx) in enumerate(ON_FACE):
+            kind, v = self.bc[f]
+            if kind == HELD and p[axis] == idx:
+                return v
+        return None
+
+    def __call__(self, p):
+        for axis in range(3):
+            if p[axis] in (-1, 4):
+                f = FACE_OF[(axis, p[axis])]
+                kind, v = self.bc[f]
+                src = GHOST_TABLE[kind][p[axis]]
+                if src[0] == "value":
+                    return v
+                q = list(p)
+                q[axis] = src[1]
+                return self(tuple(q))
+        hv = self.held(p)
+        return self.field[p] if hv is None else hv
+
+
+UNIT = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+
+
+def lap(get, p, K, h):
+    total = F(0)
+    for axis, e in enumerate(UNIT):
+        up = tuple(a + b for a, b in zip(p, e))
+        dn = tuple(a - b for a, b in zip(p, e))
+        total += K[axis] * (get(up) + get(dn) - 2 * get(p))
+    return total / (h * h)
+
+
+def exact_step(spec, state):
+    ns, h, dt = spec.ns, fr(spec.h), fr(spec.dt)
+    K = [[fr(v) for v in row] for row in spec.K]
+    P = {k: fr(v) for k, v in spec.params.items()}
+    gets = [Exact(state[s], spec.bc[s]) for s in range(ns)]
+    cells = [(x, y, z) for z in range(N) for y in range(N) for x in range(N)]
+    mu_get = None
+    if spec.model == "front_ch":
+        mu = {p: P["gamma"] * gets[2](p) ** 3 - P["eps"] * gets[2](p)
+              - P["kappa"] * lap(gets[2], p, [F(1)] * 3, h) for p in cells}
+        mu_get = Exact(mu, [(MIRROR, 0.0)] * 6)
+    src = {}
+    if spec.model == "pollutant" and spec.sources is not None:
+        for cell, sp, r in zip(*spec.sources):
+            x, y, z = int(cell) % N, (int(cell) // N) % N, int(cell) // (N * N)
+            src[(x, y, z, int(sp))] = src.get((x, y, z, int(sp)), F(0)) + fr(r)
+    new = [dict() for _ in range(ns)]
+    for p in cells:
+        c = [g(p) for g in gets]
+        rate = [lap(gets[s], p, K[s], h) for s in range(ns)]
+        if spec.model == "brusselator":
+            a, b = P["a"], P["b"]
+            rate[0] += a - (b + 1) * c[0] + c[0] ** 2 * c[1]
+            rate[1] += b * c[0] - c[0] ** 2 * c[1]
+        elif spec.model == "front_ch":
+            r = P["k"] * c[0] * c[1]
+            rate[0] -= r
+            rate[1] -= r
+            rate[2] += r + P["M"] * lap(mu_get, p, [F(1)] * 3, h)
+        elif spec.model == "pollutant":
+            u = fr(spec.wind[p[2]])
+            for s in range(ns):
+                left = gets[s]((p[0] - 1, p[1], p[2]))
+                rate[s] += -u * (c[s] - left) / h - P["decay"] * c[s]
+                rate[s] += src.get(p + (s,), F(0))
+            if ns >= 2:
+                rate[0] -= P["kab"] * c[0]
+                rate[1] += P["kab"] * c[0]
+        for s in range(ns):
+            hv = gets[s].held(p)
+            new[s][p] = hv if hv is not None else c[s] + dt * rate[s]
+    return new
+
+
+def to_exact(arr):
+    return {(x, y, z): F(float(arr[z, y, x])) for z in range(N) for y in range(N) for x in range(N)}
+
+
+def to_array(d):
+    out = np.zeros((N, N, N))
+    for (x, y, z), v in d.items():
+        out[z, y, x] = float(v)
+    return out
+
+
+def dyadic_field(rng, lo=-2.0, hi=2.0):
+    return np.round(rng.uniform(lo, hi, (N, N, N)) * 64) / 64
+
+
+CASES = {
+    "diffusion_mirror": lambda: ModelSpec(
+        "diffusion", 1, 1 / 16, 1.0, [[1.0, 2.0, 0.5]], [[(MIRROR, 0.0)] * 6]),
+    "diffusion_periodic_h2": lambda: ModelSpec(
+        "diffusion", 2, 1 / 8, 2.0, [[1.0, 0.5, 0.25], [0.25, 1.0, 0.5]],
+        [[(PERIODIC, 0.0)] * 6, [(PERIODIC, 0.0)] * 6]),
+    "diffusion_ghost_held": lambda: ModelSpec(
+        "diffusion", 2, 1 / 16, 1.0, [[1.0, 1.0, 1.0], [0.5, 0.5, 2.0]],
+        [[(GHOST, 0.25), (MIRROR, 0), (HELD, 1.5), (GHOST, -1.0), (MIRROR, 0), (HELD, 0.75)],
+         [(HELD, 2.0), (HELD, -0.5), (MIRROR, 0), (MIRROR, 0), (GHOST, 3.0), (GHOST, 0.0)]]),
+    "brusselator_mixed": lambda: ModelSpec(
+        "brusselator", 2, 1 / 128, 1.0, [[1.0] * 3, [8.0] * 3],
+        [[(PERIODIC, 0), (PERIODIC, 0), (MIRROR, 0), (MIRROR, 0), (GHOST, 4.5), (GHOST, 1.5)]] * 2,
+        {"a": 4.5, "b": 6.75}),
+    "front_held": lambda: ModelSpec(
+        "front_ch", 3, 1 / 64, 1.0, [[1.0] * 3, [1.0] * 3, [0.25] * 3],
+        [[(MIRROR, 0)] * 4 + [(HELD, 1.0), (MIRROR, 0)], [(MIRROR, 0)] * 6, [(MIRROR, 0)] * 6],
+        {"k": 1.0, "M": 0.1, "kappa": 1.0, "eps": 1.0, "gamma": 1.0}),
+    "pollutant_inflow": lambda: ModelSpec(
+        "pollutant", 4, 1 / 32, 1.0, [[0.5, 0.5, 0.125]] * 4,
+        [[(GHOST, 0.0)] + [(MIRROR, 0)] * 5] * 4, {"decay": 0.01, "kab": 0.02},
+        wind=np.array([0.0, 0.5, 0.75, 1.0]),
+        sources=(np.array([5, 5, 37, 63], np.int64), np.array([1, 1, 0, 3], np.int32),
+                 np.array([10.0, 2.0, 10.0, 4.0]))),
+    "pollutant_periodic_h2": lambda: ModelSpec(
+        "pollutant", 2, 1 / 16, 2.0, [[1.0, 0.5, 0.25]] * 2,
+        [[(PERIODIC, 0), (PERIODIC, 0), (MIRROR, 0), (GHOST, 1.0), (MIRROR, 0), (MIRROR, 0)]] * 2,
+        {"decay": 0.125, "kab": 0.25}, wind=np.array([0.5, 1.0, 2.0, 4.0]),
+        sources=(np.array([0, 63], np.int64), np.array([0, 1], np.int32), np.array([1.0, 3.0]))),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("steps", [1, 3])
+def test_oracle_matches_exact_expansion(oracle, case, steps):
+    spec = CASES[case]()
+    rng = np.random.default_rng(sum(map(ord, case)) + steps)
+    if spec.model == "brusselator":
+        fields = [4.5 + dyadic_field(rng, -0.5, 0.5), 1.5 + dyadic_field(rng, -0.5, 0.5)]
+    else:
+        fields = [dyadic_field(rng) for _ in range(spec.ns)]
+    state = [to_exact(f) for f in fields]
+    for _ in range(steps):
+        state = exact_step(spec, state)
+    got = oracle.run(spec, fields, steps)
+    for s in range(spec.ns):
+        exact = to_array(state[s])
+        scale = max(1.0, np.max(np.abs(exact)))
+        assert np.max(np.abs(got[s] - exact)) <= 1e-14 * scale, (case, s)
