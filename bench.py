@@ -1,0 +1,186 @@
+"""Benchmark: the explicit RD step on one MI355X.
+
+Default workload: the two-species Brusselator on a 256^3 periodic grid (FP32
+fields, dt = 0.01), i.e. one step = one fused 7-point-Laplacian + reaction +
+Euler pass over 16.8 M cells x 2 species.  Prints ONE JSON line with
+Gcell-updates/s, the step kernel's HBM-roofline fraction (timed with HIP
+events on the stream the kernel runs on) and the FP64 CPU oracle timed on a
+bounded sample of the same workload on the host's cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak
+PROFILES = os.path.join(ROOT, "profiles")
+
+# Algorithmic HBM bytes per cell-update: one read and one write of every
+# stored species (FP32 fields: 4 B each way).  The front model's two-pass
+# form additionally writes and reads the FP32 chemical potential (8 B/cell).
+def alg_bytes_per_cell(name: str, storage: str) -> int:
+    ns = {"brusselator256": 2, "diffusion64": 1, "diffusion512": 1, "front384": 3,
+          "pollutant512": 4}[name]
+    es = 4 if storage == "f32" else 2
+    b = 2 * ns * es
+    if name == "front384":
+        b += 8 + es          # mu written (4) and read (4) + C read again by pass 1
+    return b
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1004_0480_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hpp", ".hip")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str, digest: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(PROFILES, "%s_pmc.json" % name)
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_digest") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s: float = 12.0):
+    """The FP64 oracle as it stands, on all host cores, on a bounded sample
+    (whole grid, a few steps) of the same workload."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.run(w.spec, w.fields, 1)
+    one = time.perf_counter() - t0
+    steps = int(max(1, min(20, budget_s // max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.run(w.spec, w.fields, steps)
+    dt = time.perf_counter() - t0
+    return {"value": w.cells * steps / dt / 1e9, "unit": "Gcell-updates/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%s %dx%dx%d, %d FP64 steps (whole grid), OpenMP over z"
+                      % (w.name, w.shape[2], w.shape[1], w.shape[0], steps)}
+
+
+def copy_ceiling(torch, stream, nbytes: int, reps: int = 10):
+    from paper_1004_0480_amd import rd
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    with torch.cuda.stream(stream):
+        rd.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            rd.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, stream)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="brusselator256",
+                    choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--graph-chunk", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("RANK", "0")) != 0:
+        return
+
+    import torch
+    from paper_1004_0480_amd import rd
+    from paper_1004_0480_amd import workloads as W
+
+    w = W.make_workload(args.workload)
+    stream = torch.cuda.Stream()
+    print("bench: %s %s storage=%s steps=%d warmup=%d" % (w.name, w.shape, args.storage,
+                                                          args.steps, args.warmup),
+          file=sys.stderr, flush=True)
+    g = rd.Grid.from_workload(w, storage=args.storage, stream=stream)
+    plan = g.plan() if args.no_autotune else g.autotune(10)
+    chunk = args.graph_chunk if args.graph_chunk >= 2 else 0
+    plan["graph_chunk"] = chunk - (chunk & 1)
+    g.set_plan(**plan)
+    plan = g.plan()
+    print("bench: plan %s" % plan, file=sys.stderr, flush=True)
+
+    g.step(args.warmup)
+    g.sync()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    g.step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / args.steps
+    value = w.cells * args.steps / (ms * 1e-3) / 1e9
+
+    # sanity: the fields stayed finite
+    for s in range(w.spec.ns):
+        g.reduce(s)
+
+    bpc = alg_bytes_per_cell(w.name, args.storage)
+    launches_per_step = 2 if w.name == "front384" else 1
+    # dominant kernel: the (only, or second) step kernel; its average duration
+    # is the event-timed step time (one launch per step for single-pass models)
+    kernel_ms = ms_per_step if launches_per_step == 1 else None
+    achieved = (bpc * w.cells / (ms_per_step * 1e-3) / 1e9) if kernel_ms else None
+    digest = kernel_source_digest()
+    traffic = measured_traffic(w.name, digest)
+    ceiling = copy_ceiling(torch, stream, 2 * 256 * 1024 * 1024)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "kernel_avg_ms": kernel_ms, "alg_bytes_per_cell": bpc,
+            "copy_ceiling_GBs": ceiling,
+            "frac_of_copy_ceiling": (achieved / ceiling) if achieved else None,
+            "source_digest": digest}
+    out = {
+        "metric": "Gcell-updates/s", "value": value, "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
+                   "species": w.spec.ns, "storage": args.storage, "dt": w.spec.dt,
+                   "plan": plan, "wall_s": wall},
+        "roofline": roof,
+    }
+    g.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

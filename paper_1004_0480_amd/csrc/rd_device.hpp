@@ -1,0 +1,805 @@
+// rd_device.hpp -- device code of the MI355X (gfx950) reaction-diffusion stepper.
+//
+// One explicit method-of-lines step (section 2, Eq. (5)):
+//     c_s' = c_s + dt * ( L_s + A_s + R_s(c) + E_s )
+// with L_s the 7-point Laplacian (per-axis coefficients), A_s first-order
+// upwind advection, R_s the reaction at the old time level and E_s point
+// sources.  Boundary values are virtual ghosts resolved while loading
+// (section 4.1 sets them before each step; here they never touch memory).
+//
+// Every kernel variant funnels each cell through the same __device__ cell
+// functions below, written with explicit fmaf and compiled with
+// -ffp-contract=off, so all plans produce bitwise-identical fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rdk {
+
+enum { BC_MIRROR = 0, BC_PERIODIC = 1, BC_GHOST = 2, BC_HELD = 3 };
+
+constexpr int MAXF = 5;          // stencil fields: up to 4 species + mu
+constexpr int SLACK = 1024;      // elements after each buffer: overshoot of the widest tile
+
+struct StepArgs {
+    int nx, ny, nz;
+    int pitch;                    // elements per padded row (multiple of 64)
+    long long plane;              // elements per plane = pitch * ny
+    const void* in[MAXF];         // fields read with the stencil
+    void* out[MAXF];              // fields written
+    float kx[MAXF], ky[MAXF], kz[MAXF];   // K_{f,d} / h^2
+    int bck[MAXF][6];             // boundary kind per field and face
+    float bcv[MAXF][6];           // boundary value per field and face
+    int held[MAXF];               // bit f set: face f of field is BC_HELD
+    int out_held[MAXF];           // held mask applied to output o (its field o)
+    float dt;
+    float p[8];                   // model constants (see the models)
+    const float* wind_h;          // u(z)/h per z plane (pollutant)
+    const int* src_row;           // nz*ny+1 offsets of the row-sorted sources
+    const int* src_x;             // x of each source
+    const int* src_sp;            // species of each source
+    const float* src_rate;        // emission rate (duplicates merged)
+    int tiles_x, tiles_y, chunks_z, cz;   // tiled decomposition
+};
+
+// --------------------------------------------------------------- storage
+
+struct StF32 {
+    using T = float;
+    static __device__ __forceinline__ float up(T v) { return v; }
+    static __device__ __forceinline__ T down(float v) { return v; }
+};
+
+struct StBF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ float up(T v) { return __uint_as_float(uint32_t(v) << 16); }
+    // round to nearest even; NaN stays NaN
+    static __device__ __forceinline__ T down(float f) {
+        uint32_t u = __float_as_uint(f);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return T((u >> 16) | 0x40u);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return T(u >> 16);
+    }
+};
+
+struct StF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ float up(T v) {
+        _Float16 h;
+        __builtin_memcpy(&h, &v, 2);
+        return float(h);
+    }
+    static __device__ __forceinline__ T down(float f) {
+        _Float16 h = _Float16(f);          // v_cvt_f16_f32: round to nearest even
+        T v;
+        __builtin_memcpy(&v, &h, 2);
+        return v;
+    }
+};
+
+// FP64 as a transfer type only (rounded to FP32 first, then to storage).
+struct StF64 {
+    using T = double;
+    static __device__ __forceinline__ float up(T v) { return float(v); }
+};
+
+// N contiguous elements of type T as one naturally aligned access.
+template <typename T, int N> struct alignas(sizeof(T) * N) Vec { T v[N]; };
+
+template <class S, int VX>
+__device__ __forceinline__ void load_vec(const void* base, long long idx, float (&o)[VX]) {
+    using T = typename S::T;
+    const Vec<T, VX> r = *reinterpret_cast<const Vec<T, VX>*>(static_cast<const T*>(base) + idx);
+#pragma unroll
+    for (int i = 0; i < VX; ++i) o[i] = S::up(r.v[i]);
+}
+
+template <class S, int VX>
+__device__ __forceinline__ void store_vec(void* base, long long idx, const float (&o)[VX]) {
+    using T = typename S::T;
+    Vec<T, VX> r;
+#pragma unroll
+    for (int i = 0; i < VX; ++i) r.v[i] = S::down(o[i]);
+    *reinterpret_cast<Vec<T, VX>*>(static_cast<T*>(base) + idx) = r;
+}
+
+template <class S>
+__device__ __forceinline__ float load1(const void* base, long long idx) {
+    return S::up(static_cast<const typename S::T*>(base)[idx]);
+}
+
+// --------------------------------------------------------- cell arithmetic
+
+struct Nb { float c, xm, xp, ym, yp, zm, zp; };
+
+// sum_d K_d (c[+e_d] + c[-e_d] - 2c), K already divided by h^2
+__device__ __forceinline__ float lap7(const Nb& n, float kx, float ky, float kz) {
+    const float c2 = n.c + n.c;
+    const float dx = (n.xm + n.xp) - c2;
+    const float dy = (n.ym + n.yp) - c2;
+    const float dz = (n.zm + n.zp) - c2;
+    return __fmaf_rn(kx, dx, __fmaf_rn(ky, dy, kz * dz));
+}
+
+// Pure diffusion of NS independent species (Table 1, first row).
+template <int NS> struct Diffusion {
+    static constexpr int NF = NS, NO = NS;
+    static constexpr bool SOURCES = false;
+    static __host__ __device__ constexpr bool f32_field(int) { return false; }
+    static __host__ __device__ constexpr bool f32_out(int) { return false; }
+    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[NF], float,
+                                                bool, const float (&)[NO], float (&o)[NO]) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            o[s] = __fmaf_rn(a.dt, lap7(n[s], a.kx[s], a.ky[s], a.kz[s]), n[s].c);
+    }
+};
+
+// Brusselator activator-inhibitor kinetics: p[0]=a, p[1]=b, p[2]=-(b+1).
+struct Brusselator {
+    static constexpr int NF = 2, NO = 2;
+    static constexpr bool SOURCES = false;
+    static __host__ __device__ constexpr bool f32_field(int) { return false; }
+    static __host__ __device__ constexpr bool f32_out(int) { return false; }
+    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[2], float,
+                                                bool, const float (&)[2], float (&o)[2]) {
+        const float u = n[0].c, v = n[1].c;
+        const float uuv = (u * u) * v;
+        const float ru = __fmaf_rn(a.p[2], u, a.p[0] + uuv);   // a - (b+1) u + u^2 v
+        const float rv = __fmaf_rn(a.p[1], u, -uuv);            // b u - u^2 v
+        const float lu = lap7(n[0], a.kx[0], a.ky[0], a.kz[0]);
+        const float lv = lap7(n[1], a.kx[1], a.ky[1], a.kz[1]);
+        o[0] = __fmaf_rn(a.dt, lu + ru, u);
+        o[1] = __fmaf_rn(a.dt, lv + rv, v);
+    }
+};
+
+// Cahn-Hilliard first pass: mu = gamma C^3 - eps C - kappa Lap(C).
+// Field 0 is C (its own faces); output 0 is mu in FP32.
+// p[2]=kappa p[3]=eps p[4]=gamma; kx[0]=ky[0]=kz[0]=1/h^2.
+struct ChemPotential {
+    static constexpr int NF = 1, NO = 1;
+    static constexpr bool SOURCES = false;
+    static __host__ __device__ constexpr bool f32_field(int) { return false; }
+    static __host__ __device__ constexpr bool f32_out(int) { return true; }
+    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[1], float,
+                                                bool, const float (&)[1], float (&o)[1]) {
+        const float c = n[0].c;
+        const float lap = lap7(n[0], a.kx[0], a.ky[0], a.kz[0]);
+        o[0] = __fmaf_rn(-a.p[2], lap, __fmaf_rn(a.p[4] * c, c * c, -(a.p[3] * c)));
+    }
+};
+
+// Front with precipitation: A + B -> C at rate k, C moves by M Lap(mu).
+// Fields 0..2 = A, B, C (storage type), field 3 = mu (FP32, mirror faces).
+// p[0]=k p[1]=M; kx[3]=ky[3]=kz[3]=1/h^2.
+struct FrontCH {
+    static constexpr int NF = 4, NO = 3;
+    static constexpr bool SOURCES = false;
+    static __host__ __device__ constexpr bool f32_field(int f) { return f == 3; }
+    static __host__ __device__ constexpr bool f32_out(int) { return false; }
+    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[4], float,
+                                                bool, const float (&)[3], float (&o)[3]) {
+        const float A = n[0].c, B = n[1].c, C = n[2].c;
+        const float r = (a.p[0] * A) * B;
+        const float la = lap7(n[0], a.kx[0], a.ky[0], a.kz[0]);
+        const float lb = lap7(n[1], a.kx[1], a.ky[1], a.kz[1]);
+        const float lc = lap7(n[2], a.kx[2], a.ky[2], a.kz[2]);
+        const float lmu = lap7(n[3], a.kx[3], a.ky[3], a.kz[3]);
+        o[0] = __fmaf_rn(a.dt, la - r, A);
+        o[1] = __fmaf_rn(a.dt, lb - r, B);
+        o[2] = __fmaf_rn(a.dt, __fmaf_rn(a.p[1], lmu, lc + r), C);
+    }
+};
+
+// Advection-diffusion of NS pollutants: upwind wind along +x (u(z)/h given),
+// first-order decay p[0], transfer p[1] from species 0 to species 1, sources.
+template <int NS> struct Pollutant {
+    static constexpr int NF = NS, NO = NS;
+    static constexpr bool SOURCES = true;
+    static __host__ __device__ constexpr bool f32_field(int) { return false; }
+    static __host__ __device__ constexpr bool f32_out(int) { return false; }
+    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[NF], float uh,
+                                                bool has_e, const float (&e)[NO], float (&o)[NO]) {
+        const float c0 = n[0].c;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const float c = n[s].c;
+            float rate = lap7(n[s], a.kx[s], a.ky[s], a.kz[s]);
+            rate = __fmaf_rn(uh, n[s].xm - c, rate);       // -u (c_i - c_{i-1}) / h
+            rate = __fmaf_rn(-a.p[0], c, rate);             // decay
+            if (NS >= 2 && s == 0) rate = __fmaf_rn(-a.p[1], c0, rate);
+            if (NS >= 2 && s == 1) rate = __fmaf_rn(a.p[1], c0, rate);
+            if (has_e) rate = rate + e[s];
+            o[s] = __fmaf_rn(a.dt, rate, c);
+        }
+    }
+};
+
+// ------------------------------------------------------------ ghost logic
+
+// The value one cell beyond index 0 / n-1 comes from (idx, constant?) by the
+// face rule; an in-range index on a held face reads the held value.
+struct Src { int idx; int cst; float v; };
+
+__device__ __forceinline__ Src resolve_axis(int q, int n, int klo, int khi, float vlo, float vhi) {
+    const bool lo = q < 0, hi = q >= n;
+    const bool fixed_lo = klo == BC_GHOST || klo == BC_HELD;
+    const bool fixed_hi = khi == BC_GHOST || khi == BC_HELD;
+    int idx = q;
+    idx = lo ? (klo == BC_PERIODIC ? n - 1 : 0) : idx;
+    idx = hi ? ((q > n || khi != BC_PERIODIC) ? n - 1 : 0) : idx;   // beyond the ghost: unused
+    bool cst = (lo && fixed_lo) || (hi && q == n && fixed_hi);
+    float v = lo ? vlo : vhi;
+    // a resolved in-range index on a held face reads the held value (lo first)
+    const bool hlo = !cst && idx == 0 && klo == BC_HELD;
+    const bool hhi = !cst && !hlo && idx == n - 1 && khi == BC_HELD;
+    v = hlo ? vlo : (hhi ? vhi : v);
+    cst = cst || hlo || hhi;
+    return Src{idx, cst ? 1 : 0, v};
+}
+
+// Value of field f at in-range (x, y, z) with held layers applied
+// (a cell on several held faces takes the first in x-, x+, y-, y+, z-, z+).
+template <class S>
+__device__ __forceinline__ float cell_value(const StepArgs& a, int f, int x, int y, int z) {
+    const int hm = a.held[f];
+    if (hm) {
+        if ((hm & 1) && x == 0) return a.bcv[f][0];
+        if ((hm & 2) && x == a.nx - 1) return a.bcv[f][1];
+        if ((hm & 4) && y == 0) return a.bcv[f][2];
+        if ((hm & 8) && y == a.ny - 1) return a.bcv[f][3];
+        if ((hm & 16) && z == 0) return a.bcv[f][4];
+        if ((hm & 32) && z == a.nz - 1) return a.bcv[f][5];
+    }
+    return load1<S>(a.in[f], (long long)z * a.plane + (long long)y * a.pitch + x);
+}
+
+// Neighbour of in-range (x,y,z) one step along `axis` in direction `dir`.
+template <class S>
+__device__ __forceinline__ float neighbour(const StepArgs& a, int f, int x, int y, int z,
+                                           int axis, int dir) {
+    int q[3] = {x, y, z};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    const int p = q[axis] + dir;
+    if (p >= 0 && p < n[axis]) {
+        q[axis] = p;
+        return cell_value<S>(a, f, q[0], q[1], q[2]);
+    }
+    const int face = 2 * axis + (dir > 0 ? 1 : 0);
+    const int kind = a.bck[f][face];
+    if (kind == BC_MIRROR) return cell_value<S>(a, f, x, y, z);
+    if (kind == BC_PERIODIC) {
+        q[axis] = dir > 0 ? 0 : n[axis] - 1;
+        return cell_value<S>(a, f, q[0], q[1], q[2]);
+    }
+    return a.bcv[f][face];
+}
+
+// Merged emission rates of the cell at x of a row whose sources are
+// [s0, s1); `any` is false if the cell has none.  Returned by value so the
+// rates stay in registers.
+template <int NO> struct Emission {
+    float e[NO];
+    bool any;
+};
+
+template <int NO>
+__device__ __forceinline__ Emission<NO> cell_sources(const StepArgs& a, int x, int s0, int s1) {
+    Emission<NO> r;
+#pragma unroll
+    for (int s = 0; s < NO; ++s) r.e[s] = 0.f;
+    r.any = false;
+    for (int q = s0; q < s1; ++q) {
+        if (a.src_x[q] == x) {
+            const int sp = a.src_sp[q];
+            const float rate = a.src_rate[q];
+#pragma unroll
+            for (int s = 0; s < NO; ++s) r.e[s] = sp == s ? rate : r.e[s];
+            r.any = true;
+        }
+    }
+    return r;
+}
+
+// Output value of species s at (x, y, z): the held value on a held face, else
+// v.  Takes and returns the value (not a reference) so that the choice stays
+// a register select and the outputs never go through memory.
+__device__ __forceinline__ float held_out(const StepArgs& a, int s, int x, int y, int z, float v) {
+    const int hm = a.out_held[s];
+    if (hm) {
+        if ((hm & 32) && z == a.nz - 1) v = a.bcv[s][5];
+        if ((hm & 16) && z == 0) v = a.bcv[s][4];
+        if ((hm & 8) && y == a.ny - 1) v = a.bcv[s][3];
+        if ((hm & 4) && y == 0) v = a.bcv[s][2];
+        if ((hm & 2) && x == a.nx - 1) v = a.bcv[s][1];
+        if ((hm & 1) && x == 0) v = a.bcv[s][0];
+    }
+    return v;
+}
+
+// ------------------------------------------------------------ direct kernel
+// One thread per cell; all 7 stencil points come through the cache.  The
+// simple baseline the tiled plans are checked against bit for bit.
+
+template <class M, class S>
+__global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict__ pa) {
+    const StepArgs& a = *pa;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    Nb n[M::NF];
+#pragma unroll
+    for (int f = 0; f < M::NF; ++f) {
+        if (M::f32_field(f)) {
+            n[f].c = cell_value<StF32>(a, f, x, y, z);
+            n[f].xm = neighbour<StF32>(a, f, x, y, z, 0, -1);
+            n[f].xp = neighbour<StF32>(a, f, x, y, z, 0, +1);
+            n[f].ym = neighbour<StF32>(a, f, x, y, z, 1, -1);
+            n[f].yp = neighbour<StF32>(a, f, x, y, z, 1, +1);
+            n[f].zm = neighbour<StF32>(a, f, x, y, z, 2, -1);
+            n[f].zp = neighbour<StF32>(a, f, x, y, z, 2, +1);
+        } else {
+            n[f].c = cell_value<S>(a, f, x, y, z);
+            n[f].xm = neighbour<S>(a, f, x, y, z, 0, -1);
+            n[f].xp = neighbour<S>(a, f, x, y, z, 0, +1);
+            n[f].ym = neighbour<S>(a, f, x, y, z, 1, -1);
+            n[f].yp = neighbour<S>(a, f, x, y, z, 1, +1);
+            n[f].zm = neighbour<S>(a, f, x, y, z, 2, -1);
+            n[f].zp = neighbour<S>(a, f, x, y, z, 2, +1);
+        }
+    }
+    Emission<M::NO> em{};
+    if (M::SOURCES) {
+        const int r = z * a.ny + y;
+        em = cell_sources<M::NO>(a, x, a.src_row[r], a.src_row[r + 1]);
+    }
+    const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+    float o[M::NO];
+    M::cell(a, n, uh, em.any, em.e, o);
+    const long long idx = (long long)z * a.plane + (long long)y * a.pitch + x;
+#pragma unroll
+    for (int s = 0; s < M::NO; ++s) {
+        const float v = held_out(a, s, x, y, z, o[s]);
+        if (M::f32_out(s)) static_cast<float*>(a.out[s])[idx] = v;
+        else static_cast<typename S::T*>(a.out[s])[idx] = S::down(v);
+    }
+}
+
+// ------------------------------------------------------------- tiled kernel
+
+// Lane l receives v from lane l-1 (l-1 >= 0) or `fill` (lane 0): DPP wave_shr:1.
+__device__ __forceinline__ float lane_from_left(float v, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v),
+                                                      0x138, 0xF, 0xF, false));
+}
+// Lane l receives v from lane l+1 (l+1 <= 63) or `fill` (lane 63): DPP wave_shl:1.
+__device__ __forceinline__ float lane_from_right(float v, float fill) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v),
+                                                      0x130, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float bcast_lane(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// run of tiles (x fastest, then y, then z chunk) so that tiles sharing halo
+// rows share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    constexpr int X = 8;
+    const int q = n / X, r = n % X, xcd = b % X, i = b / X;
+    return xcd < r ? xcd * (q + 1) + i : r * (q + 1) + (xcd - r) * q + i;
+}
+
+// One row (VX cells per lane) of field f at resolved plane/row, returned by
+// value so that the held-face selects act on registers.
+template <int VX> struct Row { float v[VX]; };
+
+template <class M, class S, int VX>
+__device__ __forceinline__ Row<VX> load_row(const StepArgs& a, int f, Src pz, Src py,
+                                            int xl) {
+    Row<VX> r;
+    if (py.cst || pz.cst) {
+        const float c = py.cst ? py.v : pz.v;
+#pragma unroll
+        for (int i = 0; i < VX; ++i) r.v[i] = c;
+    } else {
+        const long long idx = (long long)pz.idx * a.plane + (long long)py.idx * a.pitch + xl;
+        if (M::f32_field(f)) load_vec<StF32, VX>(a.in[f], idx, r.v);
+        else load_vec<S, VX>(a.in[f], idx, r.v);
+    }
+    const int hm = a.held[f];
+    if (hm & 3) {
+        const float b0 = a.bcv[f][0], b1 = a.bcv[f][1];
+#pragma unroll
+        for (int i = 0; i < VX; ++i) {
+            const int x = xl + i;
+            r.v[i] = ((hm & 1) && x == 0) ? b0 : ((hm & 2) && x == a.nx - 1) ? b1 : r.v[i];
+        }
+    }
+    return r;
+}
+
+// The x-edge value a lane at the tile border needs: lane 0 the cell left of
+// the tile, lane 63 the cell right of the tile (or of the last cell, nx-1).
+template <class M, class S>
+__device__ __forceinline__ float load_edge(const StepArgs& a, int f, Src pz, Src py,
+                                           int lane, int x0, int tx_width) {
+    float e = 0.f;
+    if (lane == 0 || lane == 63) {
+        const int q = lane == 0 ? x0 - 1 : min(x0 + tx_width, a.nx);
+        const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
+        if (py.cst) e = py.v;
+        else if (pz.cst) e = pz.v;
+        else {
+            const long long idx = (long long)pz.idx * a.plane + (long long)py.idx * a.pitch + sx.idx;
+            e = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
+        }
+        if (sx.cst) e = sx.v;
+    }
+    return e;
+}
+
+template <class M, int W, int TX>
+struct TileLds {
+    float row[W > 1 ? 2 : 1][M::NF][W > 1 ? W : 1][2][W > 1 ? TX : 1];
+};
+
+// One tile: columns [x0, x0+TX), rows [y0, y0+RY*W), planes [z0, z1),
+// marching in z with planes z-1, z, z+1 in registers and z+2 in flight.
+template <class M, class S, int VX, int RY, int W>
+__device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W, 64 * VX>& sm) {
+    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, BY = RY * W;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = t % a.tiles_x;
+    const int t2 = t / a.tiles_x;
+    const int ty = t2 % a.tiles_y;
+    const int tz = t2 / a.tiles_y;
+    const int x0 = tx * TX;
+    const int yb = ty * BY;                 // first row of the block
+    const int y0 = yb + w * RY;             // first row of this wave
+    const int z0 = tz * a.cz;
+    const int z1 = min(z0 + a.cz, a.nz);
+    const int xl = x0 + lane * VX;
+
+    float P[NF][3][RY][VX];   // planes z-1, z, z+1
+    float Q[NF][RY][VX];      // plane z+2 (in flight)
+    float H[NF][VX], Hn[NF][VX];      // halo row above (wave 0) / below (wave W-1)
+    float E[NF][RY], En[NF][RY];      // x-edge values per row for plane z / z+1
+
+    auto plane_src = [&](int f, int z) {
+        return resolve_axis(z, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+    };
+    auto row_src = [&](int f, int y) {
+        return resolve_axis(y, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
+    };
+    auto load_plane = [&](float (&dst)[NF][RY][VX], int z) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const Src pz = plane_src(f, z);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const Row<VX> row = load_row<M, S, VX>(a, f, pz, row_src(f, y0 + r), xl);
+#pragma unroll
+                for (int i = 0; i < VX; ++i) dst[f][r][i] = row.v[i];
+            }
+        }
+    };
+    auto load_extras = [&](float (&h)[NF][VX], float (&e)[NF][RY], int z) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const Src pz = plane_src(f, z);
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                e[f][r] = load_edge<M, S>(a, f, pz, row_src(f, y0 + r), lane, x0, TX);
+            if (w == 0 || w == W - 1) {
+                const Row<VX> row = load_row<M, S, VX>(a, f, pz, row_src(f, w == 0 ? yb - 1 : yb + BY), xl);
+#pragma unroll
+                for (int i = 0; i < VX; ++i) h[f][i] = row.v[i];
+            }
+        }
+    };
+    // W == 1: one wave needs both halo rows; keep the second in Hb.
+    float Hb[NF][VX], Hbn[NF][VX];
+    auto load_extras1 = [&](int z, bool next) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const Src pz = plane_src(f, z);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const float e = load_edge<M, S>(a, f, pz, row_src(f, y0 + r), lane, x0, TX);
+                if (next) En[f][r] = e; else E[f][r] = e;
+            }
+            const Row<VX> top = load_row<M, S, VX>(a, f, pz, row_src(f, yb - 1), xl);
+            const Row<VX> bot = load_row<M, S, VX>(a, f, pz, row_src(f, yb + BY), xl);
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                if (next) { Hn[f][i] = top.v[i]; Hbn[f][i] = bot.v[i]; }
+                else { H[f][i] = top.v[i]; Hb[f][i] = bot.v[i]; }
+            }
+        }
+    };
+
+    // prologue
+    {
+        float T0[NF][RY][VX], T1[NF][RY][VX], T2[NF][RY][VX];
+        load_plane(T0, z0 - 1);
+        load_plane(T1, z0);
+        load_plane(T2, z0 + 1);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    P[f][0][r][i] = T0[f][r][i];
+                    P[f][1][r][i] = T1[f][r][i];
+                    P[f][2][r][i] = T2[f][r][i];
+                }
+    }
+    if (W == 1) load_extras1(z0, false); else load_extras(H, E, z0);
+    if (z0 + 2 <= z1) load_plane(Q, z0 + 2);
+    if (z0 + 1 < z1) { if (W == 1) load_extras1(z0 + 1, true); else load_extras(Hn, En, z0 + 1); }
+
+    for (int z = z0; z < z1; ++z) {
+        const int par = (z - z0) & 1;
+        // rows above row 0 and below row RY-1 of this wave
+        float up[NF][VX], dn[NF][VX];
+        if (W > 1) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    sm.row[par][f][w][0][lane * VX + i] = P[f][1][0][i];
+                    sm.row[par][f][w][1][lane * VX + i] = P[f][1][RY - 1][i];
+                }
+            __syncthreads();
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][1][lane * VX + i] : H[f][i];
+                    dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i]
+                                         : H[f][i];
+                }
+        } else {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int i = 0; i < VX; ++i) { up[f][i] = H[f][i]; dn[f][i] = Hb[f][i]; }
+        }
+
+        const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int y = y0 + r;
+            Nb n[NF][VX];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const float L = bcast_lane(E[f][r], 0);
+                const float R = bcast_lane(E[f][r], 63);
+                const float left = lane_from_left(P[f][1][r][VX - 1], L);
+                const float right = lane_from_right(P[f][1][r][0], R);
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    Nb& q = n[f][i];
+                    q.c = P[f][1][r][i];
+                    q.xm = i > 0 ? P[f][1][r][i - 1] : left;
+                    q.xp = i < VX - 1 ? P[f][1][r][i + 1] : right;
+                    if (xl + i == a.nx - 1) q.xp = R;
+                    q.ym = r > 0 ? P[f][1][r - 1][i] : up[f][i];
+                    q.yp = r < RY - 1 ? P[f][1][r + 1][i] : dn[f][i];
+                    q.zm = P[f][0][r][i];
+                    q.zp = P[f][2][r][i];
+                }
+            }
+            int s0 = 0, s1 = 0;
+            if (M::SOURCES && y < a.ny) {
+                s0 = a.src_row[z * a.ny + y];
+                s1 = a.src_row[z * a.ny + y + 1];
+            }
+            float o[NO][VX];
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                Nb ni[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) ni[f] = n[f][i];
+                Emission<NO> em{};
+                if (M::SOURCES && s0 < s1) em = cell_sources<NO>(a, xl + i, s0, s1);
+                float oi[NO];
+                M::cell(a, ni, uh, em.any, em.e, oi);
+#pragma unroll
+                for (int s = 0; s < NO; ++s) o[s][i] = held_out(a, s, xl + i, y, z, oi[s]);
+            }
+            if (y < a.ny && xl < a.nx) {
+                const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
+#pragma unroll
+                for (int s = 0; s < NO; ++s) {
+                    if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
+                    else store_vec<S, VX>(a.out[s], idx, o[s]);
+                }
+            }
+        }
+
+        // rotate the window and issue the next loads
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    P[f][0][r][i] = P[f][1][r][i];
+                    P[f][1][r][i] = P[f][2][r][i];
+                    P[f][2][r][i] = Q[f][r][i];
+                }
+#pragma unroll
+            for (int r = 0; r < RY; ++r) E[f][r] = En[f][r];
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                H[f][i] = Hn[f][i];
+                if (W == 1) Hb[f][i] = Hbn[f][i];
+            }
+        }
+        if (z + 3 <= z1) load_plane(Q, z + 3);
+        if (z + 2 < z1) { if (W == 1) load_extras1(z + 2, true); else load_extras(Hn, En, z + 2); }
+    }
+    if (W > 1) __syncthreads();   // the LDS rows may be reused by the next tile
+}
+
+// Step arguments live in device memory (not the kernel-argument segment) so
+// that boundary values picked by runtime conditions are plain scalar loads.
+template <class M, class S, int VX, int RY, int W>
+__global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restrict__ pa) {
+    __shared__ TileLds<M, W, 64 * VX> sm;
+    tile_step<M, S, VX, RY, W>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
+}
+
+// ------------------------------------------------------------ batched kernel
+// A persistent launch walks (grid, tile) work items of many grids.  Grid g's
+// step arguments for both time-level parities sit in a device table; item
+// ranges are prefix sums over grids.
+
+struct BatchEntry {
+    StepArgs args[2];     // by input parity
+    int model;            // 0 diffusion (1 species), 1 Brusselator
+    int ntiles;
+    int first_item;       // prefix sum of ntiles
+    int parity;           // parity of the current state at chunk start
+    long long steps_left; // at chunk start
+};
+
+struct BatchTable {
+    int ngrids;
+    int total_items;
+    BatchEntry e[1];      // ngrids entries follow
+};
+
+template <class S, int VX, int RY, int W>
+__global__ __launch_bounds__(64 * W) void batched_kernel(const BatchTable* __restrict__ tab, int step) {
+    __shared__ TileLds<Brusselator, W, 64 * VX> smb;
+    __shared__ TileLds<Diffusion<1>, W, 64 * VX> smd;
+    const int total = tab->total_items;
+    const int ng = tab->ngrids;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int lo = 0, hi = ng - 1;                 // last grid with first_item <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tab->e[mid].first_item <= item) lo = mid; else hi = mid - 1;
+        }
+        const BatchEntry& en = tab->e[lo];
+        if (step >= en.steps_left) continue;     // this grid already finished
+        const StepArgs& a = en.args[(en.parity + step) & 1];
+        const int t = item - en.first_item;
+        if (en.model == 1) tile_step<Brusselator, S, VX, RY, W>(a, t, smb);
+        else tile_step<Diffusion<1>, S, VX, RY, W>(a, t, smd);
+    }
+}
+
+// ------------------------------------------------------------- reductions
+
+template <class S>
+__global__ __launch_bounds__(256) void reduce_partial(const void* f, int nx, int ny, int nz,
+                                                      int pitch, long long plane, double* part) {
+    double s = 0.0, q = 0.0;
+    const long long rows = (long long)ny * nz;
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+        const long long base = (row / ny) * plane + (row % ny) * (long long)pitch;
+        for (int x = threadIdx.x; x < nx; x += 256) {
+            const double v = load1<S>(f, base + x);
+            s += v;
+            q += v * v;
+        }
+    }
+    __shared__ double ss[256], sq[256];
+    ss[threadIdx.x] = s;
+    sq[threadIdx.x] = q;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            ss[threadIdx.x] += ss[threadIdx.x + k];
+            sq[threadIdx.x] += sq[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ss[0];
+        part[2 * blockIdx.x + 1] = sq[0];
+    }
+}
+
+#ifdef RD_DEFINE_ENGINE_KERNELS   // non-template kernels: one definition, in the engine
+__global__ __launch_bounds__(256) void reduce_final(const double* part, int n, double h3, double* out) {
+    double s = 0.0, q = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        s += part[2 * i];
+        q += part[2 * i + 1];
+    }
+    __shared__ double ss[256], sq[256];
+    ss[threadIdx.x] = s;
+    sq[threadIdx.x] = q;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) {
+            ss[threadIdx.x] += ss[threadIdx.x + k];
+            sq[threadIdx.x] += sq[threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = ss[0] * h3;
+        out[1] = sq[0] * h3;
+    }
+}
+
+#endif
+
+// ------------------------------------------------------ layout conversion
+
+// dense [nz][ny][nx] of transfer type Src -> padded storage S
+template <class S, class Src>
+__global__ __launch_bounds__(256) void pack_kernel(const void* src, void* dst, int nx, int ny, int nz,
+                                                   int pitch, long long plane) {
+    const long long n = (long long)nx * ny * nz;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const long long x = i % nx, r = i / nx;
+        const long long y = r % ny, z = r / ny;
+        const float v = Src::up(static_cast<const typename Src::T*>(src)[i]);
+        static_cast<typename S::T*>(dst)[z * plane + y * pitch + x] = S::down(v);
+    }
+}
+
+template <class S, typename DstT>
+__global__ __launch_bounds__(256) void unpack_kernel(const void* src, DstT* dst, int nx, int ny, int nz,
+                                                     int pitch, long long plane) {
+    const long long n = (long long)nx * ny * nz;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const long long x = i % nx, r = i / nx;
+        const long long y = r % ny, z = r / ny;
+        dst[i] = DstT(S::up(static_cast<const typename S::T*>(src)[z * plane + y * pitch + x]));
+    }
+}
+
+#ifdef RD_DEFINE_ENGINE_KERNELS
+// ----------------------------------------------------------- copy ceiling
+
+__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
+                                                   float4* __restrict__ dst, long long n4) {
+    const long long stride = (long long)gridDim.x * 256;
+    long long i = blockIdx.x * 256LL + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n4; i += stride) dst[i] = src[i];
+}
+
+#endif
+
+}  // namespace rdk

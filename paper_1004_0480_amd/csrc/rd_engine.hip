@@ -1,0 +1,1120 @@
+// rd_engine.hip -- grids, models, plans, hipGraphs, batches and the C ABI.
+//
+// The host loop of the paper's Table 3 (allocate two arrays per species, load
+// initial values, step with swaps, export, free) behind plain C calls; each
+// step is one fused kernel (two for the Cahn-Hilliard model, section 4.1).
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "rd.h"
+#define RD_DEFINE_ENGINE_KERNELS
+#include "rd_internal.hpp"
+
+using namespace rdk;
+
+// ------------------------------------------------------------------ errors
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define RD_HIP(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(RD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+size_t elem_size(int storage) { return storage == RD_F32 ? 4 : 2; }
+int pitch_of(int64_t nx) { return int((nx + 63) / 64 * 64); }
+size_t field_elems(int64_t nx, int64_t ny, int64_t nz) {
+    return size_t(pitch_of(nx)) * size_t(ny) * size_t(nz) + SLACK;
+}
+bool is_finite(double v) { return std::isfinite(v); }
+
+int pm_of(int model, int ns) {
+    switch (model) {
+    case RD_MODEL_DIFFUSION: return PM_DIFF1 + (ns - 1);
+    case RD_MODEL_BRUSSELATOR: return PM_BRUSS;
+    case RD_MODEL_POLLUTANT: return PM_POLL1 + (ns - 1);
+    default: return -1;
+    }
+}
+
+int num_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        hipDeviceProp_t p;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
+            cus = p.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+}  // namespace
+
+namespace rdk {
+
+int tile_cfg_index(int vx, int ry, int w) {
+    for (int i = 0; i < kNumTileCfgs; ++i)
+        if (kTileCfgs[i].vx == vx && kTileCfgs[i].ry == ry && kTileCfgs[i].w == w) return i;
+    return -1;
+}
+
+hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h, const StepArgs* d,
+                       long long blocks, hipStream_t s) {
+    const bool diff = pm <= PM_DIFF4;
+    const bool react = pm == PM_BRUSS || pm == PM_CHMU || pm == PM_FRONT;
+    switch (storage) {
+    case ST_F32:
+        return diff ? launch_pass_f32_diff(pm, kernel, cfg, h, d, blocks, s)
+             : react ? launch_pass_f32_react(pm, kernel, cfg, h, d, blocks, s)
+                     : launch_pass_f32_poll(pm, kernel, cfg, h, d, blocks, s);
+    case ST_BF16:
+        return diff ? launch_pass_bf16_diff(pm, kernel, cfg, h, d, blocks, s)
+             : react ? launch_pass_bf16_react(pm, kernel, cfg, h, d, blocks, s)
+                     : launch_pass_bf16_poll(pm, kernel, cfg, h, d, blocks, s);
+    case ST_F16:
+        return diff ? launch_pass_f16_diff(pm, kernel, cfg, h, d, blocks, s)
+             : react ? launch_pass_f16_react(pm, kernel, cfg, h, d, blocks, s)
+                     : launch_pass_f16_poll(pm, kernel, cfg, h, d, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batched(int storage, const BatchTable* tab, int step, int blocks, hipStream_t s) {
+    switch (storage) {
+    case ST_F32: return launch_batched_f32(tab, step, blocks, s);
+    case ST_BF16: return launch_batched_bf16(tab, step, blocks, s);
+    case ST_F16: return launch_batched_f16(tab, step, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int batched_blocks_per_cu(int storage) {
+    switch (storage) {
+    case ST_F32: return batched_blocks_per_cu_f32();
+    case ST_BF16: return batched_blocks_per_cu_bf16();
+    default: return batched_blocks_per_cu_f16();
+    }
+}
+
+}  // namespace rdk
+
+// ------------------------------------------------------------------- grids
+
+struct rd_grid {
+    int64_t nx = 0, ny = 0, nz = 0;
+    int ns = 0;
+    double h = 1.0;
+    int storage = RD_F32;
+    hipStream_t stream = nullptr;
+    int pitch = 0;
+    long long plane = 0;
+    size_t elems = 0;
+    void* buf[2][RD_MAX_SPECIES] = {};
+    float* aux = nullptr;              // Cahn-Hilliard mu (FP32)
+    int cur = 0;                       // buffer parity holding the current state
+    bool has_model = false;
+    int model = -1;
+    float* d_wind = nullptr;
+    int* d_src_row = nullptr;
+    int* d_src_x = nullptr;
+    int* d_src_sp = nullptr;
+    float* d_src_rate = nullptr;
+    int npass = 0;
+    int pass_pm[2] = {-1, -1};
+    StepArgs args[2][2];               // [input parity][pass], host copy
+    StepArgs* d_args = nullptr;        // same, in device memory
+    rd_plan plan{};                    // requested plan (kernel 0 = auto)
+    rd_plan eff{};                     // plan in use
+    int cfg = -1;
+    long long blocks[2] = {0, 0};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gchunk = 0;
+    double* d_part = nullptr;
+    double* d_red = nullptr;
+    rd_batch* batch = nullptr;
+};
+
+namespace {
+
+constexpr int kRedBlocks = 1024;
+
+void drop_graphs(rd_grid* g) {
+    for (auto& e : g->gexec)
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
+    g->gchunk = 0;
+}
+
+void free_model_arrays(rd_grid* g) {
+    (void)hipFree(g->d_wind);
+    (void)hipFree(g->d_src_row);
+    (void)hipFree(g->d_src_x);
+    (void)hipFree(g->d_src_sp);
+    (void)hipFree(g->d_src_rate);
+    g->d_wind = nullptr;
+    g->d_src_row = g->d_src_x = g->d_src_sp = nullptr;
+    g->d_src_rate = nullptr;
+}
+
+void fill_bc(StepArgs& a, int f, const rd_model_desc* m, int s) {
+    int held = 0;
+    for (int k = 0; k < 6; ++k) {
+        a.bck[f][k] = m->bc_kind[s][k];
+        a.bcv[f][k] = float(m->bc_value[s][k]);
+        if (m->bc_kind[s][k] == RD_BC_HELD) held |= 1 << k;
+    }
+    a.held[f] = held;
+}
+
+void fill_mirror(StepArgs& a, int f) {
+    for (int k = 0; k < 6; ++k) {
+        a.bck[f][k] = BC_MIRROR;
+        a.bcv[f][k] = 0.f;
+    }
+    a.held[f] = 0;
+}
+
+// Decomposition of a tiled plan: fills tiles_* / cz, returns workgroups.
+long long set_tiling(StepArgs& a, const rd_plan& p) {
+    const int tx = 64 * p.vx, by = p.ry * p.waves;
+    const int cz = (p.cz <= 0 || p.cz > a.nz) ? a.nz : p.cz;
+    a.tiles_x = (a.nx + tx - 1) / tx;
+    a.tiles_y = (a.ny + by - 1) / by;
+    a.cz = cz;
+    a.chunks_z = (a.nz + cz - 1) / cz;
+    return (long long)a.tiles_x * a.tiles_y * a.chunks_z;
+}
+
+// Default plan: the tiled kernel with the compiled tile shape that wastes the
+// fewest lanes along x (ties: wider tiles, then 2 rows per wave), and a z
+// chunk giving about 8 workgroups per CU.
+rd_plan heuristic_plan(const rd_grid* g, int pm) {
+    rd_plan best{};
+    best.kernel = RD_KERNEL_DIRECT;
+    double best_score = 1e30;
+    const unsigned mask = cfg_mask(g->storage, pm);
+    for (int i = 0; i < kNumTileCfgs; ++i) {
+        if (!((mask >> i) & 1u)) continue;
+        const TileCfg c = kTileCfgs[i];
+        const int tx = 64 * c.vx, by = c.ry * c.w;
+        const double wx = double((g->nx + tx - 1) / tx * tx) / double(g->nx);
+        const double wy = double((g->ny + by - 1) / by * by) / double(g->ny);
+        double score = wx * wy;
+        score -= 1e-3 * c.vx;                  // wider rows first
+        score += 1e-4 * std::abs(c.ry - 2);    // then two rows per wave
+        score += c.w == 1 ? 1e-2 : 0.0;        // multi-wave tiles share halo rows in LDS
+        if (score < best_score) {
+            best_score = score;
+            best.kernel = RD_KERNEL_TILED;
+            best.vx = c.vx;
+            best.ry = c.ry;
+            best.waves = c.w;
+        }
+    }
+    if (best.kernel == RD_KERNEL_TILED) {
+        const long long xy = ((g->nx + 64 * best.vx - 1) / (64 * best.vx)) *
+                             ((g->ny + best.ry * best.waves - 1) / (best.ry * best.waves));
+        const long long target = 8LL * num_cus();
+        long long chunks = std::max(1LL, (target + xy - 1) / xy);
+        int cz = int((g->nz + chunks - 1) / chunks);
+        cz = std::max(cz, 8);
+        best.cz = cz >= g->nz ? 0 : cz;
+    }
+    best.graph_chunk = 0;
+    return best;
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int64_t, int64_t, int64_t, int, int, int>, rd_plan> g_tune_cache;
+
+int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
+    if (p.graph_chunk != 0 && (p.graph_chunk < 2 || (p.graph_chunk & 1)))
+        return fail(RD_EINVAL, "graph_chunk must be 0 or an even number >= 2");
+    if (p.kernel == RD_KERNEL_DIRECT) {
+        if (g->nz > 65535 || (g->ny + 3) / 4 > 65535)
+            return fail(RD_EINVAL, "grid too large for the direct kernel's launch shape");
+        *cfg_out = -1;
+        return RD_OK;
+    }
+    if (p.kernel != RD_KERNEL_TILED) return fail(RD_EINVAL, "unknown kernel kind");
+    const int cfg = tile_cfg_index(p.vx, p.ry, p.waves);
+    if (cfg < 0) return fail(RD_EINVAL, "tile shape not available");
+    for (int k = 0; k < g->npass; ++k)
+        if (!((cfg_mask(g->storage, g->pass_pm[k]) >> cfg) & 1u))
+            return fail(RD_EINVAL, "tile shape not compiled for this model and storage");
+    if (p.cz < 0) return fail(RD_EINVAL, "cz must be >= 0");
+    *cfg_out = cfg;
+    return RD_OK;
+}
+
+// Resolve the plan in use, fill tiling into the argument copies, upload them.
+int apply_plan(rd_grid* g) {
+    rd_plan p = g->plan;
+    if (p.kernel == RD_KERNEL_AUTO) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find({g->nx, g->ny, g->nz, g->ns, g->model, g->storage});
+        const int gc = p.graph_chunk;
+        p = it != g_tune_cache.end() ? it->second : heuristic_plan(g, g->pass_pm[g->npass - 1]);
+        p.graph_chunk = gc;
+    }
+    int cfg = -1;
+    int rc = check_plan(g, p, &cfg);
+    if (rc) return rc;
+    for (int par = 0; par < 2; ++par)
+        for (int k = 0; k < g->npass; ++k) {
+            StepArgs& a = g->args[par][k];
+            if (p.kernel == RD_KERNEL_TILED) g->blocks[k] = set_tiling(a, p);
+            else g->blocks[k] = 0;
+        }
+    for (int k = 0; k < g->npass; ++k)
+        if (p.kernel == RD_KERNEL_TILED && g->blocks[k] > 0x7fffffffLL)
+            return fail(RD_EINVAL, "too many workgroups for this plan");
+    g->eff = p;
+    g->cfg = cfg;
+    drop_graphs(g);
+    RD_HIP(hipMemcpy(g->d_args, g->args, sizeof(g->args), hipMemcpyHostToDevice));
+    return RD_OK;
+}
+
+int launch_one_step(rd_grid* g, int parity) {
+    for (int k = 0; k < g->npass; ++k) {
+        const hipError_t e = launch_pass(g->storage, g->pass_pm[k], g->eff.kernel, g->cfg,
+                                         g->args[parity][k], g->d_args + parity * 2 + k,
+                                         g->blocks[k], g->stream);
+        if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return RD_OK;
+}
+
+int build_graph(rd_grid* g, int parity, int chunk, hipGraphExec_t* out) {
+    RD_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    int rc = RD_OK;
+    for (int i = 0; i < chunk && rc == RD_OK; ++i) rc = launch_one_step(g, (parity + i) & 1);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(g->stream, &graph);
+    if (rc != RD_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(RD_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(RD_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    return RD_OK;
+}
+
+int step_grid(rd_grid* g, int64_t n) {
+    const int chunk = g->eff.graph_chunk;
+    if (chunk >= 2 && g->stream != nullptr && n >= chunk) {
+        if (g->gchunk != chunk) {
+            drop_graphs(g);
+            for (int par = 0; par < 2; ++par) {
+                const int rc = build_graph(g, par, chunk, &g->gexec[par]);
+                if (rc) {
+                    drop_graphs(g);
+                    return rc;
+                }
+            }
+            g->gchunk = chunk;
+        }
+        while (n >= chunk) {
+            RD_HIP(hipGraphLaunch(g->gexec[g->cur], g->stream));   // chunk is even: parity unchanged
+            n -= chunk;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const int rc = launch_one_step(g, g->cur);
+        if (rc) return rc;
+        g->cur ^= 1;
+    }
+    return RD_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- validation
+
+extern "C" size_t rd_grid_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t nspecies,
+                                int32_t storage_dtype, int32_t with_aux) {
+    if (nx < 1 || ny < 1 || nz < 1 || nspecies < 1 || nspecies > RD_MAX_SPECIES) return 0;
+    if (storage_dtype != RD_F32 && storage_dtype != RD_BF16 && storage_dtype != RD_F16) return 0;
+    const size_t e = field_elems(nx, ny, nz);
+    size_t b = 2 * size_t(nspecies) * e * elem_size(storage_dtype);
+    if (with_aux) b += e * sizeof(float);
+    b += 4 * sizeof(StepArgs) + 2 * kRedBlocks * sizeof(double) + 2 * sizeof(double);
+    return b;
+}
+
+extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns, double h,
+                                 const rd_model_desc* m) {
+    if (!m) return fail(RD_EINVAL, "model descriptor is NULL");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(RD_EINVAL, "grid extents must be >= 1");
+    if (!(h > 0.0) || !is_finite(h)) return fail(RD_EINVAL, "h must be a positive finite number");
+    if (m->nspecies != ns) return fail(RD_EINVAL, "model nspecies differs from the grid's");
+    switch (m->model) {
+    case RD_MODEL_DIFFUSION:
+    case RD_MODEL_POLLUTANT:
+        if (ns < 1 || ns > RD_MAX_SPECIES) return fail(RD_EINVAL, "nspecies must be 1..4");
+        break;
+    case RD_MODEL_BRUSSELATOR:
+        if (ns != 2) return fail(RD_EINVAL, "the Brusselator has 2 species");
+        break;
+    case RD_MODEL_FRONT_CH:
+        if (ns != 3) return fail(RD_EINVAL, "the front model has 3 species");
+        break;
+    default: return fail(RD_EINVAL, "unknown model");
+    }
+    if (!(m->dt > 0.0) || !is_finite(m->dt)) return fail(RD_EINVAL, "dt must be a positive finite number");
+    for (double p : m->param)
+        if (!is_finite(p)) return fail(RD_EINVAL, "model parameters must be finite");
+    for (int s = 0; s < ns; ++s) {
+        for (int d = 0; d < 3; ++d)
+            if (!(m->diff[s][d] >= 0.0) || !is_finite(m->diff[s][d]))
+                return fail(RD_EINVAL, "diffusion coefficients must be finite and >= 0");
+        for (int f = 0; f < 6; ++f) {
+            if (m->bc_kind[s][f] < RD_BC_MIRROR || m->bc_kind[s][f] > RD_BC_HELD)
+                return fail(RD_EINVAL, "unknown boundary kind");
+            if (!is_finite(m->bc_value[s][f])) return fail(RD_EINVAL, "boundary values must be finite");
+        }
+        for (int a = 0; a < 3; ++a)
+            if ((m->bc_kind[s][2 * a] == RD_BC_PERIODIC) != (m->bc_kind[s][2 * a + 1] == RD_BC_PERIODIC))
+                return fail(RD_EINVAL, "a periodic axis needs periodic on both faces");
+    }
+    double umax = 0.0;
+    if (m->model == RD_MODEL_POLLUTANT) {
+        if (!m->wind || m->nwind != nz) return fail(RD_EINVAL, "pollutant model needs nz wind values");
+        for (int64_t k = 0; k < nz; ++k) {
+            if (!(m->wind[k] >= 0.0) || !is_finite(m->wind[k]))
+                return fail(RD_EINVAL, "wind speeds must be finite and >= 0 (upwind along +x)");
+            umax = std::max(umax, m->wind[k]);
+        }
+        if (m->nsrc < 0 || (m->nsrc > 0 && (!m->src_cell || !m->src_species || !m->src_rate)))
+            return fail(RD_EINVAL, "bad source arrays");
+        const int64_t N = nx * ny * nz;
+        for (int64_t q = 0; q < m->nsrc; ++q) {
+            if (m->src_cell[q] < 0 || m->src_cell[q] >= N) return fail(RD_EINVAL, "source cell out of range");
+            if (m->src_species[q] < 0 || m->src_species[q] >= ns)
+                return fail(RD_EINVAL, "source species out of range");
+            if (!is_finite(m->src_rate[q])) return fail(RD_EINVAL, "source rates must be finite");
+        }
+        if (m->param[0] < 0.0 || m->param[1] < 0.0) return fail(RD_EINVAL, "decay and k_AB must be >= 0");
+    } else if (m->nsrc != 0) {
+        return fail(RD_EINVAL, "point sources need the pollutant model");
+    }
+    // Explicit stability (monotone bound of the 7-point stencil + upwind).
+    const double h2 = h * h;
+    for (int s = 0; s < ns; ++s) {
+        const double k = 2.0 * (m->diff[s][0] + m->diff[s][1] + m->diff[s][2]) / h2 + umax / h;
+        if (m->dt * k > 1.0 + 1e-12)
+            return fail(RD_EUNSTABLE, "dt exceeds the explicit bound dt*(2*sum(K)/h^2 + umax/h) <= 1");
+    }
+    if (m->model == RD_MODEL_FRONT_CH) {
+        const double M = m->param[1], kappa = m->param[2], eps = m->param[3];
+        if (M < 0.0 || kappa < 0.0) return fail(RD_EINVAL, "M and kappa must be >= 0");
+        const double lam = 12.0 / h2;
+        if (m->dt * M * (kappa * lam * lam + std::fabs(eps) * lam) > 1.0 + 1e-12)
+            return fail(RD_EUNSTABLE, "dt exceeds the Cahn-Hilliard bound dt*M*(kappa*(12/h^2)^2 + |eps|*12/h^2) <= 1");
+    }
+    return RD_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" const char* rd_last_error(void) { return g_err.c_str(); }
+extern "C" int rd_abi_version(void) { return RD_ABI_VERSION; }
+
+extern "C" int rd_create_grid(int64_t nx, int64_t ny, int64_t nz, int32_t nspecies, double h,
+                              int32_t storage_dtype, void* hip_stream, rd_grid** out) {
+    if (!out) return fail(RD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(RD_EINVAL, "grid extents must be >= 1");
+    if (nx > (1 << 24) || ny > (1 << 24) || nz > (1 << 24)) return fail(RD_EINVAL, "grid extent too large");
+    if ((__int128)pitch_of(nx) * ny * nz > (__int128)1 << 40) return fail(RD_EINVAL, "grid too large");
+    if (nspecies < 1 || nspecies > RD_MAX_SPECIES) return fail(RD_EINVAL, "nspecies must be 1..4");
+    if (!(h > 0.0) || !is_finite(h)) return fail(RD_EINVAL, "h must be a positive finite number");
+    if (storage_dtype != RD_F32 && storage_dtype != RD_BF16 && storage_dtype != RD_F16)
+        return fail(RD_EINVAL, "storage dtype must be RD_F32, RD_BF16 or RD_F16");
+    rd_grid* g = new rd_grid();
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->ns = nspecies;
+    g->h = h;
+    g->storage = storage_dtype;
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    g->pitch = pitch_of(nx);
+    g->plane = (long long)g->pitch * ny;
+    g->elems = field_elems(nx, ny, nz);
+    const size_t bytes = g->elems * elem_size(storage_dtype);
+    auto cleanup = [&](int code, const std::string& msg) {
+        rd_destroy_grid(g);
+        return fail(code, msg);
+    };
+    for (int p = 0; p < 2; ++p)
+        for (int s = 0; s < nspecies; ++s) {
+            const hipError_t e = hipMalloc(&g->buf[p][s], bytes);
+            if (e != hipSuccess) {
+                g->buf[p][s] = nullptr;
+                return cleanup(e == hipErrorOutOfMemory ? RD_ENOMEM : RD_EDEVICE,
+                               std::string("hipMalloc: ") + hipGetErrorString(e));
+            }
+            if (hipMemsetAsync(g->buf[p][s], 0, bytes, g->stream) != hipSuccess)
+                return cleanup(RD_EDEVICE, "hipMemsetAsync failed");
+        }
+    if (hipMalloc(&g->d_args, sizeof(g->args)) != hipSuccess ||
+        hipMalloc(&g->d_part, 2 * kRedBlocks * sizeof(double)) != hipSuccess ||
+        hipMalloc(&g->d_red, 2 * sizeof(double)) != hipSuccess)
+        return cleanup(RD_ENOMEM, "hipMalloc of grid work buffers failed");
+    if (hipStreamSynchronize(g->stream) != hipSuccess) return cleanup(RD_EDEVICE, "stream sync failed");
+    std::memset(g->args, 0, sizeof(g->args));
+    *out = g;
+    return RD_OK;
+}
+
+extern "C" int rd_destroy_grid(rd_grid* g) {
+    if (!g) return fail(RD_EINVAL, "grid is NULL");
+    if (g->batch) rd_batch_remove(g->batch, g);
+    (void)hipStreamSynchronize(g->stream);
+    drop_graphs(g);
+    for (auto& row : g->buf)
+        for (auto& b : row) (void)hipFree(b);
+    (void)hipFree(g->aux);
+    (void)hipFree(g->d_args);
+    (void)hipFree(g->d_part);
+    (void)hipFree(g->d_red);
+    free_model_arrays(g);
+    delete g;
+    return RD_OK;
+}
+
+extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
+    if (!g) return fail(RD_EINVAL, "grid is NULL");
+    if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
+    int rc = rd_validate_model(g->nx, g->ny, g->nz, g->ns, g->h, m);
+    if (rc) return rc;
+    RD_HIP(hipStreamSynchronize(g->stream));
+    drop_graphs(g);
+    free_model_arrays(g);
+    g->has_model = false;
+    const double ih2 = 1.0 / (g->h * g->h);
+    const int ns = g->ns;
+
+    // Pollutant wind and sources (sorted by row, duplicates merged in FP64).
+    if (m->model == RD_MODEL_POLLUTANT) {
+        std::vector<float> wh(g->nz);
+        for (int64_t k = 0; k < g->nz; ++k) wh[k] = float(m->wind[k] / g->h);
+        std::map<std::tuple<int64_t, int64_t, int>, double> merged;   // (row, x, species)
+        for (int64_t q = 0; q < m->nsrc; ++q) {
+            const int64_t c = m->src_cell[q];
+            merged[{c / g->nx, c % g->nx, m->src_species[q]}] += m->src_rate[q];
+        }
+        const int64_t rows = g->ny * g->nz;
+        std::vector<int> row_start(rows + 1, 0), xs, sps;
+        std::vector<float> rates;
+        for (auto& kv : merged) row_start[std::get<0>(kv.first) + 1]++;
+        for (int64_t r = 0; r < rows; ++r) row_start[r + 1] += row_start[r];
+        for (auto& kv : merged) {
+            xs.push_back(int(std::get<1>(kv.first)));
+            sps.push_back(std::get<2>(kv.first));
+            rates.push_back(float(kv.second));
+        }
+        const size_t n = std::max<size_t>(xs.size(), 1);
+        xs.resize(n, -1);
+        sps.resize(n, 0);
+        rates.resize(n, 0.f);
+        RD_HIP(hipMalloc(&g->d_wind, wh.size() * sizeof(float)));
+        RD_HIP(hipMalloc(&g->d_src_row, row_start.size() * sizeof(int)));
+        RD_HIP(hipMalloc(&g->d_src_x, n * sizeof(int)));
+        RD_HIP(hipMalloc(&g->d_src_sp, n * sizeof(int)));
+        RD_HIP(hipMalloc(&g->d_src_rate, n * sizeof(float)));
+        RD_HIP(hipMemcpy(g->d_wind, wh.data(), wh.size() * sizeof(float), hipMemcpyHostToDevice));
+        RD_HIP(hipMemcpy(g->d_src_row, row_start.data(), row_start.size() * sizeof(int), hipMemcpyHostToDevice));
+        RD_HIP(hipMemcpy(g->d_src_x, xs.data(), n * sizeof(int), hipMemcpyHostToDevice));
+        RD_HIP(hipMemcpy(g->d_src_sp, sps.data(), n * sizeof(int), hipMemcpyHostToDevice));
+        RD_HIP(hipMemcpy(g->d_src_rate, rates.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    }
+    if (m->model == RD_MODEL_FRONT_CH && !g->aux) {
+        RD_HIP(hipMalloc(&g->aux, g->elems * sizeof(float)));
+        RD_HIP(hipMemset(g->aux, 0, g->elems * sizeof(float)));
+    }
+
+    for (int par = 0; par < 2; ++par) {
+        for (int k = 0; k < 2; ++k) {
+            StepArgs& a = g->args[par][k];
+            std::memset(&a, 0, sizeof(a));
+            a.nx = int(g->nx);
+            a.ny = int(g->ny);
+            a.nz = int(g->nz);
+            a.pitch = g->pitch;
+            a.plane = g->plane;
+            a.dt = float(m->dt);
+            a.wind_h = g->d_wind;
+            a.src_row = g->d_src_row;
+            a.src_x = g->d_src_x;
+            a.src_sp = g->d_src_sp;
+            a.src_rate = g->d_src_rate;
+        }
+        if (m->model == RD_MODEL_FRONT_CH) {
+            // pass 0: mu of C with C's faces; pass 1: update A, B, C.
+            StepArgs& a0 = g->args[par][0];
+            a0.in[0] = g->buf[par][2];
+            a0.out[0] = g->aux;
+            a0.kx[0] = a0.ky[0] = a0.kz[0] = float(ih2);
+            fill_bc(a0, 0, m, 2);
+            a0.out_held[0] = 0;
+            StepArgs& a1 = g->args[par][1];
+            for (int s = 0; s < 3; ++s) {
+                a1.in[s] = g->buf[par][s];
+                a1.out[s] = g->buf[par ^ 1][s];
+                a1.kx[s] = float(m->diff[s][0] * ih2);
+                a1.ky[s] = float(m->diff[s][1] * ih2);
+                a1.kz[s] = float(m->diff[s][2] * ih2);
+                fill_bc(a1, s, m, s);
+                a1.out_held[s] = a1.held[s];
+            }
+            a1.in[3] = g->aux;
+            a1.kx[3] = a1.ky[3] = a1.kz[3] = float(ih2);
+            fill_mirror(a1, 3);
+            for (int k = 0; k < 2; ++k) {
+                StepArgs& a = g->args[par][k];
+                a.p[0] = float(m->param[0]);   // k
+                a.p[1] = float(m->param[1]);   // M
+                a.p[2] = float(m->param[2]);   // kappa
+                a.p[3] = float(m->param[3]);   // eps
+                a.p[4] = float(m->param[4]);   // gamma
+            }
+        } else {
+            StepArgs& a = g->args[par][0];
+            for (int s = 0; s < ns; ++s) {
+                a.in[s] = g->buf[par][s];
+                a.out[s] = g->buf[par ^ 1][s];
+                a.kx[s] = float(m->diff[s][0] * ih2);
+                a.ky[s] = float(m->diff[s][1] * ih2);
+                a.kz[s] = float(m->diff[s][2] * ih2);
+                fill_bc(a, s, m, s);
+                a.out_held[s] = a.held[s];
+            }
+            if (m->model == RD_MODEL_BRUSSELATOR) {
+                a.p[0] = float(m->param[0]);
+                a.p[1] = float(m->param[1]);
+                a.p[2] = float(-(m->param[1] + 1.0));
+            } else if (m->model == RD_MODEL_POLLUTANT) {
+                a.p[0] = float(m->param[0]);
+                a.p[1] = float(m->param[1]);
+            }
+        }
+    }
+    g->model = m->model;
+    if (m->model == RD_MODEL_FRONT_CH) {
+        g->npass = 2;
+        g->pass_pm[0] = PM_CHMU;
+        g->pass_pm[1] = PM_FRONT;
+    } else {
+        g->npass = 1;
+        g->pass_pm[0] = pm_of(m->model, ns);
+    }
+    rc = apply_plan(g);
+    if (rc) return rc;
+    g->has_model = true;
+    return RD_OK;
+}
+
+extern "C" int rd_set_plan(rd_grid* g, const rd_plan* p) {
+    if (!g || !p) return fail(RD_EINVAL, "NULL argument");
+    if (!g->has_model) return fail(RD_ESTATE, "set a model before a plan");
+    if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
+    RD_HIP(hipStreamSynchronize(g->stream));
+    const rd_plan old = g->plan;
+    g->plan = *p;
+    const int rc = apply_plan(g);
+    if (rc) {
+        g->plan = old;
+        (void)apply_plan(g);
+        return rc;
+    }
+    return RD_OK;
+}
+
+extern "C" int rd_get_plan(const rd_grid* g, rd_plan* p) {
+    if (!g || !p) return fail(RD_EINVAL, "NULL argument");
+    if (!g->has_model) return fail(RD_ESTATE, "no model set");
+    *p = g->eff;
+    return RD_OK;
+}
+
+extern "C" int rd_write_field(rd_grid* g, int32_t species, const void* src, int32_t src_dtype,
+                              int32_t src_on_device) {
+    if (!g || !src) return fail(RD_EINVAL, "NULL argument");
+    if (species < 0 || species >= g->ns) return fail(RD_EINVAL, "species out of range");
+    if (src_dtype < RD_F32 || src_dtype > RD_F64) return fail(RD_EINVAL, "unknown source dtype");
+    if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
+    const size_t n = size_t(g->nx) * g->ny * g->nz;
+    const size_t es = src_dtype == RD_F64 ? 8 : src_dtype == RD_F32 ? 4 : 2;
+    RD_HIP(hipStreamSynchronize(g->stream));
+    const void* dsrc = src;
+    void* stage = nullptr;
+    if (!src_on_device) {
+        RD_HIP(hipMalloc(&stage, n * es));
+        const hipError_t e = hipMemcpy(stage, src, n * es, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(stage);
+            return fail(RD_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+        }
+        dsrc = stage;
+    }
+    void* dst = g->buf[g->cur][species];
+    const unsigned blocks = unsigned(std::min<size_t>((n + 255) / 256, 8192));
+    const int nx = int(g->nx), ny = int(g->ny), nz = int(g->nz);
+#define RD_PACK(S, SRC) hipLaunchKernelGGL((pack_kernel<S, SRC>), dim3(blocks), dim3(256), 0, g->stream, \
+                                           dsrc, dst, nx, ny, nz, g->pitch, g->plane)
+#define RD_PACK_SRC(S)                                   \
+    switch (src_dtype) {                                 \
+    case RD_F32: RD_PACK(S, StF32); break;               \
+    case RD_F64: RD_PACK(S, StF64); break;               \
+    case RD_BF16: RD_PACK(S, StBF16); break;             \
+    default: RD_PACK(S, StF16); break;                   \
+    }
+    switch (g->storage) {
+    case RD_F32: RD_PACK_SRC(StF32) break;
+    case RD_BF16: RD_PACK_SRC(StBF16) break;
+    default: RD_PACK_SRC(StF16) break;
+    }
+#undef RD_PACK_SRC
+#undef RD_PACK
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipStreamSynchronize(g->stream);
+    (void)hipFree(stage);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(RD_EDEVICE, std::string("pack: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    return RD_OK;
+}
+
+extern "C" int rd_read_field(rd_grid* g, int32_t species, void* dst, int32_t dst_dtype,
+                             int32_t dst_on_device) {
+    if (!g || !dst) return fail(RD_EINVAL, "NULL argument");
+    if (species < 0 || species >= g->ns) return fail(RD_EINVAL, "species out of range");
+    if (dst_dtype != RD_F32 && dst_dtype != RD_F64) return fail(RD_EINVAL, "dst dtype must be RD_F32 or RD_F64");
+    if (dst_on_device && dst_dtype != RD_F32) return fail(RD_EINVAL, "device destinations take RD_F32");
+    const size_t n = size_t(g->nx) * g->ny * g->nz;
+    const size_t es = dst_dtype == RD_F64 ? 8 : 4;
+    RD_HIP(hipStreamSynchronize(g->stream));
+    void* ddst = dst;
+    void* stage = nullptr;
+    if (!dst_on_device) {
+        RD_HIP(hipMalloc(&stage, n * es));
+        ddst = stage;
+    }
+    const void* src = g->buf[g->cur][species];
+    const unsigned blocks = unsigned(std::min<size_t>((n + 255) / 256, 8192));
+    const int nx = int(g->nx), ny = int(g->ny), nz = int(g->nz);
+#define RD_UNPACK(S)                                                                                    \
+    if (dst_dtype == RD_F64)                                                                            \
+        hipLaunchKernelGGL((unpack_kernel<S, double>), dim3(blocks), dim3(256), 0, g->stream, src,       \
+                           static_cast<double*>(ddst), nx, ny, nz, g->pitch, g->plane);                 \
+    else                                                                                                \
+        hipLaunchKernelGGL((unpack_kernel<S, float>), dim3(blocks), dim3(256), 0, g->stream, src,        \
+                           static_cast<float*>(ddst), nx, ny, nz, g->pitch, g->plane);
+    switch (g->storage) {
+    case RD_F32: RD_UNPACK(StF32) break;
+    case RD_BF16: RD_UNPACK(StBF16) break;
+    default: RD_UNPACK(StF16) break;
+    }
+#undef RD_UNPACK
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess && stage) e = hipMemcpy(dst, stage, n * es, hipMemcpyDeviceToHost);
+    (void)hipFree(stage);
+    if (e != hipSuccess) return fail(RD_EDEVICE, std::string("read_field: ") + hipGetErrorString(e));
+    return RD_OK;
+}
+
+extern "C" int rd_step(rd_grid* g, int64_t n) {
+    if (!g) return fail(RD_EINVAL, "grid is NULL");
+    if (n < 0) return fail(RD_EINVAL, "n must be >= 0");
+    if (!g->has_model) return fail(RD_ESTATE, "rd_set_model must come before rd_step");
+    if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
+    return step_grid(g, n);
+}
+
+extern "C" int rd_sync(rd_grid* g) {
+    if (!g) return fail(RD_EINVAL, "grid is NULL");
+    RD_HIP(hipStreamSynchronize(g->stream));
+    return RD_OK;
+}
+
+extern "C" int rd_reduce(rd_grid* g, int32_t species, double out[2]) {
+    if (!g || !out) return fail(RD_EINVAL, "NULL argument");
+    if (species < 0 || species >= g->ns) return fail(RD_EINVAL, "species out of range");
+    const long long rows = g->ny * g->nz;
+    const int blocks = int(std::min<long long>(rows, kRedBlocks));
+    const void* f = g->buf[g->cur][species];
+    const int nx = int(g->nx), ny = int(g->ny), nz = int(g->nz);
+    switch (g->storage) {
+    case RD_F32:
+        hipLaunchKernelGGL((reduce_partial<StF32>), dim3(blocks), dim3(256), 0, g->stream, f, nx, ny, nz,
+                           g->pitch, g->plane, g->d_part);
+        break;
+    case RD_BF16:
+        hipLaunchKernelGGL((reduce_partial<StBF16>), dim3(blocks), dim3(256), 0, g->stream, f, nx, ny, nz,
+                           g->pitch, g->plane, g->d_part);
+        break;
+    default:
+        hipLaunchKernelGGL((reduce_partial<StF16>), dim3(blocks), dim3(256), 0, g->stream, f, nx, ny, nz,
+                           g->pitch, g->plane, g->d_part);
+        break;
+    }
+    const double h3 = g->h * g->h * g->h;
+    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(256), 0, g->stream, g->d_part, blocks, h3, g->d_red);
+    RD_HIP(hipGetLastError());
+    RD_HIP(hipMemcpyAsync(out, g->d_red, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    RD_HIP(hipStreamSynchronize(g->stream));
+    if (!is_finite(out[0]) || !is_finite(out[1])) return fail(RD_ENONFINITE, "field holds NaN or Inf");
+    return RD_OK;
+}
+
+extern "C" int rd_chemical_potential(rd_grid* g, float* dst_host) {
+    if (!g || !dst_host) return fail(RD_EINVAL, "NULL argument");
+    if (!g->has_model || g->model != RD_MODEL_FRONT_CH) return fail(RD_ESTATE, "needs the front model");
+    const hipError_t e = launch_pass(g->storage, PM_CHMU, g->eff.kernel, g->cfg, g->args[g->cur][0],
+                                     g->d_args + g->cur * 2, g->blocks[0], g->stream);
+    if (e != hipSuccess) return fail(RD_EDEVICE, std::string("mu pass: ") + hipGetErrorString(e));
+    const size_t n = size_t(g->nx) * g->ny * g->nz;
+    float* stage = nullptr;
+    RD_HIP(hipMalloc(&stage, n * sizeof(float)));
+    const unsigned blocks = unsigned(std::min<size_t>((n + 255) / 256, 8192));
+    hipLaunchKernelGGL((unpack_kernel<StF32, float>), dim3(blocks), dim3(256), 0, g->stream, g->aux, stage,
+                       int(g->nx), int(g->ny), int(g->nz), g->pitch, g->plane);
+    hipError_t e2 = hipGetLastError();
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(g->stream);
+    if (e2 == hipSuccess) e2 = hipMemcpy(dst_host, stage, n * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(stage);
+    if (e2 != hipSuccess) return fail(RD_EDEVICE, std::string("mu read: ") + hipGetErrorString(e2));
+    return RD_OK;
+}
+
+// --------------------------------------------------------------- autotune
+
+extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
+    if (!g || !best) return fail(RD_EINVAL, "NULL argument");
+    if (trial_steps < 1) return fail(RD_EINVAL, "trial_steps must be >= 1");
+    if (!g->has_model) return fail(RD_ESTATE, "set a model first");
+    if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
+    RD_HIP(hipStreamSynchronize(g->stream));
+    // Save the state (all species at the current parity).
+    const size_t bytes = g->elems * elem_size(g->storage);
+    std::vector<void*> snap(g->ns, nullptr);
+    auto release = [&]() {
+        for (void* p : snap) (void)hipFree(p);
+    };
+    for (int s = 0; s < g->ns; ++s) {
+        if (hipMalloc(&snap[s], bytes) != hipSuccess) {
+            release();
+            return fail(RD_ENOMEM, "no memory for the autotune snapshot");
+        }
+        if (hipMemcpy(snap[s], g->buf[g->cur][s], bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
+            release();
+            return fail(RD_EDEVICE, "snapshot copy failed");
+        }
+    }
+    const int cur0 = g->cur;
+    const rd_plan user = g->plan;
+
+    std::vector<rd_plan> cands;
+    rd_plan d{};
+    d.kernel = RD_KERNEL_DIRECT;
+    cands.push_back(d);
+    unsigned mask = ~0u;
+    for (int k = 0; k < g->npass; ++k) mask &= cfg_mask(g->storage, g->pass_pm[k]);
+    for (int i = 0; i < kNumTileCfgs; ++i) {
+        if (!((mask >> i) & 1u)) continue;
+        const TileCfg c = kTileCfgs[i];
+        std::vector<int> czs = {0, 128, 64, 32, 16, 8};
+        for (int cz : czs) {
+            if (cz != 0 && cz >= g->nz) continue;
+            rd_plan p{};
+            p.kernel = RD_KERNEL_TILED;
+            p.vx = c.vx;
+            p.ry = c.ry;
+            p.waves = c.w;
+            p.cz = cz;
+            cands.push_back(p);
+        }
+    }
+    hipEvent_t e0, e1;
+    RD_HIP(hipEventCreate(&e0));
+    RD_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    rd_plan best_plan = heuristic_plan(g, g->pass_pm[g->npass - 1]);
+    int rc = RD_OK;
+    for (const rd_plan& p : cands) {
+        g->plan = p;
+        if (apply_plan(g) != RD_OK) continue;
+        if ((rc = step_grid(g, 1)) != RD_OK) break;
+        if (hipEventRecord(e0, g->stream) != hipSuccess) { rc = fail(RD_EDEVICE, "event"); break; }
+        if ((rc = step_grid(g, trial_steps)) != RD_OK) break;
+        if (hipEventRecord(e1, g->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(RD_EDEVICE, "event sync failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_plan = p;
+        }
+        // restore the state for the next candidate
+        for (int s = 0; s < g->ns; ++s)
+            if (hipMemcpy(g->buf[cur0][s], snap[s], bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
+                rc = fail(RD_EDEVICE, "restore failed");
+                break;
+            }
+        g->cur = cur0;
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int s = 0; s < g->ns && rc == RD_OK; ++s)
+        if (hipMemcpy(g->buf[cur0][s], snap[s], bytes, hipMemcpyDeviceToDevice) != hipSuccess)
+            rc = fail(RD_EDEVICE, "restore failed");
+    g->cur = cur0;
+    release();
+    if (rc == RD_OK) {
+        best_plan.graph_chunk = 0;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[{g->nx, g->ny, g->nz, g->ns, g->model, g->storage}] = best_plan;
+    }
+    g->plan = user;
+    const int rc2 = apply_plan(g);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    *best = best_plan;
+    best->graph_chunk = user.graph_chunk;
+    return RD_OK;
+}
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+struct Member {
+    rd_grid* g;
+    int64_t steps_left;
+    size_t bytes;
+};
+}  // namespace
+
+struct rd_batch {
+    int max_grids = 0;
+    size_t budget = 0;
+    int storage = RD_F32;
+    hipStream_t stream = nullptr;
+    std::vector<Member> members;
+    size_t bytes = 0;
+    BatchTable* d_tab = nullptr;
+    char* h_tab = nullptr;         // pinned staging of the table
+    size_t tab_bytes = 0;
+    hipEvent_t tab_done = nullptr;
+    bool tab_pending = false;
+    std::map<int64_t, hipGraphExec_t> graphs;   // by chunk
+    int blocks = 0;
+};
+
+namespace {
+size_t table_bytes(int n) { return offsetof(BatchTable, e) + size_t(std::max(n, 1)) * sizeof(BatchEntry); }
+}
+
+extern "C" int rd_batch_create(int32_t max_grids, size_t hbm_budget_bytes, int32_t storage_dtype,
+                               void* hip_stream, rd_batch** out) {
+    if (!out) return fail(RD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_grids < 1 || max_grids > 65536) return fail(RD_EINVAL, "max_grids must be 1..65536");
+    if (storage_dtype != RD_F32 && storage_dtype != RD_BF16 && storage_dtype != RD_F16)
+        return fail(RD_EINVAL, "bad storage dtype");
+    rd_batch* b = new rd_batch();
+    b->max_grids = max_grids;
+    b->budget = hbm_budget_bytes;
+    b->storage = storage_dtype;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->tab_bytes = table_bytes(max_grids);
+    if (hipMalloc(&b->d_tab, b->tab_bytes) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_tab), b->tab_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->tab_done, hipEventDisableTiming) != hipSuccess) {
+        rd_batch_destroy(b);
+        return fail(RD_ENOMEM, "batch table allocation failed");
+    }
+    b->blocks = batched_blocks_per_cu(storage_dtype) * num_cus();
+    *out = b;
+    return RD_OK;
+}
+
+extern "C" int rd_batch_destroy(rd_batch* b) {
+    if (!b) return fail(RD_EINVAL, "batch is NULL");
+    (void)hipStreamSynchronize(b->stream);
+    for (auto& m : b->members) m.g->batch = nullptr;
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    (void)hipFree(b->d_tab);
+    if (b->h_tab) (void)hipHostFree(b->h_tab);
+    if (b->tab_done) (void)hipEventDestroy(b->tab_done);
+    delete b;
+    return RD_OK;
+}
+
+extern "C" int rd_batch_add(rd_batch* b, rd_grid* g, int64_t steps) {
+    if (!b || !g) return fail(RD_EINVAL, "NULL argument");
+    if (steps < 0) return fail(RD_EINVAL, "steps must be >= 0");
+    if (g->batch) return fail(RD_ESTATE, "grid already in a batch");
+    if (!g->has_model) return fail(RD_ESTATE, "grid has no model");
+    if (!(g->model == RD_MODEL_BRUSSELATOR || (g->model == RD_MODEL_DIFFUSION && g->ns == 1)))
+        return fail(RD_EINVAL, "batches take 1-species diffusion or Brusselator grids");
+    if (g->storage != b->storage) return fail(RD_EINVAL, "grid storage differs from the batch's");
+    if (g->stream != b->stream) return fail(RD_EINVAL, "grid and batch must use the same stream");
+    if (int(b->members.size()) >= b->max_grids) return fail(RD_EINVAL, "batch is full");
+    const size_t gb = rd_grid_bytes(g->nx, g->ny, g->nz, g->ns, g->storage, 0);
+    if (b->bytes + gb > b->budget) return fail(RD_ENOMEM, "grid would exceed the batch's HBM budget");
+    RD_HIP(hipStreamSynchronize(g->stream));
+    b->members.push_back({g, steps, gb});
+    b->bytes += gb;
+    g->batch = b;
+    return RD_OK;
+}
+
+extern "C" int rd_batch_remove(rd_batch* b, rd_grid* g) {
+    if (!b || !g) return fail(RD_EINVAL, "NULL argument");
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->members[i].g == g) {
+            RD_HIP(hipStreamSynchronize(b->stream));
+            b->bytes -= b->members[i].bytes;
+            b->members.erase(b->members.begin() + i);
+            g->batch = nullptr;
+            return RD_OK;
+        }
+    return fail(RD_EINVAL, "grid is not in this batch");
+}
+
+extern "C" int rd_batch_info(const rd_batch* b, int32_t* n_members, size_t* bytes_in_use,
+                             int64_t* steps_left_total) {
+    if (!b) return fail(RD_EINVAL, "batch is NULL");
+    int64_t tot = 0;
+    for (auto& m : b->members) tot += m.steps_left;
+    if (n_members) *n_members = int32_t(b->members.size());
+    if (bytes_in_use) *bytes_in_use = b->bytes;
+    if (steps_left_total) *steps_left_total = tot;
+    return RD_OK;
+}
+
+extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int32_t* n_finished) {
+    if (!b || !finished || !n_finished) return fail(RD_EINVAL, "NULL argument");
+    if (chunk < 1 || chunk > 100000) return fail(RD_EINVAL, "chunk must be 1..100000");
+    *n_finished = 0;
+    if (b->members.empty()) return RD_OK;
+    if (b->tab_pending) {
+        RD_HIP(hipEventSynchronize(b->tab_done));
+        b->tab_pending = false;
+    }
+    // Work list: every member's tiles, with its arguments for both parities.
+    BatchTable* t = reinterpret_cast<BatchTable*>(b->h_tab);
+    std::memset(b->h_tab, 0, table_bytes(int(b->members.size())));
+    t->ngrids = int(b->members.size());
+    long long items = 0;
+    rd_plan tile{};
+    tile.kernel = RD_KERNEL_TILED;
+    tile.vx = kBatchTile.vx;
+    tile.ry = kBatchTile.ry;
+    tile.waves = kBatchTile.w;
+    int64_t max_steps = 0;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        const Member& m = b->members[i];
+        BatchEntry& e = t->e[i];
+        tile.cz = int(std::min<int64_t>(m.g->nz, 32));
+        for (int par = 0; par < 2; ++par) {
+            e.args[par] = m.g->args[par][0];
+            e.ntiles = int(set_tiling(e.args[par], tile));
+        }
+        e.model = m.g->model == RD_MODEL_BRUSSELATOR ? 1 : 0;
+        e.first_item = int(items);
+        e.parity = m.g->cur;
+        e.steps_left = m.steps_left;
+        items += e.ntiles;
+        max_steps = std::max(max_steps, m.steps_left);
+    }
+    if (items > 0x7fffffffLL) return fail(RD_EINVAL, "batch work list too long");
+    t->total_items = int(items);
+    RD_HIP(hipMemcpyAsync(b->d_tab, b->h_tab, table_bytes(t->ngrids), hipMemcpyHostToDevice, b->stream));
+    RD_HIP(hipEventRecord(b->tab_done, b->stream));
+    b->tab_pending = true;
+    const int64_t run = std::min(chunk, max_steps);
+    if (b->stream != nullptr) {
+        auto it = b->graphs.find(run);
+        if (it == b->graphs.end()) {
+            RD_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t le = hipSuccess;
+            for (int64_t i = 0; i < run && le == hipSuccess; ++i)
+                le = launch_batched(b->storage, b->d_tab, int(i), b->blocks, b->stream);
+            hipGraph_t graph = nullptr;
+            const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
+            if (le != hipSuccess || ce != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(RD_EDEVICE, std::string("batch capture: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+            }
+            hipGraphExec_t ex = nullptr;
+            const hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(RD_EDEVICE, std::string("batch instantiate: ") + hipGetErrorString(ie));
+            it = b->graphs.emplace(run, ex).first;
+        }
+        RD_HIP(hipGraphLaunch(it->second, b->stream));
+    } else {
+        for (int64_t i = 0; i < run; ++i) {
+            const hipError_t le = launch_batched(b->storage, b->d_tab, int(i), b->blocks, b->stream);
+            if (le != hipSuccess) return fail(RD_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
+        }
+    }
+    // Book-keeping: parity and steps left per member; finished ones leave.
+    std::vector<Member> keep;
+    for (auto& m : b->members) {
+        const int64_t done = std::min(run, m.steps_left);
+        m.g->cur ^= int(done & 1);
+        m.steps_left -= done;
+        if (m.steps_left == 0) {
+            finished[(*n_finished)++] = m.g;
+            m.g->batch = nullptr;
+            b->bytes -= m.bytes;
+        } else {
+            keep.push_back(m);
+        }
+    }
+    b->members.swap(keep);
+    return RD_OK;
+}
+
+// -------------------------------------------------------------- measurement
+
+extern "C" int rd_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream) {
+    if (!dst || !src) return fail(RD_EINVAL, "NULL argument");
+    if (bytes == 0 || (bytes & 15)) return fail(RD_EINVAL, "bytes must be a positive multiple of 16");
+    const long long n4 = (long long)(bytes / 16);
+    const long long want = (n4 + 1023) / 1024;
+    const unsigned blocks = unsigned(std::max<long long>(1, std::min<long long>(want, 8LL * num_cus() * 4)));
+    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                       static_cast<const float4*>(src), static_cast<float4*>(dst), n4);
+    RD_HIP(hipGetLastError());
+    return RD_OK;
+}

@@ -1,0 +1,111 @@
+// rd_launch_impl.hpp -- kernel instantiation and dispatch for one storage type
+// and one group of models.  Included by rd_launch_<storage>_<group>.hip with
+//   RD_STORAGE      the storage struct (rdk::StF32, ...)
+//   RD_STORAGE_ID   its rdk::Storage value
+//   RD_GROUP_DIFF / RD_GROUP_REACT / RD_GROUP_POLL   which models to build
+//   RD_FN(name)     the group's function-name suffixing
+//   RD_WITH_BATCH   also build the batched kernel (once per storage)
+#pragma once
+
+#include "rd_internal.hpp"
+
+namespace rdk {
+namespace {
+
+using S = RD_STORAGE;
+constexpr int kStorage = RD_STORAGE_ID;
+
+template <class M> struct PmOf;
+template <> struct PmOf<Diffusion<1>> { static constexpr int v = PM_DIFF1; };
+template <> struct PmOf<Diffusion<2>> { static constexpr int v = PM_DIFF2; };
+template <> struct PmOf<Diffusion<3>> { static constexpr int v = PM_DIFF3; };
+template <> struct PmOf<Diffusion<4>> { static constexpr int v = PM_DIFF4; };
+template <> struct PmOf<Brusselator> { static constexpr int v = PM_BRUSS; };
+template <> struct PmOf<ChemPotential> { static constexpr int v = PM_CHMU; };
+template <> struct PmOf<FrontCH> { static constexpr int v = PM_FRONT; };
+template <> struct PmOf<Pollutant<1>> { static constexpr int v = PM_POLL1; };
+template <> struct PmOf<Pollutant<2>> { static constexpr int v = PM_POLL2; };
+template <> struct PmOf<Pollutant<3>> { static constexpr int v = PM_POLL3; };
+template <> struct PmOf<Pollutant<4>> { static constexpr int v = PM_POLL4; };
+
+template <class M>
+hipError_t run_direct(const StepArgs& h, const StepArgs* d, hipStream_t s) {
+    dim3 grid((h.nx + 63) / 64, (h.ny + 3) / 4, h.nz);
+    hipLaunchKernelGGL((direct_kernel<M, S>), grid, dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+template <class M, int I>
+hipError_t run_cfg(const StepArgs* d, long long blocks, hipStream_t s) {
+    if constexpr (((cfg_mask(kStorage, PmOf<M>::v) >> I) & 1u) != 0u) {
+        constexpr TileCfg c = kTileCfgs[I];
+        hipLaunchKernelGGL((tiled_kernel<M, S, c.vx, c.ry, c.w>), dim3((unsigned)blocks),
+                           dim3(64 * c.w), 0, s, d);
+        return hipGetLastError();
+    } else {
+        return hipErrorNotSupported;
+    }
+}
+
+template <class M>
+hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, long long blocks,
+                     hipStream_t s) {
+    if (kernel == 1) return run_direct<M>(h, d, s);
+    static_assert(kNumTileCfgs == 8, "dispatch below lists every tile shape");
+    switch (cfg) {
+    case 0: return run_cfg<M, 0>(d, blocks, s);
+    case 1: return run_cfg<M, 1>(d, blocks, s);
+    case 2: return run_cfg<M, 2>(d, blocks, s);
+    case 3: return run_cfg<M, 3>(d, blocks, s);
+    case 4: return run_cfg<M, 4>(d, blocks, s);
+    case 5: return run_cfg<M, 5>(d, blocks, s);
+    case 6: return run_cfg<M, 6>(d, blocks, s);
+    case 7: return run_cfg<M, 7>(d, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, const StepArgs* d,
+                              long long blocks, hipStream_t s) {
+    switch (pm) {
+#ifdef RD_GROUP_DIFF
+    case PM_DIFF1: return run_model<Diffusion<1>>(kernel, cfg, h, d, blocks, s);
+    case PM_DIFF2: return run_model<Diffusion<2>>(kernel, cfg, h, d, blocks, s);
+    case PM_DIFF3: return run_model<Diffusion<3>>(kernel, cfg, h, d, blocks, s);
+    case PM_DIFF4: return run_model<Diffusion<4>>(kernel, cfg, h, d, blocks, s);
+#endif
+#ifdef RD_GROUP_REACT
+    case PM_BRUSS: return run_model<Brusselator>(kernel, cfg, h, d, blocks, s);
+    case PM_CHMU: return run_model<ChemPotential>(kernel, cfg, h, d, blocks, s);
+    case PM_FRONT: return run_model<FrontCH>(kernel, cfg, h, d, blocks, s);
+#endif
+#ifdef RD_GROUP_POLL
+    case PM_POLL1: return run_model<Pollutant<1>>(kernel, cfg, h, d, blocks, s);
+    case PM_POLL2: return run_model<Pollutant<2>>(kernel, cfg, h, d, blocks, s);
+    case PM_POLL3: return run_model<Pollutant<3>>(kernel, cfg, h, d, blocks, s);
+    case PM_POLL4: return run_model<Pollutant<4>>(kernel, cfg, h, d, blocks, s);
+#endif
+    default: return hipErrorNotSupported;
+    }
+}
+
+#ifdef RD_WITH_BATCH
+#define RD_BATCH_KERNEL batched_kernel<S, kBatchTile.vx, kBatchTile.ry, kBatchTile.w>
+hipError_t RD_BATCH_FN(launch_batched)(const BatchTable* tab, int step, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchTile.w), 0, s, tab, step);
+    return hipGetLastError();
+}
+
+int RD_BATCH_FN(batched_blocks_per_cu)() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&RD_BATCH_KERNEL),
+                                                     64 * kBatchTile.w, 0) != hipSuccess)
+        return 1;
+    return n > 0 ? n : 1;
+}
+#undef RD_BATCH_KERNEL
+#endif
+
+}  // namespace rdk

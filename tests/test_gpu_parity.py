@@ -1,0 +1,411 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+FP32 fields must match the oracle to relative L2 <= 1e-5 per species after
+the stated steps; every kernel plan must give bitwise-identical fields; BF16
+and FP16 storage must lie within one unit in the last place of the oracle's
+step rounded to the storage type.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1004_0480_amd import rd
+from paper_1004_0480_amd import workloads as W
+from paper_1004_0480_amd.workloads import GHOST, HELD, MIRROR, PERIODIC, ModelSpec
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5          # FP32 rel-L2 bound per species against the FP64 oracle
+
+TILE_SHAPES = [(4, 4, 4), (4, 2, 4), (4, 1, 4), (2, 4, 4), (2, 2, 4), (2, 1, 4), (1, 4, 4), (4, 4, 1)]
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_run(w, steps, storage="f32", plan=None, fields=None):
+    g = rd.Grid(w.shape, w.spec.ns, w.spec.h, storage)
+    g.set_model(w.spec)
+    if plan:
+        g.set_plan(**plan)
+    for s, f in enumerate(fields if fields is not None else w.fields):
+        g.write(s, f)
+    g.step(steps)
+    out = g.read_all()
+    used = g.plan()
+    g.close()
+    return out, used
+
+
+def compiled_plans(w, storage="f32", czs=(0, 8)):
+    """Every tiled plan the library accepts for this model, plus direct."""
+    plans = [dict(kernel="direct")]
+    g = rd.Grid(w.shape, w.spec.ns, w.spec.h, storage)
+    g.set_model(w.spec)
+    for vx, ry, wv in TILE_SHAPES:
+        for cz in czs:
+            p = dict(kernel="tiled", vx=vx, ry=ry, waves=wv, cz=cz)
+            try:
+                g.set_plan(**p)
+            except rd.RDError:
+                continue
+            plans.append(p)
+    g.close()
+    return plans
+
+
+def check_parity(w, steps, tol=TOL, storage="f32", plan=None, label=""):
+    got, used = gpu_run(w, steps, storage, plan)
+    ref = oracle.run(w.spec, w.fields, steps)
+    for s in range(w.spec.ns):
+        e = rel_l2(got[s], ref[s])
+        m = float(np.max(np.abs(got[s] - ref[s])))
+        print("%s %s species %d: rel-L2 %.3e max-abs %.3e plan %s" % (label or w.name, w.shape, s, e, m, used))
+        assert e <= tol, (label, s, e)
+    return got, ref
+
+
+# ------------------------------------------------------------ workloads
+
+@pytest.mark.parametrize("plan", [None, dict(kernel="direct")])
+def test_diffusion64_full_run(plan):
+    """64^3 no-flux diffusion, 100 steps: the whole configured run."""
+    w = W.make_workload("diffusion64")
+    check_parity(w, w.steps, plan=plan)
+
+
+def test_quadratic_field_bitwise_on_interior():
+    """Integer quadratic, dyadic coefficients: FP32 is exact, so the GPU and
+    the oracle agree bit for bit on interior cells (across several tiles)."""
+    shape = (11, 37, 300)
+    k, j, i = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    c0 = (3 * i**2 - 2 * j**2 + 5 * k**2 + 4 * i - 7 * j + 2 * k + 11).astype(float)
+    spec = ModelSpec("diffusion", 1, 0.0625, 1.0, [[2.0, 3.0, 0.5]], W.uniform_bc(1, MIRROR))
+    w = W.Workload("quadratic", shape, spec, [c0], 1, 0)
+    ref = oracle.run(spec, [c0], 1)[0]
+    inner = (slice(1, -1),) * 3
+    for plan in compiled_plans(w, czs=(0, 4)):
+        got, _ = gpu_run(w, 1, plan=plan)
+        assert np.array_equal(got[0][inner], ref[inner]), plan
+
+
+def test_brusselator_ragged_parity():
+    w = W.make_workload("brusselator256", shape=(23, 37, 70))
+    check_parity(w, 50)
+
+
+def test_brusselator_long_run():
+    """2000 steps (the configured length) on a 64^3 periodic grid."""
+    w = W.make_workload("brusselator256", shape=(64, 64, 64))
+    check_parity(w, 2000)
+
+
+def test_brusselator_full_size_default_plan():
+    """256^3 in the plan the benchmark uses (autotuned), 10 steps."""
+    w = W.make_workload("brusselator256")
+    g = rd.Grid.from_workload(w)
+    g.autotune(5)
+    g.step(10)
+    got = g.read_all()
+    plan = g.plan()
+    g.close()
+    ref = oracle.run(w.spec, w.fields, 10)
+    for s in range(2):
+        e = rel_l2(got[s], ref[s])
+        print("brusselator256 full size species %d rel-L2 %.3e plan %s" % (s, e, plan))
+        assert e <= TOL
+
+
+def test_front_parity():
+    w = W.make_workload("front384", shape=(48, 36, 40))
+    check_parity(w, 200)
+
+
+def test_front_chemical_potential_pass():
+    """The first Laplacian pass alone, from an FP32-exact state."""
+    w = W.make_workload("front384", shape=(20, 24, 70))
+    rng = np.random.default_rng(4)
+    fields = [f.astype(np.float32).astype(np.float64) for f in w.fields]
+    fields[2] = rng.uniform(-1.2, 1.2, w.shape).astype(np.float32).astype(np.float64)
+    g = rd.Grid(w.shape, 3, 1.0)
+    g.set_model(w.spec)
+    for s in range(3):
+        g.write(s, fields[s])
+    mu = g.chemical_potential().astype(np.float64)
+    g.close()
+    ref = oracle.chemical_potential(w.spec, fields)
+    assert np.max(np.abs(mu - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_front_conserves_b_plus_c_on_gpu():
+    """sum(B + C) is invariant (B, C no-flux; A+B->C moves mass between them);
+    the GPU's FP64 reductions see only FP32 rounding drift."""
+    w = W.make_workload("front384", shape=(40, 32, 48))
+    g = rd.Grid.from_workload(w)
+    m0 = g.reduce(1)[0] + g.reduce(2)[0]
+    g.step(500)
+    m1 = g.reduce(1)[0] + g.reduce(2)[0]
+    g.close()
+    drift = abs(m1 - m0) / abs(m0)
+    print("front sum(B+C) relative drift after 500 FP32 steps: %.3e" % drift)
+    assert drift < 1e-5
+
+
+def test_pollutant_parity():
+    w = W.make_workload("pollutant512", shape=(24, 40, 96))
+    check_parity(w, 300)
+
+
+def test_pollutant_ragged_multi_tile():
+    w = W.make_workload("pollutant512", shape=(17, 21, 300))
+    check_parity(w, 60)
+
+
+# --------------------------------------------------------- plans agree
+
+@pytest.mark.parametrize("name,shape,steps", [
+    ("diffusion64", (19, 27, 130), 7),
+    ("brusselator256", (13, 22, 200), 6),
+    ("front384", (14, 18, 150), 5),
+    ("pollutant512", (12, 19, 140), 6),
+])
+def test_every_plan_bitwise_identical(name, shape, steps):
+    w = W.make_workload(name, shape=shape)
+    base = None
+    for plan in compiled_plans(w, czs=(0, 5)):
+        got, _ = gpu_run(w, steps, plan=plan)
+        if base is None:
+            base = got
+            continue
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], base[s]), (name, plan, s)
+
+
+# ---------------------------------------------------- storage precisions
+
+def round_bf16(x):
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def round_f16(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float16).astype(np.float64)
+
+
+def ulp(x, storage):
+    a = np.abs(x)
+    if storage == "bf16":
+        e = np.floor(np.log2(np.maximum(a, 1e-30)))
+        return 2.0 ** (e - 7)
+    return np.spacing(np.maximum(a, 6.1e-5).astype(np.float16)).astype(np.float64)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("name,shape", [("brusselator256", (9, 14, 80)),
+                                        ("front384", (10, 12, 70)),
+                                        ("diffusion64", (16, 16, 130))])
+def test_reduced_storage_single_step_within_one_ulp(storage, name, shape):
+    w = W.make_workload(name, shape=shape)
+    rnd = round_bf16 if storage == "bf16" else round_f16
+    start = [rnd(f) for f in w.fields]
+    got, _ = gpu_run(w, 1, storage=storage, fields=start)
+    ref = oracle.run(w.spec, start, 1)
+    for s in range(w.spec.ns):
+        expect = rnd(ref[s])
+        assert np.all(np.abs(got[s] - expect) <= ulp(expect, storage) * 1.0001), (storage, name, s)
+
+
+def test_bf16_front_error_reported():
+    """BF16 storage error against FP64 is reported (not a target)."""
+    w = W.make_workload("front384", shape=(32, 24, 40))
+    steps = 200
+    got, _ = gpu_run(w, steps, storage="bf16")
+    ref = oracle.run(w.spec, w.fields, steps)
+    for s in range(3):
+        e = rel_l2(got[s], ref[s])
+        print("front bf16 storage, %d steps, species %d: rel-L2 %.3e max-abs %.3e"
+              % (steps, s, e, np.max(np.abs(got[s] - ref[s]))))
+        assert np.all(np.isfinite(got[s])) and e < 1.0
+
+
+# ------------------------------------------------------------ reductions
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_fp64_reduction_matches_oracle(storage):
+    w = W.make_workload("brusselator256", shape=(30, 41, 77))
+    g = rd.Grid.from_workload(w, storage=storage)
+    g.step(3)
+    for s in range(2):
+        f = g.read(s)
+        m, e = g.reduce(s)
+        mo, eo = oracle.reduce(f, 1.0)
+        assert abs(m - mo) <= 1e-12 * abs(mo) and abs(e - eo) <= 1e-12 * abs(eo)
+    g.close()
+
+
+def test_nonfinite_field_detected():
+    w = W.make_workload("diffusion64", shape=(8, 8, 8))
+    f = w.fields[0].copy()
+    f[3, 4, 5] = np.nan
+    g = rd.Grid(w.shape, 1)
+    g.set_model(w.spec)
+    g.write(0, f)
+    with pytest.raises(rd.RDError) as ei:
+        g.reduce(0)
+    assert ei.value.code == rd.ENONFINITE
+    g.close()
+
+
+# ------------------------------------------------------ host-side paths
+
+def test_checkpoint_round_trip_is_bitwise():
+    w = W.make_workload("brusselator256", shape=(16, 20, 90))
+    a, _ = gpu_run(w, 30)
+    g = rd.Grid.from_workload(w)
+    g.step(13)
+    saved = g.read_all()
+    g.close()
+    g2 = rd.Grid(w.shape, 2)
+    g2.set_model(w.spec)
+    for s in range(2):
+        g2.write(s, saved[s])
+    g2.step(17)
+    b = g2.read_all()
+    g2.close()
+    for s in range(2):
+        assert np.array_equal(a[s], b[s])
+
+
+def test_graph_replay_matches_eager():
+    import torch
+    stream = torch.cuda.Stream()
+    w = W.make_workload("front384", shape=(20, 24, 64))
+    eager, _ = gpu_run(w, 37)
+    g = rd.Grid(w.shape, 3, 1.0, "f32", stream=stream)
+    g.set_model(w.spec)
+    g.set_plan(graph_chunk=6)
+    for s, f in enumerate(w.fields):
+        g.write(s, f)
+    g.step(20)
+    g.step(17)
+    got = g.read_all()
+    g.close()
+    for s in range(3):
+        assert np.array_equal(got[s], eager[s])
+
+
+def test_autotune_keeps_state_and_plans_agree():
+    w = W.make_workload("diffusion64", shape=(40, 48, 200))
+    g = rd.Grid.from_workload(w)
+    before = g.read(0)
+    plan = g.autotune(3)
+    assert np.array_equal(g.read(0), before)
+    g.set_plan(**plan)
+    g.step(9)
+    got = g.read(0)
+    g.close()
+    ref, _ = gpu_run(w, 9, plan=dict(kernel="direct"))
+    assert np.array_equal(got, ref[0])
+
+
+def test_copy_probe_copies():
+    import torch
+    src = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    rd.copy_probe(dst.data_ptr(), src.data_ptr(), src.numel() * 4)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+
+
+# --------------------------------------------------------------- edges
+
+def bc_spec(ns, faces, K=(1.0, 0.5, 0.25), dt=0.1):
+    return ModelSpec("diffusion", ns, dt, 1.0, [list(K)] * ns, [list(faces)] * ns)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 7), (5, 1, 1), (1, 6, 1), (3, 2, 65), (2, 70, 3)])
+def test_degenerate_shapes(shape):
+    rng = np.random.default_rng(sum(shape))
+    faces = [(GHOST, 0.5), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0), (HELD, 0.25), (MIRROR, 0)]
+    spec = bc_spec(1, faces)
+    w = W.Workload("edge", shape, spec, [rng.uniform(0, 1, shape)], 5, 0)
+    ref = oracle.run(spec, w.fields, 5)[0]
+    for plan in compiled_plans(w, czs=(0,)):
+        got, _ = gpu_run(w, 5, plan=plan)
+        assert np.max(np.abs(got[0] - ref)) <= 1e-6, plan
+
+
+def test_held_and_ghost_faces_every_axis():
+    shape = (9, 13, 70)
+    rng = np.random.default_rng(2)
+    faces = [(HELD, 1.0), (GHOST, -0.5), (HELD, 0.25), (MIRROR, 0), (GHOST, 2.0), (HELD, -1.0)]
+    spec = bc_spec(2, faces)
+    w = W.Workload("faces", shape, spec, [rng.uniform(0, 1, shape) for _ in range(2)], 20, 0)
+    check_parity(w, 20, label="held/ghost faces")
+    base = None
+    for plan in compiled_plans(w, czs=(0, 3)):
+        got, _ = gpu_run(w, 6, plan=plan)
+        if base is None:
+            base = got
+        assert all(np.array_equal(a, b) for a, b in zip(got, base)), plan
+
+
+def test_zero_steps_is_identity():
+    w = W.make_workload("pollutant512", shape=(5, 6, 7))
+    got, _ = gpu_run(w, 0)
+    for s in range(4):
+        assert np.array_equal(got[s], w.fields[s].astype(np.float32).astype(np.float64))
+
+
+# ---------------------------------------------------------------- batch
+
+def test_batched_results_equal_alone():
+    """Grids of different sizes and models stepped together in one persistent
+    launch per step give bit-identical fields to each grid stepped alone."""
+    import torch
+    stream = torch.cuda.Stream()
+    reqs = [W.Request(0, 0, 32, "diffusion", 37, 11), W.Request(1, 0, 48, "brusselator", 20, 12),
+            W.Request(2, 0, 64, "diffusion", 25, 13), W.Request(3, 0, 40, "brusselator", 31, 14)]
+    ws = [W.request_workload(r) for r in reqs]
+    b = rd.Batch(8, 1 << 34, "f32", stream=stream)
+    grids = []
+    for r, w in zip(reqs, ws):
+        g = rd.Grid.from_workload(w, stream=stream)
+        b.add(g, r.steps)
+        grids.append(g)
+    finished = []
+    while len(finished) < len(grids):
+        finished += b.step(8)
+    for r, w, g in zip(reqs, ws, grids):
+        alone, _ = gpu_run(w, r.steps)
+        got = g.read_all()
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], alone[s]), (r, s)
+        g.close()
+    b.close()
+
+
+def test_batch_budget_and_validation():
+    import torch
+    stream = torch.cuda.Stream()
+    w = W.request_workload(W.Request(0, 0, 32, "diffusion", 10, 1))
+    need = rd.grid_bytes(w.shape, 1)
+    b = rd.Batch(2, need + 10, "f32", stream=stream)
+    g1 = rd.Grid.from_workload(w, stream=stream)
+    g2 = rd.Grid.from_workload(w, stream=stream)
+    b.add(g1, 5)
+    with pytest.raises(rd.RDError) as ei:
+        b.add(g2, 5)
+    assert ei.value.code == rd.ENOMEM
+    with pytest.raises(rd.RDError) as ei:
+        g1.step(1)                       # a member is stepped by its batch only
+    assert ei.value.code == rd.ESTATE
+    b.remove(g1)
+    b.add(g2, 5)
+    b.close()
+    g1.close()
+    g2.close()
