@@ -107,6 +107,8 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--plan", default=None,
+                    help="JSON plan (kernel, vx, ry, waves, cz) to use instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
@@ -125,7 +127,12 @@ def main():
                                                           args.steps, args.warmup),
           file=sys.stderr, flush=True)
     g = rd.Grid.from_workload(w, storage=args.storage, stream=stream)
-    plan = g.plan() if args.no_autotune else g.autotune(10)
+    if args.plan:
+        plan = json.loads(args.plan)
+    elif args.no_autotune:
+        plan = g.plan()
+    else:
+        plan = g.autotune(10)
     chunk = args.graph_chunk if args.graph_chunk >= 2 else 0
     plan["graph_chunk"] = chunk - (chunk & 1)
     g.set_plan(**plan)

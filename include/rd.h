@@ -122,15 +122,19 @@ typedef struct rd_model_desc {
 enum {
     RD_KERNEL_AUTO = 0,    /* library choice (autotune cache or heuristic)      */
     RD_KERNEL_DIRECT = 1,  /* one thread per cell, neighbours through the cache */
-    RD_KERNEL_TILED = 2    /* xy tile per workgroup, z-march register window,
+    RD_KERNEL_TILED = 2,   /* xy tile per workgroup, z-march register window,
                               wave64 lane shifts for x, LDS for inter-wave rows */
+    RD_KERNEL_BLOCK = 3    /* xy tile x cz-plane slab per workgroup, all planes
+                              loaded up front; same lane shifts and LDS rows    */
 };
 typedef struct rd_plan {
     int32_t kernel;       /* RD_KERNEL_*                                        */
-    int32_t vx;           /* TILED: cells per lane along x (1, 2 or 4)          */
-    int32_t ry;           /* TILED: rows per wave (1, 2 or 4)                   */
-    int32_t waves;        /* TILED: waves per workgroup (1, 2 or 4)             */
-    int32_t cz;           /* TILED: z planes per workgroup, 0 = whole z axis    */
+    int32_t vx;           /* TILED/BLOCK: cells per lane along x (1, 2 or 4)    */
+    int32_t ry;           /* TILED/BLOCK: rows per wave (1, 2 or 4)             */
+    int32_t waves;        /* TILED/BLOCK: waves per workgroup (1 or 4)          */
+    int32_t cz;           /* TILED: z planes per workgroup, 0 = whole z axis;
+                             BLOCK: planes per slab (2, 4 or 8)                */
+    int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2) */
     int32_t graph_chunk;  /* rd_step replays hipGraphs of this many steps (even,
                              >= 2); 0 launches every step directly            */
 } rd_plan;

@@ -394,22 +394,30 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return xcd < r ? xcd * (q + 1) + i : r * (q + 1) + (xcd - r) * q + i;
 }
 
-// One row (VX cells per lane) of field f at resolved plane/row, returned by
-// value so that the held-face selects act on registers.
-template <int VX> struct Row { float v[VX]; };
+// ---- tiled march ---------------------------------------------------------
+//
+// A workgroup owns columns [x0, x0+TX) x rows [yb, yb+BY) and marches planes
+// [z0, z1).  Each wave holds RY rows of VX cells per lane for planes z-1, z,
+// z+1 (the z window) and keeps PF further planes in flight.  Loads are issued
+// back to back from always-valid (clamped) addresses; boundary rules that
+// replace a loaded value (fixed ghosts, held layers) are applied when the
+// plane enters the window, so they never sit between loads.
 
 template <class M, class S, int VX>
-__device__ __forceinline__ Row<VX> load_row(const StepArgs& a, int f, Src pz, Src py,
-                                            int xl) {
-    Row<VX> r;
+__device__ __forceinline__ void load_raw(const StepArgs& a, int f, long long idx, float (&v)[VX]) {
+    if (M::f32_field(f)) load_vec<StF32, VX>(a.in[f], idx, v);
+    else load_vec<S, VX>(a.in[f], idx, v);
+}
+
+// Replace loaded values where a boundary rule fixes them: a fixed row or
+// plane (ghost / held layer), then held x faces (x faces win, face order).
+template <int VX>
+__device__ __forceinline__ void fix_row(const StepArgs& a, int f, Src pz, Src py, int xl,
+                                        float (&v)[VX]) {
     if (py.cst || pz.cst) {
         const float c = py.cst ? py.v : pz.v;
 #pragma unroll
-        for (int i = 0; i < VX; ++i) r.v[i] = c;
-    } else {
-        const long long idx = (long long)pz.idx * a.plane + (long long)py.idx * a.pitch + xl;
-        if (M::f32_field(f)) load_vec<StF32, VX>(a.in[f], idx, r.v);
-        else load_vec<S, VX>(a.in[f], idx, r.v);
+        for (int i = 0; i < VX; ++i) v[i] = c;
     }
     const int hm = a.held[f];
     if (hm & 3) {
@@ -417,30 +425,9 @@ __device__ __forceinline__ Row<VX> load_row(const StepArgs& a, int f, Src pz, Sr
 #pragma unroll
         for (int i = 0; i < VX; ++i) {
             const int x = xl + i;
-            r.v[i] = ((hm & 1) && x == 0) ? b0 : ((hm & 2) && x == a.nx - 1) ? b1 : r.v[i];
+            v[i] = ((hm & 1) && x == 0) ? b0 : ((hm & 2) && x == a.nx - 1) ? b1 : v[i];
         }
     }
-    return r;
-}
-
-// The x-edge value a lane at the tile border needs: lane 0 the cell left of
-// the tile, lane 63 the cell right of the tile (or of the last cell, nx-1).
-template <class M, class S>
-__device__ __forceinline__ float load_edge(const StepArgs& a, int f, Src pz, Src py,
-                                           int lane, int x0, int tx_width) {
-    float e = 0.f;
-    if (lane == 0 || lane == 63) {
-        const int q = lane == 0 ? x0 - 1 : min(x0 + tx_width, a.nx);
-        const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
-        if (py.cst) e = py.v;
-        else if (pz.cst) e = pz.v;
-        else {
-            const long long idx = (long long)pz.idx * a.plane + (long long)py.idx * a.pitch + sx.idx;
-            e = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
-        }
-        if (sx.cst) e = sx.v;
-    }
-    return e;
 }
 
 template <class M, int W, int TX>
@@ -448,9 +435,22 @@ struct TileLds {
     float row[W > 1 ? 2 : 1][M::NF][W > 1 ? W : 1][2][W > 1 ? TX : 1];
 };
 
-// One tile: columns [x0, x0+TX), rows [y0, y0+RY*W), planes [z0, z1),
-// marching in z with planes z-1, z, z+1 in registers and z+2 in flight.
-template <class M, class S, int VX, int RY, int W>
+// Value of row element `x` (0 <= x < nx <= TX) held by this wave: lane x/VX,
+// element x%VX.  Every element is read out of that lane first and the choice
+// is made among those values, so the window never needs an address.
+template <int VX>
+__device__ __forceinline__ float row_element(const float (&v)[VX], int x) {
+    const int src = x / VX, e = x % VX;
+    float t = bcast_lane(v[0], src);
+#pragma unroll
+    for (int i = 1; i < VX; ++i) {
+        const float u = bcast_lane(v[i], src);
+        t = e == i ? u : t;
+    }
+    return t;
+}
+
+template <class M, class S, int VX, int RY, int W, int PF>
 __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W, 64 * VX>& sm) {
     constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, BY = RY * W;
     const int lane = threadIdx.x & 63;
@@ -465,11 +465,8 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
     const int z0 = tz * a.cz;
     const int z1 = min(z0 + a.cz, a.nz);
     const int xl = x0 + lane * VX;
-
-    float P[NF][3][RY][VX];   // planes z-1, z, z+1
-    float Q[NF][RY][VX];      // plane z+2 (in flight)
-    float H[NF][VX], Hn[NF][VX];      // halo row above (wave 0) / below (wave W-1)
-    float E[NF][RY], En[NF][RY];      // x-edge values per row for plane z / z+1
+    const bool whole_row = a.tiles_x == 1;  // x ghosts come from the row itself
+    const bool top = W == 1 || w == 0, bottom = W == 1 || w == W - 1;
 
     auto plane_src = [&](int f, int z) {
         return resolve_axis(z, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
@@ -477,49 +474,71 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
     auto row_src = [&](int f, int y) {
         return resolve_axis(y, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
     };
-    auto load_plane = [&](float (&dst)[NF][RY][VX], int z) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const Src pz = plane_src(f, z);
-#pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                const Row<VX> row = load_row<M, S, VX>(a, f, pz, row_src(f, y0 + r), xl);
-#pragma unroll
-                for (int i = 0; i < VX; ++i) dst[f][r][i] = row.v[i];
-            }
-        }
+    auto row_idx = [&](Src pz, Src py) {
+        return (long long)pz.idx * a.plane + (long long)py.idx * a.pitch;
     };
-    auto load_extras = [&](float (&h)[NF][VX], float (&e)[NF][RY], int z) {
+
+    float P[NF][3][RY][VX];       // planes z-1, z, z+1 (ready)
+    float Q[PF][NF][RY][VX];      // planes z+2 .. z+1+PF (in flight)
+    float Ht[NF][VX], Hb[NF][VX];             // halo rows above / below, plane z
+    float Htn[NF][VX], Hbn[NF][VX];           // same, plane z+1 (in flight)
+    float E[NF][RY], En[NF][RY];              // x-edge loads (multi-tile rows)
+
+    auto issue_plane = [&](float (&d)[NF][RY][VX], int z) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const Src pz = plane_src(f, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r)
-                e[f][r] = load_edge<M, S>(a, f, pz, row_src(f, y0 + r), lane, x0, TX);
-            if (w == 0 || w == W - 1) {
-                const Row<VX> row = load_row<M, S, VX>(a, f, pz, row_src(f, w == 0 ? yb - 1 : yb + BY), xl);
-#pragma unroll
-                for (int i = 0; i < VX; ++i) h[f][i] = row.v[i];
-            }
+                load_raw<M, S, VX>(a, f, row_idx(pz, row_src(f, y0 + r)) + xl, d[f][r]);
         }
     };
-    // W == 1: one wave needs both halo rows; keep the second in Hb.
-    float Hb[NF][VX], Hbn[NF][VX];
-    auto load_extras1 = [&](int z, bool next) {
+    auto finish_plane = [&](float (&d)[NF][RY][VX], int z) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const Src pz = plane_src(f, z);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                const float e = load_edge<M, S>(a, f, pz, row_src(f, y0 + r), lane, x0, TX);
-                if (next) En[f][r] = e; else E[f][r] = e;
-            }
-            const Row<VX> top = load_row<M, S, VX>(a, f, pz, row_src(f, yb - 1), xl);
-            const Row<VX> bot = load_row<M, S, VX>(a, f, pz, row_src(f, yb + BY), xl);
+            for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, pz, row_src(f, y0 + r), xl, d[f][r]);
+        }
+    };
+    // halo rows (block edges) and x-edge values of plane z
+    auto issue_extras = [&](float (&ht)[NF][VX], float (&hb)[NF][VX], float (&e)[NF][RY], int z) {
 #pragma unroll
-            for (int i = 0; i < VX; ++i) {
-                if (next) { Hn[f][i] = top.v[i]; Hbn[f][i] = bot.v[i]; }
-                else { H[f][i] = top.v[i]; Hb[f][i] = bot.v[i]; }
+        for (int f = 0; f < NF; ++f) {
+            const Src pz = plane_src(f, z);
+            if (top) load_raw<M, S, VX>(a, f, row_idx(pz, row_src(f, yb - 1)) + xl, ht[f]);
+            if (bottom) load_raw<M, S, VX>(a, f, row_idx(pz, row_src(f, yb + BY)) + xl, hb[f]);
+            if (!whole_row) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    e[f][r] = 0.f;
+                    if (lane == 0 || lane == 63) {
+                        const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
+                        const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0],
+                                                    a.bcv[f][1]);
+                        const long long idx = row_idx(pz, row_src(f, y0 + r)) + sx.idx;
+                        e[f][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
+                    }
+                }
+            }
+        }
+    };
+    auto finish_extras = [&](float (&ht)[NF][VX], float (&hb)[NF][VX], float (&e)[NF][RY], int z) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const Src pz = plane_src(f, z);
+            if (top) fix_row<VX>(a, f, pz, row_src(f, yb - 1), xl, ht[f]);
+            if (bottom) fix_row<VX>(a, f, pz, row_src(f, yb + BY), xl, hb[f]);
+            if (!whole_row) {
+                const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
+                const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const Src py = row_src(f, y0 + r);
+                    float v = e[f][r];
+                    v = py.cst ? py.v : (pz.cst ? pz.v : v);
+                    e[f][r] = sx.cst ? sx.v : v;
+                }
             }
         }
     };
@@ -527,9 +546,18 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
     // prologue
     {
         float T0[NF][RY][VX], T1[NF][RY][VX], T2[NF][RY][VX];
-        load_plane(T0, z0 - 1);
-        load_plane(T1, z0);
-        load_plane(T2, z0 + 1);
+        issue_plane(T0, z0 - 1);
+        issue_plane(T1, z0);
+        issue_plane(T2, z0 + 1);
+        issue_extras(Ht, Hb, E, z0);
+#pragma unroll
+        for (int k = 0; k < PF; ++k)
+            if (z0 + 2 + k <= z1) issue_plane(Q[k], z0 + 2 + k);
+        if (z0 + 1 < z1) issue_extras(Htn, Hbn, En, z0 + 1);
+        finish_plane(T0, z0 - 1);
+        finish_plane(T1, z0);
+        finish_plane(T2, z0 + 1);
+        finish_extras(Ht, Hb, E, z0);
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -541,14 +569,10 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
                     P[f][2][r][i] = T2[f][r][i];
                 }
     }
-    if (W == 1) load_extras1(z0, false); else load_extras(H, E, z0);
-    if (z0 + 2 <= z1) load_plane(Q, z0 + 2);
-    if (z0 + 1 < z1) { if (W == 1) load_extras1(z0 + 1, true); else load_extras(Hn, En, z0 + 1); }
 
     for (int z = z0; z < z1; ++z) {
         const int par = (z - z0) & 1;
-        // rows above row 0 and below row RY-1 of this wave
-        float up[NF][VX], dn[NF][VX];
+        float up[NF][VX], dn[NF][VX];      // rows above row 0 / below row RY-1
         if (W > 1) {
 #pragma unroll
             for (int f = 0; f < NF; ++f)
@@ -562,15 +586,15 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
             for (int f = 0; f < NF; ++f)
 #pragma unroll
                 for (int i = 0; i < VX; ++i) {
-                    up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][1][lane * VX + i] : H[f][i];
+                    up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][1][lane * VX + i] : Ht[f][i];
                     dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i]
-                                         : H[f][i];
+                                         : Hb[f][i];
                 }
         } else {
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int i = 0; i < VX; ++i) { up[f][i] = H[f][i]; dn[f][i] = Hb[f][i]; }
+                for (int i = 0; i < VX; ++i) { up[f][i] = Ht[f][i]; dn[f][i] = Hb[f][i]; }
         }
 
         const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
@@ -580,8 +604,18 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
             Nb n[NF][VX];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const float L = bcast_lane(E[f][r], 0);
-                const float R = bcast_lane(E[f][r], 63);
+                float L, R;
+                if (whole_row) {
+                    // ghost left of x=0 and right of x=nx-1, from this very row
+                    const int klo = a.bck[f][0], khi = a.bck[f][1];
+                    const float first = row_element<VX>(P[f][1][r], 0);
+                    const float last = row_element<VX>(P[f][1][r], a.nx - 1);
+                    L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
+                    R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
+                } else {
+                    L = bcast_lane(E[f][r], 0);
+                    R = bcast_lane(E[f][r], 63);
+                }
                 const float left = lane_from_left(P[f][1][r][VX - 1], L);
                 const float right = lane_from_right(P[f][1][r][0], R);
 #pragma unroll
@@ -625,7 +659,7 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
             }
         }
 
-        // rotate the window and issue the next loads
+        // slide the window: z+2 enters, issue plane z+2+PF and the extras of z+2
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
 #pragma unroll
@@ -634,28 +668,279 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W
                 for (int i = 0; i < VX; ++i) {
                     P[f][0][r][i] = P[f][1][r][i];
                     P[f][1][r][i] = P[f][2][r][i];
-                    P[f][2][r][i] = Q[f][r][i];
+                    P[f][2][r][i] = Q[0][f][r][i];
+#pragma unroll
+                    for (int k = 0; k + 1 < PF; ++k) Q[k][f][r][i] = Q[k + 1][f][r][i];
                 }
 #pragma unroll
             for (int r = 0; r < RY; ++r) E[f][r] = En[f][r];
 #pragma unroll
             for (int i = 0; i < VX; ++i) {
-                H[f][i] = Hn[f][i];
-                if (W == 1) Hb[f][i] = Hbn[f][i];
+                Ht[f][i] = Htn[f][i];
+                Hb[f][i] = Hbn[f][i];
             }
         }
-        if (z + 3 <= z1) load_plane(Q, z + 3);
-        if (z + 2 < z1) { if (W == 1) load_extras1(z + 2, true); else load_extras(Hn, En, z + 2); }
+        if (z + 2 + PF <= z1) issue_plane(Q[PF - 1], z + 2 + PF);
+        if (z + 2 < z1) issue_extras(Htn, Hbn, En, z + 2);
+        if (z + 2 <= z1) {
+            float T[NF][RY][VX];
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) T[f][r][i] = P[f][2][r][i];
+            finish_plane(T, z + 2);
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int r = 0; r < RY; ++r)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) P[f][2][r][i] = T[f][r][i];
+        }
+        if (z + 1 < z1) finish_extras(Ht, Hb, E, z + 1);
     }
     if (W > 1) __syncthreads();   // the LDS rows may be reused by the next tile
 }
 
 // Step arguments live in device memory (not the kernel-argument segment) so
 // that boundary values picked by runtime conditions are plain scalar loads.
-template <class M, class S, int VX, int RY, int W>
+template <class M, class S, int VX, int RY, int W, int PF>
 __global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restrict__ pa) {
     __shared__ TileLds<M, W, 64 * VX> sm;
-    tile_step<M, S, VX, RY, W>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
+    tile_step<M, S, VX, RY, W, PF>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
+}
+
+// ---- plane-block kernel ---------------------------------------------------
+//
+// A workgroup computes the slab of columns [x0, x0+TX), rows [yb, yb+BY) and
+// CZ planes [z0, z0+CZ).  All CZ+2 planes it reads (one halo plane on each
+// side) are requested up front; the boundary rules of rows and planes are
+// resolved once per slab.  There is no loop-carried window, so the compiler
+// keeps every plane in fixed registers and lets all loads fly together.
+
+template <class M, int W, int TX>
+struct BlockLds {
+    float row[W > 1 ? 2 : 1][M::NF][W > 1 ? W : 1][2][W > 1 ? TX : 1];
+};
+
+template <class M, class S, int VX, int RY, int W, int CZ>
+__device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M, W, 64 * VX>& sm) {
+    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, BY = RY * W, NP = CZ + 2;
+    constexpr int NH = W == 1 ? 2 : 1;      // halo rows a wave loads per plane
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = t % a.tiles_x;
+    const int t2 = t / a.tiles_x;
+    const int ty = t2 % a.tiles_y;
+    const int tz = t2 / a.tiles_y;
+    const int x0 = tx * TX;
+    const int yb = ty * BY;
+    const int y0 = yb + w * RY;
+    const int z0 = tz * CZ;
+    const int xl = x0 + lane * VX;
+    const bool whole_row = a.tiles_x == 1;
+    const bool edge_wave = W == 1 || w == 0 || w == W - 1;
+    // halo row h of this wave: W == 1: h=0 above, h=1 below; else above for
+    // wave 0, below for wave W-1.
+    const int hrow0 = (W == 1 || w == 0) ? yb - 1 : yb + BY;
+
+    // z-independent row sources and z plane sources, resolved once
+    Src rs[NF][RY], rh[NF][NH], ps[NF][NP];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r)
+            rs[f][r] = resolve_axis(y0 + r, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+            rh[f][h] = resolve_axis(h == 0 ? hrow0 : yb + BY, a.ny, a.bck[f][2], a.bck[f][3],
+                                    a.bcv[f][2], a.bcv[f][3]);
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            ps[f][k] = resolve_axis(z0 - 1 + k, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+    }
+
+    // issue every load of the slab
+    float V[NF][NP][RY][VX];
+    float H[NF][CZ][NH][VX];
+    float E[NF][CZ][RY];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                load_raw<M, S, VX>(a, f, (long long)ps[f][k].idx * a.plane +
+                                             (long long)rs[f][r].idx * a.pitch + xl, V[f][k][r]);
+    if (edge_wave) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int k = 0; k < CZ; ++k)
+#pragma unroll
+                for (int h = 0; h < NH; ++h)
+                    load_raw<M, S, VX>(a, f, (long long)ps[f][k + 1].idx * a.plane +
+                                                 (long long)rh[f][h].idx * a.pitch + xl, H[f][k][h]);
+    }
+    int sxi[NF];
+    if (!whole_row) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
+            sxi[f] = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]).idx;
+#pragma unroll
+            for (int k = 0; k < CZ; ++k)
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    E[f][k][r] = 0.f;
+                    if (lane == 0 || lane == 63) {
+                        const long long idx = (long long)ps[f][k + 1].idx * a.plane +
+                                              (long long)rs[f][r].idx * a.pitch + sxi[f];
+                        E[f][k][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
+                    }
+                }
+        }
+    }
+
+    // boundary rules that replace loaded values (fixed rows/planes, held x faces)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        bool any = (a.held[f] & 3) != 0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) any = any || ps[f][k].cst;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) any = any || rs[f][r].cst;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) any = any || rh[f][h].cst;
+        if (any) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+#pragma unroll
+                for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, ps[f][k], rs[f][r], xl, V[f][k][r]);
+            if (edge_wave) {
+#pragma unroll
+                for (int k = 0; k < CZ; ++k)
+#pragma unroll
+                    for (int h = 0; h < NH; ++h) fix_row<VX>(a, f, ps[f][k + 1], rh[f][h], xl, H[f][k][h]);
+            }
+        }
+        if (!whole_row) {
+            const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
+            const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
+#pragma unroll
+            for (int k = 0; k < CZ; ++k)
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const Src py = rs[f][r], pz = ps[f][k + 1];
+                    float v = E[f][k][r];
+                    v = py.cst ? py.v : (pz.cst ? pz.v : v);
+                    E[f][k][r] = sx.cst ? sx.v : v;
+                }
+        }
+    }
+
+#pragma unroll
+    for (int k = 1; k <= CZ; ++k) {
+        const int z = z0 + k - 1;
+        if (z < a.nz) {
+            float up[NF][VX], dn[NF][VX];
+            if (W > 1) {
+                const int par = k & 1;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        sm.row[par][f][w][0][lane * VX + i] = V[f][k][0][i];
+                        sm.row[par][f][w][1][lane * VX + i] = V[f][k][RY - 1][i];
+                    }
+                __syncthreads();
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][1][lane * VX + i] : H[f][k - 1][0][i];
+                        dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i]
+                                             : H[f][k - 1][0][i];
+                    }
+            } else {
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        up[f][i] = H[f][k - 1][0][i];
+                        dn[f][i] = H[f][k - 1][NH - 1][i];
+                    }
+            }
+            const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int y = y0 + r;
+                Nb n[NF][VX];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    float L, R;
+                    if (whole_row) {
+                        const int klo = a.bck[f][0], khi = a.bck[f][1];
+                        const float first = bcast_lane(V[f][k][r][0], 0);
+                        const float last = row_element<VX>(V[f][k][r], a.nx - 1);
+                        L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
+                        R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
+                    } else {
+                        L = bcast_lane(E[f][k - 1][r], 0);
+                        R = bcast_lane(E[f][k - 1][r], 63);
+                    }
+                    const float left = lane_from_left(V[f][k][r][VX - 1], L);
+                    const float right = lane_from_right(V[f][k][r][0], R);
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        Nb& q = n[f][i];
+                        q.c = V[f][k][r][i];
+                        q.xm = i > 0 ? V[f][k][r][i - 1] : left;
+                        q.xp = i < VX - 1 ? V[f][k][r][i + 1] : right;
+                        if (xl + i == a.nx - 1) q.xp = R;
+                        q.ym = r > 0 ? V[f][k][r - 1][i] : up[f][i];
+                        q.yp = r < RY - 1 ? V[f][k][r + 1][i] : dn[f][i];
+                        q.zm = V[f][k - 1][r][i];
+                        q.zp = V[f][k + 1][r][i];
+                    }
+                }
+                int s0 = 0, s1 = 0;
+                if (M::SOURCES && y < a.ny) {
+                    s0 = a.src_row[z * a.ny + y];
+                    s1 = a.src_row[z * a.ny + y + 1];
+                }
+                float o[NO][VX];
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    Nb ni[NF];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) ni[f] = n[f][i];
+                    Emission<NO> em{};
+                    if (M::SOURCES && s0 < s1) em = cell_sources<NO>(a, xl + i, s0, s1);
+                    float oi[NO];
+                    M::cell(a, ni, uh, em.any, em.e, oi);
+#pragma unroll
+                    for (int s = 0; s < NO; ++s) o[s][i] = held_out(a, s, xl + i, y, z, oi[s]);
+                }
+                if (y < a.ny && xl < a.nx) {
+                    const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
+#pragma unroll
+                    for (int s = 0; s < NO; ++s) {
+                        if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
+                        else store_vec<S, VX>(a.out[s], idx, o[s]);
+                    }
+                }
+            }
+        }
+    }
+    if (W > 1) __syncthreads();   // the LDS rows may be reused by the next slab
+}
+
+template <class M, class S, int VX, int RY, int W, int CZ>
+__global__ __launch_bounds__(64 * W) void block_kernel(const StepArgs* __restrict__ pa) {
+    __shared__ BlockLds<M, W, 64 * VX> sm;
+    block_step<M, S, VX, RY, W, CZ>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
 // ------------------------------------------------------------ batched kernel
@@ -678,7 +963,7 @@ struct BatchTable {
     BatchEntry e[1];      // ngrids entries follow
 };
 
-template <class S, int VX, int RY, int W>
+template <class S, int VX, int RY, int W, int PF>
 __global__ __launch_bounds__(64 * W) void batched_kernel(const BatchTable* __restrict__ tab, int step) {
     __shared__ TileLds<Brusselator, W, 64 * VX> smb;
     __shared__ TileLds<Diffusion<1>, W, 64 * VX> smd;
@@ -694,8 +979,8 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(const BatchTable* __res
         if (step >= en.steps_left) continue;     // this grid already finished
         const StepArgs& a = en.args[(en.parity + step) & 1];
         const int t = item - en.first_item;
-        if (en.model == 1) tile_step<Brusselator, S, VX, RY, W>(a, t, smb);
-        else tile_step<Diffusion<1>, S, VX, RY, W>(a, t, smd);
+        if (en.model == 1) tile_step<Brusselator, S, VX, RY, W, PF>(a, t, smb);
+        else tile_step<Diffusion<1>, S, VX, RY, W, PF>(a, t, smd);
     }
 }
 
@@ -786,20 +1071,17 @@ __global__ __launch_bounds__(256) void unpack_kernel(const void* src, DstT* dst,
 #ifdef RD_DEFINE_ENGINE_KERNELS
 // ----------------------------------------------------------- copy ceiling
 
+// One 16-byte element per thread, streamed with non-temporal load/store:
+// the read+write bandwidth ceiling a kernel can reach.
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
                                                    float4* __restrict__ dst, long long n4) {
-    const long long stride = (long long)gridDim.x * 256;
-    long long i = blockIdx.x * 256LL + threadIdx.x;
-    for (; i + 3 * stride < n4; i += 4 * stride) {
-        const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i < n4) {
+        const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(src) + i);
+        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(dst) + i);
     }
-    for (; i < n4; i += stride) dst[i] = src[i];
 }
-
 #endif
 
 }  // namespace rdk

@@ -69,9 +69,17 @@ int num_cus() {
 
 namespace rdk {
 
-int tile_cfg_index(int vx, int ry, int w) {
+int block_cfg_index(int vx, int ry, int w, int cz) {
+    for (int i = 0; i < kNumBlockCfgs; ++i)
+        if (kBlockCfgs[i].vx == vx && kBlockCfgs[i].ry == ry && kBlockCfgs[i].w == w && kBlockCfgs[i].cz == cz)
+            return i;
+    return -1;
+}
+
+int tile_cfg_index(int vx, int ry, int w, int pf) {
     for (int i = 0; i < kNumTileCfgs; ++i)
-        if (kTileCfgs[i].vx == vx && kTileCfgs[i].ry == ry && kTileCfgs[i].w == w) return i;
+        if (kTileCfgs[i].vx == vx && kTileCfgs[i].ry == ry && kTileCfgs[i].w == w && kTileCfgs[i].pf == pf)
+            return i;
     return -1;
 }
 
@@ -204,40 +212,36 @@ long long set_tiling(StepArgs& a, const rd_plan& p) {
     return (long long)a.tiles_x * a.tiles_y * a.chunks_z;
 }
 
-// Default plan: the tiled kernel with the compiled tile shape that wastes the
-// fewest lanes along x (ties: wider tiles, then 2 rows per wave), and a z
-// chunk giving about 8 workgroups per CU.
-rd_plan heuristic_plan(const rd_grid* g, int pm) {
+// Default plan: the plane-block kernel with the compiled slab shape that
+// wastes the fewest lanes and rows (ties: wider rows, one row per wave,
+// four-plane slabs, multi-wave workgroups).
+rd_plan heuristic_plan(const rd_grid* g) {
     rd_plan best{};
     best.kernel = RD_KERNEL_DIRECT;
     double best_score = 1e30;
-    const unsigned mask = cfg_mask(g->storage, pm);
-    for (int i = 0; i < kNumTileCfgs; ++i) {
+    unsigned mask = ~0u;
+    for (int k = 0; k < g->npass; ++k) mask &= block_mask(g->storage, g->pass_pm[k]);
+    for (int i = 0; i < kNumBlockCfgs; ++i) {
         if (!((mask >> i) & 1u)) continue;
-        const TileCfg c = kTileCfgs[i];
+        const BlockCfg c = kBlockCfgs[i];
         const int tx = 64 * c.vx, by = c.ry * c.w;
         const double wx = double((g->nx + tx - 1) / tx * tx) / double(g->nx);
         const double wy = double((g->ny + by - 1) / by * by) / double(g->ny);
-        double score = wx * wy;
-        score -= 1e-3 * c.vx;                  // wider rows first
-        score += 1e-4 * std::abs(c.ry - 2);    // then two rows per wave
-        score += c.w == 1 ? 1e-2 : 0.0;        // multi-wave tiles share halo rows in LDS
+        const double wz = double((g->nz + c.cz - 1) / c.cz * c.cz) / double(g->nz);
+        double score = wx * wy * wz;
+        score -= 1e-3 * c.vx;
+        score += 1e-4 * std::abs(c.ry - 1);
+        score += 1e-5 * std::abs(c.cz - 4);
+        score += c.w == 1 ? 1e-2 : 0.0;
         if (score < best_score) {
             best_score = score;
-            best.kernel = RD_KERNEL_TILED;
+            best.kernel = RD_KERNEL_BLOCK;
             best.vx = c.vx;
             best.ry = c.ry;
             best.waves = c.w;
+            best.cz = c.cz;
+            best.prefetch = 0;
         }
-    }
-    if (best.kernel == RD_KERNEL_TILED) {
-        const long long xy = ((g->nx + 64 * best.vx - 1) / (64 * best.vx)) *
-                             ((g->ny + best.ry * best.waves - 1) / (best.ry * best.waves));
-        const long long target = 8LL * num_cus();
-        long long chunks = std::max(1LL, (target + xy - 1) / xy);
-        int cz = int((g->nz + chunks - 1) / chunks);
-        cz = std::max(cz, 8);
-        best.cz = cz >= g->nz ? 0 : cz;
     }
     best.graph_chunk = 0;
     return best;
@@ -255,8 +259,17 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
         *cfg_out = -1;
         return RD_OK;
     }
+    if (p.kernel == RD_KERNEL_BLOCK) {
+        const int cfg = block_cfg_index(p.vx, p.ry, p.waves, p.cz);
+        if (cfg < 0) return fail(RD_EINVAL, "slab shape not available");
+        for (int k = 0; k < g->npass; ++k)
+            if (!((block_mask(g->storage, g->pass_pm[k]) >> cfg) & 1u))
+                return fail(RD_EINVAL, "slab shape not compiled for this model and storage");
+        *cfg_out = cfg;
+        return RD_OK;
+    }
     if (p.kernel != RD_KERNEL_TILED) return fail(RD_EINVAL, "unknown kernel kind");
-    const int cfg = tile_cfg_index(p.vx, p.ry, p.waves);
+    const int cfg = tile_cfg_index(p.vx, p.ry, p.waves, p.prefetch);
     if (cfg < 0) return fail(RD_EINVAL, "tile shape not available");
     for (int k = 0; k < g->npass; ++k)
         if (!((cfg_mask(g->storage, g->pass_pm[k]) >> cfg) & 1u))
@@ -273,7 +286,7 @@ int apply_plan(rd_grid* g) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find({g->nx, g->ny, g->nz, g->ns, g->model, g->storage});
         const int gc = p.graph_chunk;
-        p = it != g_tune_cache.end() ? it->second : heuristic_plan(g, g->pass_pm[g->npass - 1]);
+        p = it != g_tune_cache.end() ? it->second : heuristic_plan(g);
         p.graph_chunk = gc;
     }
     int cfg = -1;
@@ -282,11 +295,11 @@ int apply_plan(rd_grid* g) {
     for (int par = 0; par < 2; ++par)
         for (int k = 0; k < g->npass; ++k) {
             StepArgs& a = g->args[par][k];
-            if (p.kernel == RD_KERNEL_TILED) g->blocks[k] = set_tiling(a, p);
+            if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK) g->blocks[k] = set_tiling(a, p);
             else g->blocks[k] = 0;
         }
     for (int k = 0; k < g->npass; ++k)
-        if (p.kernel == RD_KERNEL_TILED && g->blocks[k] > 0x7fffffffLL)
+        if (g->blocks[k] > 0x7fffffffLL)
             return fail(RD_EINVAL, "too many workgroups for this plan");
     g->eff = p;
     g->cfg = cfg;
@@ -847,23 +860,36 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     for (int i = 0; i < kNumTileCfgs; ++i) {
         if (!((mask >> i) & 1u)) continue;
         const TileCfg c = kTileCfgs[i];
-        std::vector<int> czs = {0, 128, 64, 32, 16, 8};
-        for (int cz : czs) {
+        for (int cz : {0, 32, 16, 8, 4}) {
             if (cz != 0 && cz >= g->nz) continue;
             rd_plan p{};
             p.kernel = RD_KERNEL_TILED;
             p.vx = c.vx;
             p.ry = c.ry;
             p.waves = c.w;
+            p.prefetch = c.pf;
             p.cz = cz;
             cands.push_back(p);
         }
+    }
+    unsigned bmask = ~0u;
+    for (int k = 0; k < g->npass; ++k) bmask &= block_mask(g->storage, g->pass_pm[k]);
+    for (int i = 0; i < kNumBlockCfgs; ++i) {
+        if (!((bmask >> i) & 1u)) continue;
+        const BlockCfg c = kBlockCfgs[i];
+        rd_plan p{};
+        p.kernel = RD_KERNEL_BLOCK;
+        p.vx = c.vx;
+        p.ry = c.ry;
+        p.waves = c.w;
+        p.cz = c.cz;
+        cands.push_back(p);
     }
     hipEvent_t e0, e1;
     RD_HIP(hipEventCreate(&e0));
     RD_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    rd_plan best_plan = heuristic_plan(g, g->pass_pm[g->npass - 1]);
+    rd_plan best_plan = heuristic_plan(g);
     int rc = RD_OK;
     for (const rd_plan& p : cands) {
         g->plan = p;
@@ -1039,6 +1065,7 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     tile.vx = kBatchTile.vx;
     tile.ry = kBatchTile.ry;
     tile.waves = kBatchTile.w;
+    tile.prefetch = kBatchTile.pf;
     int64_t max_steps = 0;
     for (size_t i = 0; i < b->members.size(); ++i) {
         const Member& m = b->members[i];
@@ -1111,9 +1138,9 @@ extern "C" int rd_copy_probe(void* dst, const void* src, size_t bytes, void* hip
     if (!dst || !src) return fail(RD_EINVAL, "NULL argument");
     if (bytes == 0 || (bytes & 15)) return fail(RD_EINVAL, "bytes must be a positive multiple of 16");
     const long long n4 = (long long)(bytes / 16);
-    const long long want = (n4 + 1023) / 1024;
-    const unsigned blocks = unsigned(std::max<long long>(1, std::min<long long>(want, 8LL * num_cus() * 4)));
-    hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+    const long long blocks = (n4 + 255) / 256;
+    if (blocks > 0x7fffffffLL) return fail(RD_EINVAL, "copy too large");
+    hipLaunchKernelGGL(copy_kernel, dim3(unsigned(blocks)), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
                        static_cast<const float4*>(src), static_cast<float4*>(dst), n4);
     RD_HIP(hipGetLastError());
     return RD_OK;

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
+
 #include "rd_device.hpp"
 
 namespace rdk {
@@ -19,40 +21,61 @@ enum PassModel {
 
 enum Storage { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2, ST_COUNT };
 
-// Tile shapes of the tiled kernel: cells per lane along x, rows per wave,
-// waves per workgroup.
-struct TileCfg { int vx, ry, w; };
+// Tile shapes of the tiled (z-march) kernel: cells per lane along x, rows per
+// wave, waves per workgroup, planes kept in flight ahead of the z window.
+struct TileCfg { int vx, ry, w, pf; };
 constexpr TileCfg kTileCfgs[] = {
-    {4, 4, 4}, {4, 2, 4}, {4, 1, 4}, {2, 4, 4}, {2, 2, 4}, {2, 1, 4}, {1, 4, 4}, {4, 4, 1},
+    {4, 2, 4, 1}, {4, 1, 4, 2}, {2, 2, 4, 2}, {1, 4, 4, 2},
 };
 constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
 
-// Which tile shapes are compiled for each storage and pass model (bit i =
-// kTileCfgs[i]).  Models with more fields keep fewer rows per wave so that
-// their register window fits without spilling.
-constexpr unsigned cfg_mask(int storage, int pm) {
-    const bool light = pm == PM_DIFF1 || pm == PM_CHMU;
-    const bool medium = pm == PM_BRUSS || pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2;
-    if (storage == ST_F32) {
-        if (pm == PM_DIFF1) return 0b11001011u;            // 444 424 244 144 441
-        if (pm == PM_CHMU) return 0b00011011u;             // 444 424 244 224
-        if (medium) return 0b01011011u;                    // 444 424 244 224 144
-        return 0b01110110u;                                // 424 414 224 214 144
-    }
-    if (storage == ST_BF16) {
-        if (pm == PM_DIFF1 || pm == PM_BRUSS) return 0b01001011u;   // 444 424 244 144
-        if (light) return 0b00001001u;                              // 444 244
-        if (pm == PM_FRONT) return 0b00010110u;                     // 424 414 224
-        return 0b00010010u;                                         // 424 224
-    }
-    if (pm == PM_DIFF1 || pm == PM_BRUSS) return 0b01001010u;       // 424 244 144
-    if (light) return 0b00000001u;                                  // 444
-    return 0b00010100u;                                             // 414 224
+// Slab shapes of the plane-block kernel: cells per lane along x, rows per
+// wave, waves per workgroup, planes per slab.
+struct BlockCfg { int vx, ry, w, cz; };
+constexpr BlockCfg kBlockCfgs[] = {
+    {4, 1, 4, 2}, {4, 1, 4, 4}, {4, 2, 4, 2}, {4, 2, 4, 4},
+    {4, 1, 4, 8}, {2, 2, 4, 4}, {2, 1, 4, 4}, {4, 2, 1, 2},
+};
+constexpr int kNumBlockCfgs = sizeof(kBlockCfgs) / sizeof(kBlockCfgs[0]);
+
+constexpr unsigned bits(std::initializer_list<int> l) {
+    unsigned m = 0;
+    for (int i : l) m |= 1u << i;
+    return m;
 }
 
-int tile_cfg_index(int vx, int ry, int w);   // -1 if no such shape
+// Which shapes are compiled for each storage and pass model (bit i = index
+// into the table).  Models with more fields skip the largest register
+// footprints.  The chemical-potential pass covers every shape of the front
+// update so both passes of a step share one plan.
+constexpr unsigned cfg_mask(int storage, int pm) {
+    const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
+    if (storage == ST_F32) return light ? bits({0, 1, 2, 3}) : bits({0, 1, 2});
+    if (storage == ST_BF16) return light ? bits({0, 1, 2}) : bits({1, 2});
+    return bits({1, 2});
+}
+constexpr unsigned block_mask(int storage, int pm) {
+    const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
+    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2;
+    if (storage == ST_F32) {
+        if (light) return bits({0, 1, 2, 3, 4, 5, 6, 7});
+        if (medium) return bits({0, 1, 2, 5, 6});
+        return bits({0, 2, 5, 6});
+    }
+    if (storage == ST_BF16) {
+        if (pm == PM_DIFF1 || pm == PM_BRUSS) return bits({0, 1, 2, 3, 5});
+        if (pm == PM_CHMU || pm == PM_FRONT) return bits({0, 2, 5, 6});
+        return bits({0, 5});
+    }
+    if (pm == PM_DIFF1 || pm == PM_BRUSS) return bits({0, 1, 5});
+    return bits({0, 5});
+}
 
-// Launch one pass.  kernel: 1 direct, 2 tiled (cfg = kTileCfgs index).
+int tile_cfg_index(int vx, int ry, int w, int pf);   // -1 if no such shape
+int block_cfg_index(int vx, int ry, int w, int cz);  // -1 if no such shape
+
+// Launch one pass.  kernel: 1 direct, 2 tiled (cfg = kTileCfgs index),
+// 3 plane block (cfg = kBlockCfgs index).
 // `h` is the host copy of the arguments (for the launch shape), `d` the same
 // arguments in device memory (what the kernel reads).
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h,
@@ -60,7 +83,7 @@ hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs&
 
 // Batched persistent kernel (tile shape kBatchTile): one step of every table
 // entry whose steps_left > step.
-constexpr TileCfg kBatchTile = {1, 4, 4};
+constexpr TileCfg kBatchTile = {2, 2, 4, 2};
 hipError_t launch_batched(int storage, const BatchTable* tab, int step, int blocks, hipStream_t s);
 int batched_blocks_per_cu(int storage);
 

@@ -39,7 +39,19 @@ template <class M, int I>
 hipError_t run_cfg(const StepArgs* d, long long blocks, hipStream_t s) {
     if constexpr (((cfg_mask(kStorage, PmOf<M>::v) >> I) & 1u) != 0u) {
         constexpr TileCfg c = kTileCfgs[I];
-        hipLaunchKernelGGL((tiled_kernel<M, S, c.vx, c.ry, c.w>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((tiled_kernel<M, S, c.vx, c.ry, c.w, c.pf>), dim3((unsigned)blocks),
+                           dim3(64 * c.w), 0, s, d);
+        return hipGetLastError();
+    } else {
+        return hipErrorNotSupported;
+    }
+}
+
+template <class M, int I>
+hipError_t run_block(const StepArgs* d, long long blocks, hipStream_t s) {
+    if constexpr (((block_mask(kStorage, PmOf<M>::v) >> I) & 1u) != 0u) {
+        constexpr BlockCfg c = kBlockCfgs[I];
+        hipLaunchKernelGGL((block_kernel<M, S, c.vx, c.ry, c.w, c.cz>), dim3((unsigned)blocks),
                            dim3(64 * c.w), 0, s, d);
         return hipGetLastError();
     } else {
@@ -51,16 +63,26 @@ template <class M>
 hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, long long blocks,
                      hipStream_t s) {
     if (kernel == 1) return run_direct<M>(h, d, s);
-    static_assert(kNumTileCfgs == 8, "dispatch below lists every tile shape");
+    if (kernel == 3) {
+        static_assert(kNumBlockCfgs == 8, "dispatch below lists every slab shape");
+        switch (cfg) {
+        case 0: return run_block<M, 0>(d, blocks, s);
+        case 1: return run_block<M, 1>(d, blocks, s);
+        case 2: return run_block<M, 2>(d, blocks, s);
+        case 3: return run_block<M, 3>(d, blocks, s);
+        case 4: return run_block<M, 4>(d, blocks, s);
+        case 5: return run_block<M, 5>(d, blocks, s);
+        case 6: return run_block<M, 6>(d, blocks, s);
+        case 7: return run_block<M, 7>(d, blocks, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    static_assert(kNumTileCfgs == 4, "dispatch below lists every tile shape");
     switch (cfg) {
     case 0: return run_cfg<M, 0>(d, blocks, s);
     case 1: return run_cfg<M, 1>(d, blocks, s);
     case 2: return run_cfg<M, 2>(d, blocks, s);
     case 3: return run_cfg<M, 3>(d, blocks, s);
-    case 4: return run_cfg<M, 4>(d, blocks, s);
-    case 5: return run_cfg<M, 5>(d, blocks, s);
-    case 6: return run_cfg<M, 6>(d, blocks, s);
-    case 7: return run_cfg<M, 7>(d, blocks, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -92,7 +114,7 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 }
 
 #ifdef RD_WITH_BATCH
-#define RD_BATCH_KERNEL batched_kernel<S, kBatchTile.vx, kBatchTile.ry, kBatchTile.w>
+#define RD_BATCH_KERNEL batched_kernel<S, kBatchTile.vx, kBatchTile.ry, kBatchTile.w, kBatchTile.pf>
 hipError_t RD_BATCH_FN(launch_batched)(const BatchTable* tab, int step, int blocks, hipStream_t s) {
     hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchTile.w), 0, s, tab, step);
     return hipGetLastError();

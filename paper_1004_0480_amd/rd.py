@@ -21,7 +21,7 @@ F32, BF16, F16, F64 = 0, 1, 2, 3
 STORAGE = {"f32": F32, "bf16": BF16, "f16": F16}
 MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3}
 BC = {"mirror": 0, "periodic": 1, "ghost": 2, "held": 3}
-KERNEL = {"auto": 0, "direct": 1, "tiled": 2}
+KERNEL = {"auto": 0, "direct": 1, "tiled": 2, "block": 3}
 PARAMS = {
     "diffusion": (),
     "brusselator": ("a", "b"),
@@ -53,7 +53,8 @@ class ModelDesc(C.Structure):
 
 class Plan(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("vx", C.c_int32), ("ry", C.c_int32),
-                ("waves", C.c_int32), ("cz", C.c_int32), ("graph_chunk", C.c_int32)]
+                ("waves", C.c_int32), ("cz", C.c_int32), ("prefetch", C.c_int32),
+                ("graph_chunk", C.c_int32)]
 
     def as_dict(self) -> Dict[str, int]:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -98,6 +99,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("librdmi.so is not built (run __graft_entry__.build()); "
                                "there is no CPU fallback for the HIP path")
+        # torch ships its own HIP runtime under the same soname; load it first
+        # so that this library binds to it and the process has one runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -267,9 +274,9 @@ class Grid:
         _check(lib().rd_chemical_potential(self._p, out.ctypes.data_as(C.POINTER(C.c_float))))
         return out
 
-    def set_plan(self, kernel="auto", vx=0, ry=0, waves=0, cz=0, graph_chunk=0):
+    def set_plan(self, kernel="auto", vx=0, ry=0, waves=0, cz=0, prefetch=0, graph_chunk=0):
         p = Plan(KERNEL[kernel] if isinstance(kernel, str) else int(kernel), vx, ry, waves, cz,
-                 graph_chunk)
+                 prefetch, graph_chunk)
         _check(lib().rd_set_plan(self._p, C.byref(p)))
 
     def plan(self) -> Dict[str, int]:

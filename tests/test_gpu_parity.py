@@ -19,7 +19,11 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-5          # FP32 rel-L2 bound per species against the FP64 oracle
 
-TILE_SHAPES = [(4, 4, 4), (4, 2, 4), (4, 1, 4), (2, 4, 4), (2, 2, 4), (2, 1, 4), (1, 4, 4), (4, 4, 1)]
+# candidate (vx, ry, waves, prefetch) z-march shapes and (vx, ry, waves, cz)
+# slab shapes; the library rejects the ones it did not compile for a model
+TILE_SHAPES = [(4, 2, 4, 1), (4, 1, 4, 2), (2, 2, 4, 2), (1, 4, 4, 2)]
+BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
+                (2, 1, 4, 4), (4, 2, 1, 2)]
 
 
 def rel_l2(a, b):
@@ -45,14 +49,15 @@ def compiled_plans(w, storage="f32", czs=(0, 8)):
     plans = [dict(kernel="direct")]
     g = rd.Grid(w.shape, w.spec.ns, w.spec.h, storage)
     g.set_model(w.spec)
-    for vx, ry, wv in TILE_SHAPES:
-        for cz in czs:
-            p = dict(kernel="tiled", vx=vx, ry=ry, waves=wv, cz=cz)
-            try:
-                g.set_plan(**p)
-            except rd.RDError:
-                continue
-            plans.append(p)
+    cands = [dict(kernel="tiled", vx=vx, ry=ry, waves=wv, cz=cz, prefetch=pf)
+             for vx, ry, wv, pf in TILE_SHAPES for cz in czs]
+    cands += [dict(kernel="block", vx=vx, ry=ry, waves=wv, cz=cz) for vx, ry, wv, cz in BLOCK_SHAPES]
+    for p in cands:
+        try:
+            g.set_plan(**p)
+        except rd.RDError:
+            continue
+        plans.append(p)
     g.close()
     return plans
 
