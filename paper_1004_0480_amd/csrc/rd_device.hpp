@@ -22,6 +22,10 @@ enum { BC_MIRROR = 0, BC_PERIODIC = 1, BC_GHOST = 2, BC_HELD = 3 };
 constexpr int MAXF = 5;          // stencil fields: up to 4 species + mu
 constexpr int SLACK = 1024;      // elements after each buffer: overshoot of the widest tile
 
+#ifndef RD_NT_STORE
+#define RD_NT_STORE 0
+#endif
+
 struct StepArgs {
     int nx, ny, nz;
     int pitch;                    // elements per padded row (multiple of 64)
@@ -101,7 +105,25 @@ __device__ __forceinline__ void store_vec(void* base, long long idx, const float
     Vec<T, VX> r;
 #pragma unroll
     for (int i = 0; i < VX; ++i) r.v[i] = S::down(o[i]);
+#if RD_NT_STORE
+    // streaming store: the next step reads these values from HBM anyway
+    if constexpr (sizeof(r) == 16) {
+        typedef unsigned v4u __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(&r),
+                                    reinterpret_cast<v4u*>(static_cast<T*>(base) + idx));
+    } else if constexpr (sizeof(r) == 8) {
+        typedef unsigned v2u __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(*reinterpret_cast<const v2u*>(&r),
+                                    reinterpret_cast<v2u*>(static_cast<T*>(base) + idx));
+    } else if constexpr (sizeof(r) == 4) {
+        __builtin_nontemporal_store(*reinterpret_cast<const unsigned*>(&r),
+                                    reinterpret_cast<unsigned*>(static_cast<T*>(base) + idx));
+    } else {
+        *reinterpret_cast<Vec<T, VX>*>(static_cast<T*>(base) + idx) = r;
+    }
+#else
     *reinterpret_cast<Vec<T, VX>*>(static_cast<T*>(base) + idx) = r;
+#endif
 }
 
 template <class S>

@@ -35,6 +35,7 @@ struct BlockCfg { int vx, ry, w, cz; };
 constexpr BlockCfg kBlockCfgs[] = {
     {4, 1, 4, 2}, {4, 1, 4, 4}, {4, 2, 4, 2}, {4, 2, 4, 4},
     {4, 1, 4, 8}, {2, 2, 4, 4}, {2, 1, 4, 4}, {4, 2, 1, 2},
+    {4, 1, 1, 2}, {4, 2, 1, 4}, {4, 4, 1, 2}, {4, 2, 2, 2}, {4, 3, 1, 2},
 };
 constexpr int kNumBlockCfgs = sizeof(kBlockCfgs) / sizeof(kBlockCfgs[0]);
 
@@ -58,9 +59,9 @@ constexpr unsigned block_mask(int storage, int pm) {
     const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
     const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2;
     if (storage == ST_F32) {
-        if (light) return bits({0, 1, 2, 3, 4, 5, 6, 7});
-        if (medium) return bits({0, 1, 2, 5, 6});
-        return bits({0, 2, 5, 6});
+        if (light) return bits({0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12});
+        if (medium) return bits({0, 1, 2, 5, 6, 7, 8, 11});
+        return bits({0, 2, 5, 6, 7, 8, 11});
     }
     if (storage == ST_BF16) {
         if (pm == PM_DIFF1 || pm == PM_BRUSS) return bits({0, 1, 2, 3, 5});

@@ -64,7 +64,7 @@ hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, 
                      hipStream_t s) {
     if (kernel == 1) return run_direct<M>(h, d, s);
     if (kernel == 3) {
-        static_assert(kNumBlockCfgs == 8, "dispatch below lists every slab shape");
+        static_assert(kNumBlockCfgs == 13, "dispatch below lists every slab shape");
         switch (cfg) {
         case 0: return run_block<M, 0>(d, blocks, s);
         case 1: return run_block<M, 1>(d, blocks, s);
@@ -74,6 +74,11 @@ hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, 
         case 5: return run_block<M, 5>(d, blocks, s);
         case 6: return run_block<M, 6>(d, blocks, s);
         case 7: return run_block<M, 7>(d, blocks, s);
+        case 8: return run_block<M, 8>(d, blocks, s);
+        case 9: return run_block<M, 9>(d, blocks, s);
+        case 10: return run_block<M, 10>(d, blocks, s);
+        case 11: return run_block<M, 11>(d, blocks, s);
+        case 12: return run_block<M, 12>(d, blocks, s);
         default: return hipErrorInvalidValue;
         }
     }

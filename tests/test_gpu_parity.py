@@ -23,7 +23,8 @@ TOL = 1e-5          # FP32 rel-L2 bound per species against the FP64 oracle
 # slab shapes; the library rejects the ones it did not compile for a model
 TILE_SHAPES = [(4, 2, 4, 1), (4, 1, 4, 2), (2, 2, 4, 2), (1, 4, 4, 2)]
 BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
-                (2, 1, 4, 4), (4, 2, 1, 2)]
+                (2, 1, 4, 4), (4, 2, 1, 2), (4, 1, 1, 2), (4, 2, 1, 4), (4, 4, 1, 2), (4, 2, 2, 2),
+                (4, 3, 1, 2)]
 
 
 def rel_l2(a, b):
