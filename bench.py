@@ -96,14 +96,57 @@ def copy_ceiling(torch, stream, nbytes: int, reps: int = 10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def serve_bench(args):
+    """Served batch: 4096 requests (cubes of 32-128, diffusion or Brusselator,
+    200-2000 steps).  A saturating run (all requests at t=0) measures the
+    capacity; the served run then draws Poisson arrivals at 80% of it."""
+    import torch
+    from paper_1004_0480_amd import serve as S
+    from paper_1004_0480_amd import workloads as W
+    trace = W.make_trace(args.requests, seed=4)
+    out = {"metric": "Gcell-updates/s (served batch)", "unit": "Gcell-updates/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic", "vs_baseline": None, "modes": {}}
+    for storage in (["f32", "bf16"] if args.storage == "both" else [args.storage]):
+        res = {}
+        for phase in ("capacity", "served"):
+            if phase == "capacity":
+                arr = [0.0] * len(trace)
+            else:
+                arr = S.poisson_arrivals(trace, 0.8 * res["capacity"]["requests_per_s"])
+            ex = S.GpuExecutor(storage, max_resident=args.max_resident, hbm_budget=args.hbm_budget)
+            print("bench: serve %s %s (%d requests)" % (storage, phase, len(trace)),
+                  file=sys.stderr, flush=True)
+            rep = S.serve(trace, arr, ex, args.max_resident, args.hbm_budget, args.chunk)
+            ex.close()
+            torch.cuda.synchronize()
+            summ = rep.summary()
+            summ["requests_per_s"] = len(trace) / rep.makespan
+            res[phase] = summ
+            print("bench: %s" % json.dumps(summ), file=sys.stderr, flush=True)
+        out["modes"][storage] = res
+    first = out["modes"][next(iter(out["modes"]))]["served"]
+    out.update({"value": first["gcell_updates_per_s"], "p50_latency_s": first["p50_latency_s"],
+                "p99_latency_s": first["p99_latency_s"], "dtype": next(iter(out["modes"])),
+                "config": {"workload": "served batch", "requests": len(trace),
+                           "edges": list(W.SERVE_EDGES), "steps": [200, 2000],
+                           "max_resident": args.max_resident, "hbm_budget": args.hbm_budget,
+                           "chunk": args.chunk, "arrival_rate": "0.8 x measured capacity"}})
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="brusselator256",
-                    choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64"])
-    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"])
+                    choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64",
+                             "serve"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16", "both"])
+    ap.add_argument("--requests", type=int, default=4096)
+    ap.add_argument("--max-resident", type=int, default=256)
+    ap.add_argument("--hbm-budget", type=int, default=16 << 30)
+    ap.add_argument("--chunk", type=int, default=50)
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -116,6 +159,9 @@ def main():
         sys.exit(2)
     if int(os.environ.get("RANK", "0")) != 0:
         return
+
+    if args.workload == "serve":
+        return serve_bench(args)
 
     import torch
     from paper_1004_0480_amd import rd
@@ -177,7 +223,7 @@ def main():
         "metric": "Gcell-updates/s", "value": value, "unit": "Gcell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
         "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
                    "species": w.spec.ns, "storage": args.storage, "dt": w.spec.dt,
                    "plan": plan, "wall_s": wall},

@@ -985,10 +985,10 @@ struct BatchTable {
     BatchEntry e[1];      // ngrids entries follow
 };
 
-template <class S, int VX, int RY, int W, int PF>
+template <class S, int VX, int RY, int W, int CZ>
 __global__ __launch_bounds__(64 * W) void batched_kernel(const BatchTable* __restrict__ tab, int step) {
-    __shared__ TileLds<Brusselator, W, 64 * VX> smb;
-    __shared__ TileLds<Diffusion<1>, W, 64 * VX> smd;
+    __shared__ BlockLds<Brusselator, W, 64 * VX> smb;
+    __shared__ BlockLds<Diffusion<1>, W, 64 * VX> smd;
     const int total = tab->total_items;
     const int ng = tab->ngrids;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
@@ -1001,8 +1001,8 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(const BatchTable* __res
         if (step >= en.steps_left) continue;     // this grid already finished
         const StepArgs& a = en.args[(en.parity + step) & 1];
         const int t = item - en.first_item;
-        if (en.model == 1) tile_step<Brusselator, S, VX, RY, W, PF>(a, t, smb);
-        else tile_step<Diffusion<1>, S, VX, RY, W, PF>(a, t, smd);
+        if (en.model == 1) block_step<Brusselator, S, VX, RY, W, CZ>(a, t, smb);
+        else block_step<Diffusion<1>, S, VX, RY, W, CZ>(a, t, smd);
     }
 }
 

@@ -1061,16 +1061,15 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     t->ngrids = int(b->members.size());
     long long items = 0;
     rd_plan tile{};
-    tile.kernel = RD_KERNEL_TILED;
-    tile.vx = kBatchTile.vx;
-    tile.ry = kBatchTile.ry;
-    tile.waves = kBatchTile.w;
-    tile.prefetch = kBatchTile.pf;
+    tile.kernel = RD_KERNEL_BLOCK;
+    tile.vx = kBatchBlock.vx;
+    tile.ry = kBatchBlock.ry;
+    tile.waves = kBatchBlock.w;
+    tile.cz = kBatchBlock.cz;
     int64_t max_steps = 0;
     for (size_t i = 0; i < b->members.size(); ++i) {
         const Member& m = b->members[i];
         BatchEntry& e = t->e[i];
-        tile.cz = int(std::min<int64_t>(m.g->nz, 32));
         for (int par = 0; par < 2; ++par) {
             e.args[par] = m.g->args[par][0];
             e.ntiles = int(set_tiling(e.args[par], tile));

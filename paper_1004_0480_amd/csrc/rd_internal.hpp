@@ -82,9 +82,10 @@ int block_cfg_index(int vx, int ry, int w, int cz);  // -1 if no such shape
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h,
                        const StepArgs* d, long long blocks, hipStream_t s);
 
-// Batched persistent kernel (tile shape kBatchTile): one step of every table
+// Batched persistent kernel (slab shape kBatchBlock: 128-cell rows cover the
+// served grid edges of up to 128 cells in one tile): one step of every table
 // entry whose steps_left > step.
-constexpr TileCfg kBatchTile = {2, 2, 4, 2};
+constexpr BlockCfg kBatchBlock = {2, 2, 1, 2};
 hipError_t launch_batched(int storage, const BatchTable* tab, int step, int blocks, hipStream_t s);
 int batched_blocks_per_cu(int storage);
 

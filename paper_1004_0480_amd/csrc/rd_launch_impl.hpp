@@ -119,16 +119,16 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 }
 
 #ifdef RD_WITH_BATCH
-#define RD_BATCH_KERNEL batched_kernel<S, kBatchTile.vx, kBatchTile.ry, kBatchTile.w, kBatchTile.pf>
+#define RD_BATCH_KERNEL batched_kernel<S, kBatchBlock.vx, kBatchBlock.ry, kBatchBlock.w, kBatchBlock.cz>
 hipError_t RD_BATCH_FN(launch_batched)(const BatchTable* tab, int step, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchTile.w), 0, s, tab, step);
+    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchBlock.w), 0, s, tab, step);
     return hipGetLastError();
 }
 
 int RD_BATCH_FN(batched_blocks_per_cu)() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&RD_BATCH_KERNEL),
-                                                     64 * kBatchTile.w, 0) != hipSuccess)
+                                                     64 * kBatchBlock.w, 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }

@@ -262,3 +262,29 @@ def request_workload(req: Request) -> Workload:
     w = make_workload("brusselator256", shape=shape, seed=req.seed, steps=req.steps)
     w.name = "brusselator"
     return w
+
+
+def request_fields_device(req: Request, device="cuda"):
+    """Initial state of a served request generated on the device (torch,
+    float32), seeded by the request: the diffusion64 or brusselator256 initial
+    condition at the request's edge, with the noise drawn by a seeded device
+    generator (a different but equally seeded recipe from the numpy one, used
+    where host generation of thousands of grids would dominate)."""
+    import torch
+    n = req.edge
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(req.seed) & 0x7FFFFFFFFFFFFFFF)
+    if req.model == "diffusion":
+        c = torch.arange(n, device=device, dtype=torch.float32) - (n - 1) / 2.0
+        r2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
+        blob = torch.exp(-r2 / (2.0 * 6.0 * 6.0))
+        return [blob + 1e-3 * torch.rand((n, n, n), generator=gen, device=device)]
+    spec = brusselator_spec()
+    a, b = spec.params["a"], spec.params["b"]
+    xu = torch.rand((n, n, n), generator=gen, device=device) * 0.02 - 0.01
+    xv = torch.rand((n, n, n), generator=gen, device=device) * 0.02 - 0.01
+    return [a * (1.0 + xu), (b / a) * (1.0 + xv)]
+
+
+def request_spec(req: Request) -> ModelSpec:
+    return diffusion_spec() if req.model == "diffusion" else brusselator_spec()
