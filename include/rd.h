@@ -135,6 +135,9 @@ typedef struct rd_plan {
     int32_t cz;           /* TILED: z planes per workgroup, 0 = whole z axis;
                              BLOCK: planes per slab (2, 4 or 8)                */
     int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2) */
+    int32_t order;        /* BLOCK: slab enumeration, 0 = x, then y, then z chunk;
+                             1 = z chunk fastest (z-neighbour slabs run together
+                             on one XCD and share its L2)                       */
     int32_t graph_chunk;  /* rd_step replays hipGraphs of this many steps (even,
                              >= 2); 0 launches every step directly            */
 } rd_plan;

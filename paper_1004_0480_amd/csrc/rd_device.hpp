@@ -45,7 +45,20 @@ struct StepArgs {
     const int* src_sp;            // species of each source
     const float* src_rate;        // emission rate (duplicates merged)
     int tiles_x, tiles_y, chunks_z, cz;   // tiled decomposition
+    int zfast;                    // slab enumeration: z chunk fastest
 };
+
+// Tile coordinates of logical tile t: x, then y, then z chunk, or (zfast) z
+// chunk, then x, then y.
+struct TileXYZ { int x, y, z; };
+__device__ __forceinline__ TileXYZ tile_coords(const StepArgs& a, int t) {
+    if (a.zfast) {
+        const int tz = t % a.chunks_z, r = t / a.chunks_z;
+        return TileXYZ{r % a.tiles_x, r / a.tiles_x, tz};
+    }
+    const int tx = t % a.tiles_x, r = t / a.tiles_x;
+    return TileXYZ{tx, r % a.tiles_y, r / a.tiles_y};
+}
 
 // --------------------------------------------------------------- storage
 
@@ -741,46 +754,58 @@ __global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restric
 // resolved once per slab.  There is no loop-carried window, so the compiler
 // keeps every plane in fixed registers and lets all loads fly together.
 
+// Rows exchanged between the waves of a workgroup, by plane parity: with two
+// waves each exports the one row the other needs (wave 0 its last, wave 1
+// its first); with more, every wave exports its first and last rows.
 template <class M, int W, int TX>
 struct BlockLds {
-    float row[W > 1 ? 2 : 1][M::NF][W > 1 ? W : 1][2][W > 1 ? TX : 1];
+    static constexpr int EXP = W == 2 ? 1 : 2;
+    float row[W > 1 ? 2 : 1][M::NF][W > 1 ? W : 1][EXP][W > 1 ? TX : 1];
 };
 
-template <class M, class S, int VX, int RY, int W, int CZ>
-__device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M, W, 64 * VX>& sm) {
-    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, BY = RY * W, NP = CZ + 2;
-    constexpr int NH = W == 1 ? 2 : 1;      // halo rows a wave loads per plane
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tx = t % a.tiles_x;
-    const int t2 = t / a.tiles_x;
-    const int ty = t2 % a.tiles_y;
-    const int tz = t2 / a.tiles_y;
-    const int x0 = tx * TX;
-    const int yb = ty * BY;
-    const int y0 = yb + w * RY;
-    const int z0 = tz * CZ;
-    const int xl = x0 + lane * VX;
-    const bool whole_row = a.tiles_x == 1;
-    const bool edge_wave = W == 1 || w == 0 || w == W - 1;
-    // halo row h of this wave: W == 1: h=0 above, h=1 below; else above for
-    // wave 0, below for wave W-1.
-    const int hrow0 = (W == 1 || w == 0) ? yb - 1 : yb + BY;
+// Lane l receives v from lane l-1, lane 0 from lane 63: DPP wave_ror:1.
+__device__ __forceinline__ float lane_from_left_wrap(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x13C, 0xF, 0xF,
+                                                      false));
+}
+// Lane l receives v from lane l+1, lane 63 from lane 0: DPP wave_rol:1.
+__device__ __forceinline__ float lane_from_right_wrap(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x134, 0xF, 0xF,
+                                                      false));
+}
 
-    // z-independent row sources and z plane sources, resolved once
-    Src rs[NF][RY], rh[NF][NH], ps[NF][NP];
+// Where the x neighbour outside a lane row comes from, per side of a tile:
+// the loaded edge value (interior side or a wrapped/mirrored edge column),
+// the cell's own value (mirror face), a fixed ghost value, or the lane
+// rotation of a whole periodic row.
+enum { XS_EDGE = 0, XS_OWN = 1, XS_CONST = 2, XS_ROT = 3 };
+
+template <class M, class S, int VX, int RY, int W, int CZ, bool FAST>
+__device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 64 * VX>& sm, int lane, int w,
+                                              int x0, int yb, int y0, int z0, int xl, bool whole_row,
+                                              const Src (&rs)[M::NF][RY], const Src (&rh)[M::NF][W == 1 ? 2 : 1],
+                                              const Src (&ps)[M::NF][CZ + 2]) {
+    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, NP = CZ + 2;
+    constexpr int NH = W == 1 ? 2 : 1;
+    const bool edge_wave = W == 1 || w == 0 || w == W - 1;
+
+    // x sides of this tile, per field
+    int xsl[NF], xsr[NF];
+    bool need_edges = false;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-            rs[f][r] = resolve_axis(y0 + r, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
-#pragma unroll
-        for (int h = 0; h < NH; ++h)
-            rh[f][h] = resolve_axis(h == 0 ? hrow0 : yb + BY, a.ny, a.bck[f][2], a.bck[f][3],
-                                    a.bcv[f][2], a.bcv[f][3]);
-#pragma unroll
-        for (int k = 0; k < NP; ++k)
-            ps[f][k] = resolve_axis(z0 - 1 + k, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+        const int klo = a.bck[f][0], khi = a.bck[f][1];
+        const bool left_face = x0 == 0, right_face = x0 + TX >= a.nx;
+        if (!FAST || whole_row) {
+            // general path (and whole rows): sides from the face rule
+            xsl[f] = klo == BC_MIRROR ? XS_OWN : klo == BC_PERIODIC ? XS_ROT : XS_CONST;
+            xsr[f] = khi == BC_MIRROR ? XS_OWN : khi == BC_PERIODIC ? XS_ROT : XS_CONST;
+        }
+        if (!whole_row) {
+            xsl[f] = !left_face ? XS_EDGE : klo == BC_MIRROR ? XS_OWN : klo == BC_PERIODIC ? XS_EDGE : XS_CONST;
+            xsr[f] = !right_face ? XS_EDGE : khi == BC_MIRROR ? XS_OWN : khi == BC_PERIODIC ? XS_EDGE : XS_CONST;
+        }
+        need_edges = need_edges || xsl[f] == XS_EDGE || xsr[f] == XS_EDGE;
     }
 
     // issue every load of the slab
@@ -805,12 +830,11 @@ __device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M,
                     load_raw<M, S, VX>(a, f, (long long)ps[f][k + 1].idx * a.plane +
                                                  (long long)rh[f][h].idx * a.pitch + xl, H[f][k][h]);
     }
-    int sxi[NF];
-    if (!whole_row) {
+    if (!FAST ? !whole_row : need_edges) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
-            sxi[f] = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]).idx;
+            const int sxi = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]).idx;
 #pragma unroll
             for (int k = 0; k < CZ; ++k)
 #pragma unroll
@@ -818,47 +842,49 @@ __device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M,
                     E[f][k][r] = 0.f;
                     if (lane == 0 || lane == 63) {
                         const long long idx = (long long)ps[f][k + 1].idx * a.plane +
-                                              (long long)rs[f][r].idx * a.pitch + sxi[f];
+                                              (long long)rs[f][r].idx * a.pitch + sxi;
                         E[f][k][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
                     }
                 }
         }
     }
 
-    // boundary rules that replace loaded values (fixed rows/planes, held x faces)
+    if (!FAST) {
+        // boundary rules that replace loaded values (fixed rows/planes, held x faces)
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        bool any = (a.held[f] & 3) != 0;
+        for (int f = 0; f < NF; ++f) {
+            bool any = (a.held[f] & 3) != 0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) any = any || ps[f][k].cst;
+            for (int k = 0; k < NP; ++k) any = any || ps[f][k].cst;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) any = any || rs[f][r].cst;
+            for (int r = 0; r < RY; ++r) any = any || rs[f][r].cst;
 #pragma unroll
-        for (int h = 0; h < NH; ++h) any = any || rh[f][h].cst;
-        if (any) {
+            for (int h = 0; h < NH; ++h) any = any || rh[f][h].cst;
+            if (any) {
 #pragma unroll
-            for (int k = 0; k < NP; ++k)
+                for (int k = 0; k < NP; ++k)
 #pragma unroll
-                for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, ps[f][k], rs[f][r], xl, V[f][k][r]);
-            if (edge_wave) {
+                    for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, ps[f][k], rs[f][r], xl, V[f][k][r]);
+                if (edge_wave) {
+#pragma unroll
+                    for (int k = 0; k < CZ; ++k)
+#pragma unroll
+                        for (int h = 0; h < NH; ++h) fix_row<VX>(a, f, ps[f][k + 1], rh[f][h], xl, H[f][k][h]);
+                }
+            }
+            if (!whole_row) {
+                const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
+                const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
 #pragma unroll
                 for (int k = 0; k < CZ; ++k)
 #pragma unroll
-                    for (int h = 0; h < NH; ++h) fix_row<VX>(a, f, ps[f][k + 1], rh[f][h], xl, H[f][k][h]);
+                    for (int r = 0; r < RY; ++r) {
+                        const Src py = rs[f][r], pz = ps[f][k + 1];
+                        float v = E[f][k][r];
+                        v = py.cst ? py.v : (pz.cst ? pz.v : v);
+                        E[f][k][r] = sx.cst ? sx.v : v;
+                    }
             }
-        }
-        if (!whole_row) {
-            const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
-            const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
-#pragma unroll
-            for (int k = 0; k < CZ; ++k)
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    const Src py = rs[f][r], pz = ps[f][k + 1];
-                    float v = E[f][k][r];
-                    v = py.cst ? py.v : (pz.cst ? pz.v : v);
-                    E[f][k][r] = sx.cst ? sx.v : v;
-                }
         }
     }
 
@@ -869,19 +895,25 @@ __device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M,
             float up[NF][VX], dn[NF][VX];
             if (W > 1) {
                 const int par = k & 1;
+                constexpr int EXP = BlockLds<M, W, TX>::EXP;
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
 #pragma unroll
                     for (int i = 0; i < VX; ++i) {
-                        sm.row[par][f][w][0][lane * VX + i] = V[f][k][0][i];
-                        sm.row[par][f][w][1][lane * VX + i] = V[f][k][RY - 1][i];
+                        if (EXP == 1) {
+                            sm.row[par][f][w][0][lane * VX + i] = w == 0 ? V[f][k][RY - 1][i] : V[f][k][0][i];
+                        } else {
+                            sm.row[par][f][w][0][lane * VX + i] = V[f][k][0][i];
+                            sm.row[par][f][w][EXP - 1][lane * VX + i] = V[f][k][RY - 1][i];
+                        }
                     }
                 __syncthreads();
 #pragma unroll
                 for (int f = 0; f < NF; ++f)
 #pragma unroll
                     for (int i = 0; i < VX; ++i) {
-                        up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][1][lane * VX + i] : H[f][k - 1][0][i];
+                        up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][EXP - 1][lane * VX + i]
+                                         : H[f][k - 1][0][i];
                         dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i]
                                              : H[f][k - 1][0][i];
                     }
@@ -901,26 +933,46 @@ __device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M,
                 Nb n[NF][VX];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    float L, R;
-                    if (whole_row) {
-                        const int klo = a.bck[f][0], khi = a.bck[f][1];
-                        const float first = bcast_lane(V[f][k][r][0], 0);
-                        const float last = row_element<VX>(V[f][k][r], a.nx - 1);
-                        L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
-                        R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
+                    const float (&v)[VX] = V[f][k][r];
+                    float left, right, R = 0.f;
+                    if (FAST) {
+                        // fill value of lane 0 (left) / lane 63 (right): no lane reads
+                        if (xsl[f] == XS_ROT) {
+                            left = lane_from_left_wrap(v[VX - 1]);
+                        } else {
+                            const float fl = xsl[f] == XS_OWN ? v[0] : xsl[f] == XS_CONST ? a.bcv[f][0]
+                                                                                          : E[f][k - 1][r];
+                            left = lane_from_left(v[VX - 1], fl);
+                        }
+                        if (xsr[f] == XS_ROT) {
+                            right = lane_from_right_wrap(v[0]);
+                        } else {
+                            const float fr = xsr[f] == XS_OWN ? v[VX - 1] : xsr[f] == XS_CONST ? a.bcv[f][1]
+                                                                                               : E[f][k - 1][r];
+                            right = lane_from_right(v[0], fr);
+                        }
                     } else {
-                        L = bcast_lane(E[f][k - 1][r], 0);
-                        R = bcast_lane(E[f][k - 1][r], 63);
+                        float L;
+                        if (whole_row) {
+                            const int klo = a.bck[f][0], khi = a.bck[f][1];
+                            const float first = bcast_lane(v[0], 0);
+                            const float last = row_element<VX>(v, a.nx - 1);
+                            L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
+                            R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
+                        } else {
+                            L = bcast_lane(E[f][k - 1][r], 0);
+                            R = bcast_lane(E[f][k - 1][r], 63);
+                        }
+                        left = lane_from_left(v[VX - 1], L);
+                        right = lane_from_right(v[0], R);
                     }
-                    const float left = lane_from_left(V[f][k][r][VX - 1], L);
-                    const float right = lane_from_right(V[f][k][r][0], R);
 #pragma unroll
                     for (int i = 0; i < VX; ++i) {
                         Nb& q = n[f][i];
-                        q.c = V[f][k][r][i];
-                        q.xm = i > 0 ? V[f][k][r][i - 1] : left;
-                        q.xp = i < VX - 1 ? V[f][k][r][i + 1] : right;
-                        if (xl + i == a.nx - 1) q.xp = R;
+                        q.c = v[i];
+                        q.xm = i > 0 ? v[i - 1] : left;
+                        q.xp = i < VX - 1 ? v[i + 1] : right;
+                        if (!FAST && xl + i == a.nx - 1) q.xp = R;
                         q.ym = r > 0 ? V[f][k][r - 1][i] : up[f][i];
                         q.yp = r < RY - 1 ? V[f][k][r + 1][i] : dn[f][i];
                         q.zm = V[f][k - 1][r][i];
@@ -943,7 +995,7 @@ __device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M,
                     float oi[NO];
                     M::cell(a, ni, uh, em.any, em.e, oi);
 #pragma unroll
-                    for (int s = 0; s < NO; ++s) o[s][i] = held_out(a, s, xl + i, y, z, oi[s]);
+                    for (int s = 0; s < NO; ++s) o[s][i] = FAST ? oi[s] : held_out(a, s, xl + i, y, z, oi[s]);
                 }
                 if (y < a.ny && xl < a.nx) {
                     const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
@@ -956,6 +1008,75 @@ __device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M,
             }
         }
     }
+}
+
+template <class M, class S, int VX, int RY, int W, int CZ>
+__device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M, W, 64 * VX>& sm) {
+    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, BY = RY * W, NP = CZ + 2;
+    constexpr int NH = W == 1 ? 2 : 1;      // halo rows a wave loads per plane
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TileXYZ tc = tile_coords(a, t);
+    const int x0 = tc.x * TX;
+    const int yb = tc.y * BY;
+    const int y0 = yb + w * RY;
+    const int z0 = tc.z * CZ;
+    const int xl = x0 + lane * VX;
+    const bool whole_row = a.tiles_x == 1;
+    // halo row h of this wave: W == 1: h=0 above, h=1 below; else above for
+    // wave 0, below for wave W-1.
+    const int hrow0 = (W == 1 || w == 0) ? yb - 1 : yb + BY;
+
+    // z-independent row sources and z plane sources, resolved once per slab.
+    // A slab two or more cells inside every y and z face reads only its own
+    // rows and planes: no rule applies there.
+    Src rs[NF][RY], rh[NF][NH], ps[NF][NP];
+    bool fast = a.nx % TX == 0;
+    const bool inside = yb >= 2 && yb + BY <= a.ny - 2 && z0 >= 2 && z0 + CZ <= a.nz - 2;
+    if (inside) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int r = 0; r < RY; ++r) rs[f][r] = Src{y0 + r, 0, 0.f};
+#pragma unroll
+            for (int h = 0; h < NH; ++h) rh[f][h] = Src{h == 0 ? hrow0 : yb + BY, 0, 0.f};
+#pragma unroll
+            for (int k = 0; k < NP; ++k) ps[f][k] = Src{z0 - 1 + k, 0, 0.f};
+            fast = fast && (a.held[f] & 3) == 0;
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                rs[f][r] = resolve_axis(y0 + r, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
+                fast = fast && !rs[f][r].cst;
+            }
+#pragma unroll
+            for (int h = 0; h < NH; ++h) {
+                rh[f][h] = resolve_axis(h == 0 ? hrow0 : yb + BY, a.ny, a.bck[f][2], a.bck[f][3],
+                                        a.bcv[f][2], a.bcv[f][3]);
+                fast = fast && !rh[f][h].cst;
+            }
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                ps[f][k] = resolve_axis(z0 - 1 + k, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+                fast = fast && !ps[f][k].cst;
+            }
+            fast = fast && (a.held[f] & 3) == 0;
+        }
+    }
+    // outputs on a held face of this slab need the held value
+#pragma unroll
+    for (int s = 0; s < NO; ++s) {
+        const int hm = a.out_held[s];
+        const bool touches = ((hm & 1) && x0 == 0) || ((hm & 2) && x0 + TX >= a.nx) ||
+                             ((hm & 4) && yb == 0) || ((hm & 8) && yb + BY >= a.ny) ||
+                             ((hm & 16) && z0 == 0) || ((hm & 32) && z0 + CZ >= a.nz);
+        fast = fast && !touches;
+    }
+    if (fast) block_compute<M, S, VX, RY, W, CZ, true>(a, sm, lane, w, x0, yb, y0, z0, xl, whole_row, rs, rh, ps);
+    else block_compute<M, S, VX, RY, W, CZ, false>(a, sm, lane, w, x0, yb, y0, z0, xl, whole_row, rs, rh, ps);
     if (W > 1) __syncthreads();   // the LDS rows may be reused by the next slab
 }
 
@@ -966,41 +1087,46 @@ __global__ __launch_bounds__(64 * W) void block_kernel(const StepArgs* __restric
 }
 
 // ------------------------------------------------------------ batched kernel
-// A persistent launch walks (grid, tile) work items of many grids.  Grid g's
-// step arguments for both time-level parities sit in a device table; item
-// ranges are prefix sums over grids.
+// A persistent launch walks the (grid, slab) work items of many grids.  The
+// host writes, before each tick, `meta` = {ngrids, total_items, first_item[0..
+// ngrids]} and one entry per grid (its step arguments for both parities,
+// model, parity of the current state, steps left).  Every workgroup takes a
+// contiguous run of items, so it locates its first grid once and then walks
+// forward; consecutive items are neighbouring slabs of the same grid.
 
 struct BatchEntry {
     StepArgs args[2];     // by input parity
     int model;            // 0 diffusion (1 species), 1 Brusselator
     int ntiles;
-    int first_item;       // prefix sum of ntiles
-    int parity;           // parity of the current state at chunk start
-    long long steps_left; // at chunk start
-};
-
-struct BatchTable {
-    int ngrids;
-    int total_items;
-    BatchEntry e[1];      // ngrids entries follow
+    int first_item;
+    int parity;           // parity of the current state at tick start
+    long long steps_left; // at tick start
 };
 
 template <class S, int VX, int RY, int W, int CZ>
-__global__ __launch_bounds__(64 * W) void batched_kernel(const BatchTable* __restrict__ tab, int step) {
+__global__ __launch_bounds__(64 * W) void batched_kernel(const int* __restrict__ meta,
+                                                          const BatchEntry* __restrict__ ents, int step) {
     __shared__ BlockLds<Brusselator, W, 64 * VX> smb;
     __shared__ BlockLds<Diffusion<1>, W, 64 * VX> smd;
-    const int total = tab->total_items;
-    const int ng = tab->ngrids;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int lo = 0, hi = ng - 1;                 // last grid with first_item <= item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tab->e[mid].first_item <= item) lo = mid; else hi = mid - 1;
-        }
-        const BatchEntry& en = tab->e[lo];
+    const int ng = meta[0];
+    const int total = meta[1];
+    const int* first = meta + 2;
+    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+    int item = (int)blockIdx.x * per;
+    const int end = min(total, item + per);
+    if (item >= end) return;
+    int lo = 0, hi = ng - 1;                     // last grid with first_item <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    int g = lo;
+    for (; item < end; ++item) {
+        while (g + 1 < ng && first[g + 1] <= item) ++g;
+        const BatchEntry& en = ents[g];
         if (step >= en.steps_left) continue;     // this grid already finished
         const StepArgs& a = en.args[(en.parity + step) & 1];
-        const int t = item - en.first_item;
+        const int t = item - first[g];
         if (en.model == 1) block_step<Brusselator, S, VX, RY, W, CZ>(a, t, smb);
         else block_step<Diffusion<1>, S, VX, RY, W, CZ>(a, t, smd);
     }

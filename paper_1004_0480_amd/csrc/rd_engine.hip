@@ -104,11 +104,12 @@ hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs&
     }
 }
 
-hipError_t launch_batched(int storage, const BatchTable* tab, int step, int blocks, hipStream_t s) {
+hipError_t launch_batched(int storage, const int* meta, const BatchEntry* ents, int step, int blocks,
+                          hipStream_t s) {
     switch (storage) {
-    case ST_F32: return launch_batched_f32(tab, step, blocks, s);
-    case ST_BF16: return launch_batched_bf16(tab, step, blocks, s);
-    case ST_F16: return launch_batched_f16(tab, step, blocks, s);
+    case ST_F32: return launch_batched_f32(meta, ents, step, blocks, s);
+    case ST_BF16: return launch_batched_bf16(meta, ents, step, blocks, s);
+    case ST_F16: return launch_batched_f16(meta, ents, step, blocks, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -209,6 +210,7 @@ long long set_tiling(StepArgs& a, const rd_plan& p) {
     a.tiles_y = (a.ny + by - 1) / by;
     a.cz = cz;
     a.chunks_z = (a.nz + cz - 1) / cz;
+    a.zfast = p.kernel == RD_KERNEL_BLOCK && p.order == 1;
     return (long long)a.tiles_x * a.tiles_y * a.chunks_z;
 }
 
@@ -259,6 +261,7 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
         *cfg_out = -1;
         return RD_OK;
     }
+    if (p.order < 0 || p.order > 1) return fail(RD_EINVAL, "order must be 0 or 1");
     if (p.kernel == RD_KERNEL_BLOCK) {
         const int cfg = block_cfg_index(p.vx, p.ry, p.waves, p.cz);
         if (cfg < 0) return fail(RD_EINVAL, "slab shape not available");
@@ -884,6 +887,8 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
         p.waves = c.w;
         p.cz = c.cz;
         cands.push_back(p);
+        p.order = 1;
+        cands.push_back(p);
     }
     hipEvent_t e0, e1;
     RD_HIP(hipEventCreate(&e0));
@@ -954,7 +959,7 @@ struct rd_batch {
     hipStream_t stream = nullptr;
     std::vector<Member> members;
     size_t bytes = 0;
-    BatchTable* d_tab = nullptr;
+    char* d_tab = nullptr;         // meta ints, then entries (at entries_off)
     char* h_tab = nullptr;         // pinned staging of the table
     size_t tab_bytes = 0;
     hipEvent_t tab_done = nullptr;
@@ -964,7 +969,10 @@ struct rd_batch {
 };
 
 namespace {
-size_t table_bytes(int n) { return offsetof(BatchTable, e) + size_t(std::max(n, 1)) * sizeof(BatchEntry); }
+// device table: {ngrids, total_items, first_item[max_grids + 1]} padded to
+// 256 bytes, then max_grids entries
+size_t meta_bytes(int max_grids) { return (size_t(max_grids + 3) * sizeof(int) + 255) / 256 * 256; }
+size_t table_bytes(int max_grids, int n) { return meta_bytes(max_grids) + size_t(std::max(n, 1)) * sizeof(BatchEntry); }
 }
 
 extern "C" int rd_batch_create(int32_t max_grids, size_t hbm_budget_bytes, int32_t storage_dtype,
@@ -979,8 +987,8 @@ extern "C" int rd_batch_create(int32_t max_grids, size_t hbm_budget_bytes, int32
     b->budget = hbm_budget_bytes;
     b->storage = storage_dtype;
     b->stream = static_cast<hipStream_t>(hip_stream);
-    b->tab_bytes = table_bytes(max_grids);
-    if (hipMalloc(&b->d_tab, b->tab_bytes) != hipSuccess ||
+    b->tab_bytes = table_bytes(max_grids, max_grids);
+    if (hipMalloc(reinterpret_cast<void**>(&b->d_tab), b->tab_bytes) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&b->h_tab), b->tab_bytes, hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&b->tab_done, hipEventDisableTiming) != hipSuccess) {
         rd_batch_destroy(b);
@@ -1055,10 +1063,12 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
         RD_HIP(hipEventSynchronize(b->tab_done));
         b->tab_pending = false;
     }
-    // Work list: every member's tiles, with its arguments for both parities.
-    BatchTable* t = reinterpret_cast<BatchTable*>(b->h_tab);
-    std::memset(b->h_tab, 0, table_bytes(int(b->members.size())));
-    t->ngrids = int(b->members.size());
+    // Work list: every member's slabs, with its arguments for both parities.
+    const int ng = int(b->members.size());
+    const size_t moff = meta_bytes(b->max_grids);
+    int* meta = reinterpret_cast<int*>(b->h_tab);
+    BatchEntry* ents = reinterpret_cast<BatchEntry*>(b->h_tab + moff);
+    std::memset(b->h_tab, 0, table_bytes(b->max_grids, ng));
     long long items = 0;
     rd_plan tile{};
     tile.kernel = RD_KERNEL_BLOCK;
@@ -1067,23 +1077,28 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     tile.waves = kBatchBlock.w;
     tile.cz = kBatchBlock.cz;
     int64_t max_steps = 0;
-    for (size_t i = 0; i < b->members.size(); ++i) {
+    for (int i = 0; i < ng; ++i) {
         const Member& m = b->members[i];
-        BatchEntry& e = t->e[i];
+        BatchEntry& e = ents[i];
         for (int par = 0; par < 2; ++par) {
             e.args[par] = m.g->args[par][0];
             e.ntiles = int(set_tiling(e.args[par], tile));
         }
         e.model = m.g->model == RD_MODEL_BRUSSELATOR ? 1 : 0;
         e.first_item = int(items);
+        meta[2 + i] = int(items);
         e.parity = m.g->cur;
         e.steps_left = m.steps_left;
         items += e.ntiles;
         max_steps = std::max(max_steps, m.steps_left);
     }
     if (items > 0x7fffffffLL) return fail(RD_EINVAL, "batch work list too long");
-    t->total_items = int(items);
-    RD_HIP(hipMemcpyAsync(b->d_tab, b->h_tab, table_bytes(t->ngrids), hipMemcpyHostToDevice, b->stream));
+    meta[0] = ng;
+    meta[1] = int(items);
+    meta[2 + ng] = int(items);
+    RD_HIP(hipMemcpyAsync(b->d_tab, b->h_tab, moff, hipMemcpyHostToDevice, b->stream));
+    RD_HIP(hipMemcpyAsync(b->d_tab + moff, b->h_tab + moff, size_t(ng) * sizeof(BatchEntry),
+                          hipMemcpyHostToDevice, b->stream));
     RD_HIP(hipEventRecord(b->tab_done, b->stream));
     b->tab_pending = true;
     const int64_t run = std::min(chunk, max_steps);
@@ -1093,7 +1108,9 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
             RD_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             hipError_t le = hipSuccess;
             for (int64_t i = 0; i < run && le == hipSuccess; ++i)
-                le = launch_batched(b->storage, b->d_tab, int(i), b->blocks, b->stream);
+                le = launch_batched(b->storage, reinterpret_cast<const int*>(b->d_tab),
+                                    reinterpret_cast<const BatchEntry*>(b->d_tab + meta_bytes(b->max_grids)),
+                                    int(i), b->blocks, b->stream);
             hipGraph_t graph = nullptr;
             const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
             if (le != hipSuccess || ce != hipSuccess) {
@@ -1109,7 +1126,9 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
         RD_HIP(hipGraphLaunch(it->second, b->stream));
     } else {
         for (int64_t i = 0; i < run; ++i) {
-            const hipError_t le = launch_batched(b->storage, b->d_tab, int(i), b->blocks, b->stream);
+            const hipError_t le = launch_batched(b->storage, reinterpret_cast<const int*>(b->d_tab),
+                                                 reinterpret_cast<const BatchEntry*>(b->d_tab + meta_bytes(b->max_grids)),
+                                                 int(i), b->blocks, b->stream);
             if (le != hipSuccess) return fail(RD_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));
         }
     }

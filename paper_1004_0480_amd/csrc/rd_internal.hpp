@@ -86,7 +86,8 @@ hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs&
 // served grid edges of up to 128 cells in one tile): one step of every table
 // entry whose steps_left > step.
 constexpr BlockCfg kBatchBlock = {2, 2, 1, 2};
-hipError_t launch_batched(int storage, const BatchTable* tab, int step, int blocks, hipStream_t s);
+hipError_t launch_batched(int storage, const int* meta, const BatchEntry* ents, int step, int blocks,
+                          hipStream_t s);
 int batched_blocks_per_cu(int storage);
 
 // Per storage and model group (one translation unit each); return
@@ -105,9 +106,9 @@ RD_DECLARE_GROUP(f16_react)
 RD_DECLARE_GROUP(f16_poll)
 #undef RD_DECLARE_GROUP
 
-hipError_t launch_batched_f32(const BatchTable* tab, int step, int blocks, hipStream_t s);
-hipError_t launch_batched_bf16(const BatchTable* tab, int step, int blocks, hipStream_t s);
-hipError_t launch_batched_f16(const BatchTable* tab, int step, int blocks, hipStream_t s);
+hipError_t launch_batched_f32(const int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
+hipError_t launch_batched_bf16(const int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
+hipError_t launch_batched_f16(const int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
 int batched_blocks_per_cu_f32();
 int batched_blocks_per_cu_bf16();
 int batched_blocks_per_cu_f16();

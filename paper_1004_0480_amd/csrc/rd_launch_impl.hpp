@@ -120,8 +120,9 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 
 #ifdef RD_WITH_BATCH
 #define RD_BATCH_KERNEL batched_kernel<S, kBatchBlock.vx, kBatchBlock.ry, kBatchBlock.w, kBatchBlock.cz>
-hipError_t RD_BATCH_FN(launch_batched)(const BatchTable* tab, int step, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchBlock.w), 0, s, tab, step);
+hipError_t RD_BATCH_FN(launch_batched)(const int* meta, const BatchEntry* ents, int step, int blocks,
+                                       hipStream_t s) {
+    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchBlock.w), 0, s, meta, ents, step);
     return hipGetLastError();
 }
 

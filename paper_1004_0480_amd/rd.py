@@ -54,7 +54,7 @@ class ModelDesc(C.Structure):
 class Plan(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("vx", C.c_int32), ("ry", C.c_int32),
                 ("waves", C.c_int32), ("cz", C.c_int32), ("prefetch", C.c_int32),
-                ("graph_chunk", C.c_int32)]
+                ("order", C.c_int32), ("graph_chunk", C.c_int32)]
 
     def as_dict(self) -> Dict[str, int]:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -226,6 +226,10 @@ class Grid:
                   "torch.float16": F16}[str(src.dtype)]
             if not src.is_contiguous() or tuple(src.shape) != self.shape:
                 raise ValueError("device source must be contiguous with shape (nz, ny, nx)")
+            # the library reads the tensor on the grid's stream: let the stream
+            # that produced it finish first
+            import torch
+            torch.cuda.current_stream(src.device).synchronize()
             _check(lib().rd_write_field(self._p, species, C.c_void_p(src.data_ptr()), dt, 1))
             return
         a = np.asarray(src)
@@ -248,7 +252,12 @@ class Grid:
         return out
 
     def read_device(self, species: int, dst) -> None:
-        """Copy one species into a contiguous float32 CUDA tensor (nz, ny, nx)."""
+        """Copy one species into a contiguous float32 CUDA tensor (nz, ny, nx)
+        (synchronous: the tensor is ready for any stream on return)."""
+        import torch
+        if str(dst.dtype) != "torch.float32" or not dst.is_contiguous() or tuple(dst.shape) != self.shape:
+            raise ValueError("destination must be a contiguous float32 tensor of shape (nz, ny, nx)")
+        torch.cuda.current_stream(dst.device).synchronize()
         _check(lib().rd_read_field(self._p, species, C.c_void_p(dst.data_ptr()), F32, 1))
 
     def read_all(self, dtype=np.float64) -> List[np.ndarray]:
@@ -274,9 +283,9 @@ class Grid:
         _check(lib().rd_chemical_potential(self._p, out.ctypes.data_as(C.POINTER(C.c_float))))
         return out
 
-    def set_plan(self, kernel="auto", vx=0, ry=0, waves=0, cz=0, prefetch=0, graph_chunk=0):
+    def set_plan(self, kernel="auto", vx=0, ry=0, waves=0, cz=0, prefetch=0, order=0, graph_chunk=0):
         p = Plan(KERNEL[kernel] if isinstance(kernel, str) else int(kernel), vx, ry, waves, cz,
-                 prefetch, graph_chunk)
+                 prefetch, order, graph_chunk)
         _check(lib().rd_set_plan(self._p, C.byref(p)))
 
     def plan(self) -> Dict[str, int]:

@@ -235,8 +235,10 @@ class GpuExecutor:
             g = self.rd.Grid((req.edge,) * 3, 2 if req.model == "brusselator" else 1, 1.0,
                              self.storage, stream=self.stream)
             g.set_model(self.W.request_spec(req))
-        for s, f in enumerate(self.W.request_fields_device(req)):
-            g.write(s, f)
+        with self.torch.cuda.stream(self.stream):      # same stream as the grid's copies
+            fields = self.W.request_fields_device(req)
+            for s, f in enumerate(fields):
+                g.write(s, f)
         self.batch.add(g, int(req.steps))
         h = g.handle.value
         self.by_handle[h] = key

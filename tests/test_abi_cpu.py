@@ -33,7 +33,7 @@ def test_model_desc_layout_matches_header():
     # int32 model, int32 nspecies, double dt, 4x3 double, 4x6 int32, 4x6 double,
     # 8 double, ptr, int64, int64, ptr, ptr, ptr
     assert C.sizeof(rd.ModelDesc) == 4 + 4 + 8 + 96 + 96 + 192 + 64 + 8 + 8 + 8 + 8 + 8 + 8
-    assert C.sizeof(rd.Plan) == 28
+    assert C.sizeof(rd.Plan) == 32
 
 
 @pytest.mark.parametrize("args", [

@@ -52,7 +52,8 @@ def compiled_plans(w, storage="f32", czs=(0, 8)):
     g.set_model(w.spec)
     cands = [dict(kernel="tiled", vx=vx, ry=ry, waves=wv, cz=cz, prefetch=pf)
              for vx, ry, wv, pf in TILE_SHAPES for cz in czs]
-    cands += [dict(kernel="block", vx=vx, ry=ry, waves=wv, cz=cz) for vx, ry, wv, cz in BLOCK_SHAPES]
+    cands += [dict(kernel="block", vx=vx, ry=ry, waves=wv, cz=cz, order=o)
+              for vx, ry, wv, cz in BLOCK_SHAPES for o in (0, 1)]
     for p in cands:
         try:
             g.set_plan(**p)
@@ -415,3 +416,74 @@ def test_batch_budget_and_validation():
     b.close()
     g1.close()
     g2.close()
+
+
+# ------------------------------------------------ full sizes, bench plans
+
+@pytest.mark.parametrize("name,steps", [("front384", 3), ("pollutant512", 4), ("diffusion512", 4)])
+def test_full_size_autotuned_plan_parity(name, steps):
+    """The full configured grid in the autotuned plan the benchmark uses,
+    against the whole-grid FP64 oracle for a few steps."""
+    w = W.make_workload(name)
+    g = rd.Grid.from_workload(w)
+    g.autotune(2)
+    g.step(steps)
+    plan = g.plan()
+    got = g.read_all()
+    g.close()
+    ref = oracle.run(w.spec, w.fields, steps)
+    for s in range(w.spec.ns):
+        e = rel_l2(got[s], ref[s])
+        print("%s full size %d steps species %d: rel-L2 %.3e plan %s" % (name, steps, s, e, plan))
+        assert e <= TOL
+        ref[s] = None
+
+
+def test_front_full_size_long_run_invariants():
+    """front384 at full size for 400 steps: fields stay finite and sum(B+C)
+    drifts only by FP32 rounding."""
+    w = W.make_workload("front384")
+    g = rd.Grid.from_workload(w)
+    g.autotune(2)
+    m0 = g.reduce(1)[0] + g.reduce(2)[0]
+    g.step(400)
+    m1 = g.reduce(1)[0] + g.reduce(2)[0]
+    for s in range(3):
+        g.reduce(s)                       # raises on NaN / Inf
+    g.close()
+    drift = abs(m1 - m0) / abs(m0)
+    print("front384 full size, 400 steps: sum(B+C) relative drift %.3e" % drift)
+    assert drift < 1e-5
+
+
+def test_pollutant_full_size_mass_budget():
+    """pollutant512 at full size, one step in the autotuned plan: the change of
+    each species' total obeys the exact discrete budget (sources, decay,
+    outflow through x+, diffusive loss at the clean-inflow face, A->B)."""
+    w = W.make_workload("pollutant512")
+    rng = np.random.default_rng(21)
+    fields = [rng.uniform(0, 1, w.shape).astype(np.float32).astype(np.float64) for _ in range(4)]
+    g = rd.Grid(w.shape, 4, 1.0)
+    g.set_model(w.spec)
+    g.autotune(2)
+    for s in range(4):
+        g.write(s, fields[s])
+    before = [g.reduce(s)[0] for s in range(4)]
+    g.step(1)
+    after = [g.reduce(s)[0] for s in range(4)]
+    g.close()
+    spec = w.spec
+    dt, lam, kab = spec.dt, spec.params["decay"], spec.params["kab"]
+    u = spec.wind[:, None]
+    for s in range(4):
+        c = fields[s]
+        flux = np.sum(-u * c[:, :, -1]) - spec.K[s][0] * np.sum(c[:, :, 0])
+        e = sum(r for cell, sp, r in zip(*spec.sources) if sp == s)
+        change = flux - lam * np.sum(c) + e
+        if s == 0:
+            change -= kab * np.sum(fields[0])
+        if s == 1:
+            change += kab * np.sum(fields[0])
+        got = after[s] - before[s]
+        # FP32 rounding of 33.5 M updates of size ~1: allow 1e-6 of the total
+        assert abs(got - dt * change) <= 1e-6 * before[s], (s, got, dt * change)
