@@ -254,8 +254,12 @@ template <int NS> struct Pollutant {
 
 // ------------------------------------------------------------ ghost logic
 
-// The value one cell beyond index 0 / n-1 comes from (idx, constant?) by the
-// face rule; an in-range index on a held face reads the held value.
+// The value one cell beyond index 0 / n-1 comes from (idx, rule, value) by
+// the face rule; an in-range index on a held face reads the held value.
+// cst: 0 = load from idx, 1 = held layer, 2 = fixed ghost beyond the face.
+// A ghost beyond a face takes that face's rule before any held layer of
+// another axis; held layers go by x-, x+, y-, y+, z-, z+.
+enum { CST_NONE = 0, CST_HELD = 1, CST_GHOST = 2 };
 struct Src { int idx; int cst; float v; };
 
 __device__ __forceinline__ Src resolve_axis(int q, int n, int klo, int khi, float vlo, float vhi) {
@@ -265,51 +269,34 @@ __device__ __forceinline__ Src resolve_axis(int q, int n, int klo, int khi, floa
     int idx = q;
     idx = lo ? (klo == BC_PERIODIC ? n - 1 : 0) : idx;
     idx = hi ? ((q > n || khi != BC_PERIODIC) ? n - 1 : 0) : idx;   // beyond the ghost: unused
-    bool cst = (lo && fixed_lo) || (hi && q == n && fixed_hi);
+    const bool ghost = (lo && fixed_lo) || (hi && q == n && fixed_hi);
     float v = lo ? vlo : vhi;
     // a resolved in-range index on a held face reads the held value (lo first)
-    const bool hlo = !cst && idx == 0 && klo == BC_HELD;
-    const bool hhi = !cst && !hlo && idx == n - 1 && khi == BC_HELD;
+    const bool hlo = !ghost && idx == 0 && klo == BC_HELD;
+    const bool hhi = !ghost && !hlo && idx == n - 1 && khi == BC_HELD;
     v = hlo ? vlo : (hhi ? vhi : v);
-    cst = cst || hlo || hhi;
-    return Src{idx, cst ? 1 : 0, v};
+    return Src{idx, ghost ? CST_GHOST : (hlo || hhi) ? CST_HELD : CST_NONE, v};
 }
 
-// Value of field f at in-range (x, y, z) with held layers applied
-// (a cell on several held faces takes the first in x-, x+, y-, y+, z-, z+).
-template <class S>
-__device__ __forceinline__ float cell_value(const StepArgs& a, int f, int x, int y, int z) {
-    const int hm = a.held[f];
-    if (hm) {
-        if ((hm & 1) && x == 0) return a.bcv[f][0];
-        if ((hm & 2) && x == a.nx - 1) return a.bcv[f][1];
-        if ((hm & 4) && y == 0) return a.bcv[f][2];
-        if ((hm & 8) && y == a.ny - 1) return a.bcv[f][3];
-        if ((hm & 16) && z == 0) return a.bcv[f][4];
-        if ((hm & 32) && z == a.nz - 1) return a.bcv[f][5];
-    }
-    return load1<S>(a.in[f], (long long)z * a.plane + (long long)y * a.pitch + x);
+// Value at a point whose three axes resolved to sx, sy, sz (at most one of
+// them from outside the grid), given the value v loaded from the resolved
+// address.
+__device__ __forceinline__ float fixed_or(const Src& sx, const Src& sy, const Src& sz, float v) {
+    return sx.cst == CST_GHOST ? sx.v : sy.cst == CST_GHOST ? sy.v : sz.cst == CST_GHOST ? sz.v
+         : sx.cst ? sx.v : sy.cst ? sy.v : sz.cst ? sz.v : v;
 }
 
-// Neighbour of in-range (x,y,z) one step along `axis` in direction `dir`.
+// Value of field f at (x, y, z), where a coordinate may lie one cell outside
+// the grid: each axis is resolved by its face rules, one load is made from
+// the resolved (always valid) address, and a value fixed by a rule replaces
+// it.  Written as value selects so that no address depends on the rules.
 template <class S>
-__device__ __forceinline__ float neighbour(const StepArgs& a, int f, int x, int y, int z,
-                                           int axis, int dir) {
-    int q[3] = {x, y, z};
-    const int n[3] = {a.nx, a.ny, a.nz};
-    const int p = q[axis] + dir;
-    if (p >= 0 && p < n[axis]) {
-        q[axis] = p;
-        return cell_value<S>(a, f, q[0], q[1], q[2]);
-    }
-    const int face = 2 * axis + (dir > 0 ? 1 : 0);
-    const int kind = a.bck[f][face];
-    if (kind == BC_MIRROR) return cell_value<S>(a, f, x, y, z);
-    if (kind == BC_PERIODIC) {
-        q[axis] = dir > 0 ? 0 : n[axis] - 1;
-        return cell_value<S>(a, f, q[0], q[1], q[2]);
-    }
-    return a.bcv[f][face];
+__device__ __forceinline__ float stencil_value(const StepArgs& a, int f, int x, int y, int z) {
+    const Src sx = resolve_axis(x, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
+    const Src sy = resolve_axis(y, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
+    const Src sz = resolve_axis(z, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+    const float v = load1<S>(a.in[f], (long long)sz.idx * a.plane + (long long)sy.idx * a.pitch + sx.idx);
+    return fixed_or(sx, sy, sz, v);
 }
 
 // Merged emission rates of the cell at x of a row whose sources are
@@ -369,21 +356,21 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
 #pragma unroll
     for (int f = 0; f < M::NF; ++f) {
         if (M::f32_field(f)) {
-            n[f].c = cell_value<StF32>(a, f, x, y, z);
-            n[f].xm = neighbour<StF32>(a, f, x, y, z, 0, -1);
-            n[f].xp = neighbour<StF32>(a, f, x, y, z, 0, +1);
-            n[f].ym = neighbour<StF32>(a, f, x, y, z, 1, -1);
-            n[f].yp = neighbour<StF32>(a, f, x, y, z, 1, +1);
-            n[f].zm = neighbour<StF32>(a, f, x, y, z, 2, -1);
-            n[f].zp = neighbour<StF32>(a, f, x, y, z, 2, +1);
+            n[f].c = stencil_value<StF32>(a, f, x, y, z);
+            n[f].xm = stencil_value<StF32>(a, f, x - 1, y, z);
+            n[f].xp = stencil_value<StF32>(a, f, x + 1, y, z);
+            n[f].ym = stencil_value<StF32>(a, f, x, y - 1, z);
+            n[f].yp = stencil_value<StF32>(a, f, x, y + 1, z);
+            n[f].zm = stencil_value<StF32>(a, f, x, y, z - 1);
+            n[f].zp = stencil_value<StF32>(a, f, x, y, z + 1);
         } else {
-            n[f].c = cell_value<S>(a, f, x, y, z);
-            n[f].xm = neighbour<S>(a, f, x, y, z, 0, -1);
-            n[f].xp = neighbour<S>(a, f, x, y, z, 0, +1);
-            n[f].ym = neighbour<S>(a, f, x, y, z, 1, -1);
-            n[f].yp = neighbour<S>(a, f, x, y, z, 1, +1);
-            n[f].zm = neighbour<S>(a, f, x, y, z, 2, -1);
-            n[f].zp = neighbour<S>(a, f, x, y, z, 2, +1);
+            n[f].c = stencil_value<S>(a, f, x, y, z);
+            n[f].xm = stencil_value<S>(a, f, x - 1, y, z);
+            n[f].xp = stencil_value<S>(a, f, x + 1, y, z);
+            n[f].ym = stencil_value<S>(a, f, x, y - 1, z);
+            n[f].yp = stencil_value<S>(a, f, x, y + 1, z);
+            n[f].zm = stencil_value<S>(a, f, x, y, z - 1);
+            n[f].zp = stencil_value<S>(a, f, x, y, z + 1);
         }
     }
     Emission<M::NO> em{};
@@ -403,7 +390,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
     }
 }
 
-// ------------------------------------------------------------- tiled kernel
+// ------------------------------------------------------ lane and tile helpers
 
 // Lane l receives v from lane l-1 (l-1 >= 0) or `fill` (lane 0): DPP wave_shr:1.
 __device__ __forceinline__ float lane_from_left(float v, float fill) {
@@ -429,14 +416,7 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
     return xcd < r ? xcd * (q + 1) + i : r * (q + 1) + (xcd - r) * q + i;
 }
 
-// ---- tiled march ---------------------------------------------------------
-//
-// A workgroup owns columns [x0, x0+TX) x rows [yb, yb+BY) and marches planes
-// [z0, z1).  Each wave holds RY rows of VX cells per lane for planes z-1, z,
-// z+1 (the z window) and keeps PF further planes in flight.  Loads are issued
-// back to back from always-valid (clamped) addresses; boundary rules that
-// replace a loaded value (fixed ghosts, held layers) are applied when the
-// plane enters the window, so they never sit between loads.
+// ---- shared helpers of the tiled kernels --------------------------------
 
 template <class M, class S, int VX>
 __device__ __forceinline__ void load_raw(const StepArgs& a, int f, long long idx, float (&v)[VX]) {
@@ -444,18 +424,18 @@ __device__ __forceinline__ void load_raw(const StepArgs& a, int f, long long idx
     else load_vec<S, VX>(a.in[f], idx, v);
 }
 
-// Replace loaded values where a boundary rule fixes them: a fixed row or
-// plane (ghost / held layer), then held x faces (x faces win, face order).
+// Replace loaded values where a boundary rule fixes them: a ghost row or
+// plane beyond a face, else held x faces, then a held row, then a held plane.
 template <int VX>
-__device__ __forceinline__ void fix_row(const StepArgs& a, int f, Src pz, Src py, int xl,
-                                        float (&v)[VX]) {
+__device__ __forceinline__ void fix_row(const StepArgs& a, int f, Src pz, Src py, int xl, float (&v)[VX]) {
+    const bool ghost = py.cst == CST_GHOST || pz.cst == CST_GHOST;
     if (py.cst || pz.cst) {
-        const float c = py.cst ? py.v : pz.v;
+        const float c = py.cst == CST_GHOST ? py.v : pz.cst == CST_GHOST ? pz.v : py.cst ? py.v : pz.v;
 #pragma unroll
         for (int i = 0; i < VX; ++i) v[i] = c;
     }
     const int hm = a.held[f];
-    if (hm & 3) {
+    if ((hm & 3) && !ghost) {
         const float b0 = a.bcv[f][0], b1 = a.bcv[f][1];
 #pragma unroll
         for (int i = 0; i < VX; ++i) {
@@ -464,11 +444,6 @@ __device__ __forceinline__ void fix_row(const StepArgs& a, int f, Src pz, Src py
         }
     }
 }
-
-template <class M, int W, int TX>
-struct TileLds {
-    float row[W > 1 ? 2 : 1][M::NF][W > 1 ? W : 1][2][W > 1 ? TX : 1];
-};
 
 // Value of row element `x` (0 <= x < nx <= TX) held by this wave: lane x/VX,
 // element x%VX.  Every element is read out of that lane first and the choice
@@ -483,267 +458,6 @@ __device__ __forceinline__ float row_element(const float (&v)[VX], int x) {
         t = e == i ? u : t;
     }
     return t;
-}
-
-template <class M, class S, int VX, int RY, int W, int PF>
-__device__ __forceinline__ void tile_step(const StepArgs& a, int t, TileLds<M, W, 64 * VX>& sm) {
-    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, BY = RY * W;
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tx = t % a.tiles_x;
-    const int t2 = t / a.tiles_x;
-    const int ty = t2 % a.tiles_y;
-    const int tz = t2 / a.tiles_y;
-    const int x0 = tx * TX;
-    const int yb = ty * BY;                 // first row of the block
-    const int y0 = yb + w * RY;             // first row of this wave
-    const int z0 = tz * a.cz;
-    const int z1 = min(z0 + a.cz, a.nz);
-    const int xl = x0 + lane * VX;
-    const bool whole_row = a.tiles_x == 1;  // x ghosts come from the row itself
-    const bool top = W == 1 || w == 0, bottom = W == 1 || w == W - 1;
-
-    auto plane_src = [&](int f, int z) {
-        return resolve_axis(z, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
-    };
-    auto row_src = [&](int f, int y) {
-        return resolve_axis(y, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
-    };
-    auto row_idx = [&](Src pz, Src py) {
-        return (long long)pz.idx * a.plane + (long long)py.idx * a.pitch;
-    };
-
-    float P[NF][3][RY][VX];       // planes z-1, z, z+1 (ready)
-    float Q[PF][NF][RY][VX];      // planes z+2 .. z+1+PF (in flight)
-    float Ht[NF][VX], Hb[NF][VX];             // halo rows above / below, plane z
-    float Htn[NF][VX], Hbn[NF][VX];           // same, plane z+1 (in flight)
-    float E[NF][RY], En[NF][RY];              // x-edge loads (multi-tile rows)
-
-    auto issue_plane = [&](float (&d)[NF][RY][VX], int z) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const Src pz = plane_src(f, z);
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-                load_raw<M, S, VX>(a, f, row_idx(pz, row_src(f, y0 + r)) + xl, d[f][r]);
-        }
-    };
-    auto finish_plane = [&](float (&d)[NF][RY][VX], int z) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const Src pz = plane_src(f, z);
-#pragma unroll
-            for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, pz, row_src(f, y0 + r), xl, d[f][r]);
-        }
-    };
-    // halo rows (block edges) and x-edge values of plane z
-    auto issue_extras = [&](float (&ht)[NF][VX], float (&hb)[NF][VX], float (&e)[NF][RY], int z) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const Src pz = plane_src(f, z);
-            if (top) load_raw<M, S, VX>(a, f, row_idx(pz, row_src(f, yb - 1)) + xl, ht[f]);
-            if (bottom) load_raw<M, S, VX>(a, f, row_idx(pz, row_src(f, yb + BY)) + xl, hb[f]);
-            if (!whole_row) {
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    e[f][r] = 0.f;
-                    if (lane == 0 || lane == 63) {
-                        const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
-                        const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0],
-                                                    a.bcv[f][1]);
-                        const long long idx = row_idx(pz, row_src(f, y0 + r)) + sx.idx;
-                        e[f][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
-                    }
-                }
-            }
-        }
-    };
-    auto finish_extras = [&](float (&ht)[NF][VX], float (&hb)[NF][VX], float (&e)[NF][RY], int z) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const Src pz = plane_src(f, z);
-            if (top) fix_row<VX>(a, f, pz, row_src(f, yb - 1), xl, ht[f]);
-            if (bottom) fix_row<VX>(a, f, pz, row_src(f, yb + BY), xl, hb[f]);
-            if (!whole_row) {
-                const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
-                const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
-#pragma unroll
-                for (int r = 0; r < RY; ++r) {
-                    const Src py = row_src(f, y0 + r);
-                    float v = e[f][r];
-                    v = py.cst ? py.v : (pz.cst ? pz.v : v);
-                    e[f][r] = sx.cst ? sx.v : v;
-                }
-            }
-        }
-    };
-
-    // prologue
-    {
-        float T0[NF][RY][VX], T1[NF][RY][VX], T2[NF][RY][VX];
-        issue_plane(T0, z0 - 1);
-        issue_plane(T1, z0);
-        issue_plane(T2, z0 + 1);
-        issue_extras(Ht, Hb, E, z0);
-#pragma unroll
-        for (int k = 0; k < PF; ++k)
-            if (z0 + 2 + k <= z1) issue_plane(Q[k], z0 + 2 + k);
-        if (z0 + 1 < z1) issue_extras(Htn, Hbn, En, z0 + 1);
-        finish_plane(T0, z0 - 1);
-        finish_plane(T1, z0);
-        finish_plane(T2, z0 + 1);
-        finish_extras(Ht, Hb, E, z0);
-#pragma unroll
-        for (int f = 0; f < NF; ++f)
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-#pragma unroll
-                for (int i = 0; i < VX; ++i) {
-                    P[f][0][r][i] = T0[f][r][i];
-                    P[f][1][r][i] = T1[f][r][i];
-                    P[f][2][r][i] = T2[f][r][i];
-                }
-    }
-
-    for (int z = z0; z < z1; ++z) {
-        const int par = (z - z0) & 1;
-        float up[NF][VX], dn[NF][VX];      // rows above row 0 / below row RY-1
-        if (W > 1) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int i = 0; i < VX; ++i) {
-                    sm.row[par][f][w][0][lane * VX + i] = P[f][1][0][i];
-                    sm.row[par][f][w][1][lane * VX + i] = P[f][1][RY - 1][i];
-                }
-            __syncthreads();
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int i = 0; i < VX; ++i) {
-                    up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][1][lane * VX + i] : Ht[f][i];
-                    dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i]
-                                         : Hb[f][i];
-                }
-        } else {
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int i = 0; i < VX; ++i) { up[f][i] = Ht[f][i]; dn[f][i] = Hb[f][i]; }
-        }
-
-        const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const int y = y0 + r;
-            Nb n[NF][VX];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                float L, R;
-                if (whole_row) {
-                    // ghost left of x=0 and right of x=nx-1, from this very row
-                    const int klo = a.bck[f][0], khi = a.bck[f][1];
-                    const float first = row_element<VX>(P[f][1][r], 0);
-                    const float last = row_element<VX>(P[f][1][r], a.nx - 1);
-                    L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
-                    R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
-                } else {
-                    L = bcast_lane(E[f][r], 0);
-                    R = bcast_lane(E[f][r], 63);
-                }
-                const float left = lane_from_left(P[f][1][r][VX - 1], L);
-                const float right = lane_from_right(P[f][1][r][0], R);
-#pragma unroll
-                for (int i = 0; i < VX; ++i) {
-                    Nb& q = n[f][i];
-                    q.c = P[f][1][r][i];
-                    q.xm = i > 0 ? P[f][1][r][i - 1] : left;
-                    q.xp = i < VX - 1 ? P[f][1][r][i + 1] : right;
-                    if (xl + i == a.nx - 1) q.xp = R;
-                    q.ym = r > 0 ? P[f][1][r - 1][i] : up[f][i];
-                    q.yp = r < RY - 1 ? P[f][1][r + 1][i] : dn[f][i];
-                    q.zm = P[f][0][r][i];
-                    q.zp = P[f][2][r][i];
-                }
-            }
-            int s0 = 0, s1 = 0;
-            if (M::SOURCES && y < a.ny) {
-                s0 = a.src_row[z * a.ny + y];
-                s1 = a.src_row[z * a.ny + y + 1];
-            }
-            float o[NO][VX];
-#pragma unroll
-            for (int i = 0; i < VX; ++i) {
-                Nb ni[NF];
-#pragma unroll
-                for (int f = 0; f < NF; ++f) ni[f] = n[f][i];
-                Emission<NO> em{};
-                if (M::SOURCES && s0 < s1) em = cell_sources<NO>(a, xl + i, s0, s1);
-                float oi[NO];
-                M::cell(a, ni, uh, em.any, em.e, oi);
-#pragma unroll
-                for (int s = 0; s < NO; ++s) o[s][i] = held_out(a, s, xl + i, y, z, oi[s]);
-            }
-            if (y < a.ny && xl < a.nx) {
-                const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
-#pragma unroll
-                for (int s = 0; s < NO; ++s) {
-                    if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
-                    else store_vec<S, VX>(a.out[s], idx, o[s]);
-                }
-            }
-        }
-
-        // slide the window: z+2 enters, issue plane z+2+PF and the extras of z+2
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-#pragma unroll
-                for (int i = 0; i < VX; ++i) {
-                    P[f][0][r][i] = P[f][1][r][i];
-                    P[f][1][r][i] = P[f][2][r][i];
-                    P[f][2][r][i] = Q[0][f][r][i];
-#pragma unroll
-                    for (int k = 0; k + 1 < PF; ++k) Q[k][f][r][i] = Q[k + 1][f][r][i];
-                }
-#pragma unroll
-            for (int r = 0; r < RY; ++r) E[f][r] = En[f][r];
-#pragma unroll
-            for (int i = 0; i < VX; ++i) {
-                Ht[f][i] = Htn[f][i];
-                Hb[f][i] = Hbn[f][i];
-            }
-        }
-        if (z + 2 + PF <= z1) issue_plane(Q[PF - 1], z + 2 + PF);
-        if (z + 2 < z1) issue_extras(Htn, Hbn, En, z + 2);
-        if (z + 2 <= z1) {
-            float T[NF][RY][VX];
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int r = 0; r < RY; ++r)
-#pragma unroll
-                    for (int i = 0; i < VX; ++i) T[f][r][i] = P[f][2][r][i];
-            finish_plane(T, z + 2);
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-#pragma unroll
-                for (int r = 0; r < RY; ++r)
-#pragma unroll
-                    for (int i = 0; i < VX; ++i) P[f][2][r][i] = T[f][r][i];
-        }
-        if (z + 1 < z1) finish_extras(Ht, Hb, E, z + 1);
-    }
-    if (W > 1) __syncthreads();   // the LDS rows may be reused by the next tile
-}
-
-// Step arguments live in device memory (not the kernel-argument segment) so
-// that boundary values picked by runtime conditions are plain scalar loads.
-template <class M, class S, int VX, int RY, int W, int PF>
-__global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restrict__ pa) {
-    __shared__ TileLds<M, W, 64 * VX> sm;
-    tile_step<M, S, VX, RY, W, PF>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
 // ---- plane-block kernel ---------------------------------------------------
@@ -780,24 +494,19 @@ __device__ __forceinline__ float lane_from_right_wrap(float v) {
 // rotation of a whole periodic row.
 enum { XS_EDGE = 0, XS_OWN = 1, XS_CONST = 2, XS_ROT = 3 };
 
-template <class M, class S, int VX, int RY, int W, int CZ, bool FAST>
-__device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 64 * VX>& sm, int lane, int w,
-                                              int x0, int yb, int y0, int z0, int xl, bool whole_row,
-                                              const Src (&rs)[M::NF][RY], const Src (&rh)[M::NF][W == 1 ? 2 : 1],
-                                              const Src (&ps)[M::NF][CZ + 2]) {
-    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, NP = CZ + 2;
-    constexpr int NH = W == 1 ? 2 : 1;
-    const bool edge_wave = W == 1 || w == 0 || w == W - 1;
-
-    // x sides of this tile, per field
-    int xsl[NF], xsr[NF];
+// x sides of a tile per field; returns whether any x-edge value must be
+// loaded.  FAST (whole tiles, no fixed rows): interior sides and split
+// periodic rows take the loaded edge, faces their rule.  Otherwise the
+// ghosts come from lane reads (whole rows) or the loaded edges.
+template <class M, bool FAST>
+__device__ __forceinline__ bool x_sides(const StepArgs& a, int x0, int tx, bool whole_row, int (&xsl)[M::NF],
+                                        int (&xsr)[M::NF]) {
     bool need_edges = false;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+    for (int f = 0; f < M::NF; ++f) {
         const int klo = a.bck[f][0], khi = a.bck[f][1];
-        const bool left_face = x0 == 0, right_face = x0 + TX >= a.nx;
+        const bool left_face = x0 == 0, right_face = x0 + tx >= a.nx;
         if (!FAST || whole_row) {
-            // general path (and whole rows): sides from the face rule
             xsl[f] = klo == BC_MIRROR ? XS_OWN : klo == BC_PERIODIC ? XS_ROT : XS_CONST;
             xsr[f] = khi == BC_MIRROR ? XS_OWN : khi == BC_PERIODIC ? XS_ROT : XS_CONST;
         }
@@ -807,11 +516,152 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
         }
         need_edges = need_edges || xsl[f] == XS_EDGE || xsr[f] == XS_EDGE;
     }
+    return FAST ? need_edges : !whole_row;
+}
+
+// The cells of plane z that one wave owns.  v0 holds its RY rows of the
+// plane, vm / vp the same rows of planes z-1 / z+1, h its halo rows (one
+// wave: above and below; several: above for wave 0, below for the last),
+// e the x-edge values (lane 0 left, lane 63 right).  Rows of neighbouring
+// waves pass through LDS buffer `par`.  FAST takes the x ghosts from the
+// side modes with no lane reads; otherwise from lane reads, with the ragged
+// end of the row handled.  `held` applies held output faces.
+template <class M, class S, int VX, int RY, int W, bool FAST>
+__device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64 * VX>& sm, int par, int lane,
+                                            int w, int xl, int y0, int z, bool whole_row, bool held,
+                                            const int (&xsl)[M::NF], const int (&xsr)[M::NF],
+                                            const float (&vm)[M::NF][RY][VX], const float (&v0)[M::NF][RY][VX],
+                                            const float (&vp)[M::NF][RY][VX],
+                                            const float (&h)[M::NF][W == 1 ? 2 : 1][VX],
+                                            const float (&e)[M::NF][RY]) {
+    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX;
+    constexpr int NH = W == 1 ? 2 : 1;
+    float up[NF][VX], dn[NF][VX];
+    if (W > 1) {
+        constexpr int EXP = BlockLds<M, W, TX>::EXP;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                if (EXP == 1) {
+                    sm.row[par][f][w][0][lane * VX + i] = w == 0 ? v0[f][RY - 1][i] : v0[f][0][i];
+                } else {
+                    sm.row[par][f][w][0][lane * VX + i] = v0[f][0][i];
+                    sm.row[par][f][w][EXP - 1][lane * VX + i] = v0[f][RY - 1][i];
+                }
+            }
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][EXP - 1][lane * VX + i] : h[f][0][i];
+                dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i] : h[f][0][i];
+            }
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                up[f][i] = h[f][0][i];
+                dn[f][i] = h[f][NH - 1][i];
+            }
+    }
+    const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int y = y0 + r;
+        Nb n[NF][VX];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const float (&v)[VX] = v0[f][r];
+            float left, right, R = 0.f;
+            if (FAST) {
+                // fill value of lane 0 (left) / lane 63 (right): no lane reads
+                if (xsl[f] == XS_ROT) {
+                    left = lane_from_left_wrap(v[VX - 1]);
+                } else {
+                    const float fl = xsl[f] == XS_OWN ? v[0] : xsl[f] == XS_CONST ? a.bcv[f][0] : e[f][r];
+                    left = lane_from_left(v[VX - 1], fl);
+                }
+                if (xsr[f] == XS_ROT) {
+                    right = lane_from_right_wrap(v[0]);
+                } else {
+                    const float fr = xsr[f] == XS_OWN ? v[VX - 1] : xsr[f] == XS_CONST ? a.bcv[f][1] : e[f][r];
+                    right = lane_from_right(v[0], fr);
+                }
+            } else {
+                float L;
+                if (whole_row) {
+                    const int klo = a.bck[f][0], khi = a.bck[f][1];
+                    const float first = bcast_lane(v[0], 0);
+                    const float last = row_element<VX>(v, a.nx - 1);
+                    L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
+                    R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
+                } else {
+                    L = bcast_lane(e[f][r], 0);
+                    R = bcast_lane(e[f][r], 63);
+                }
+                left = lane_from_left(v[VX - 1], L);
+                right = lane_from_right(v[0], R);
+            }
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                Nb& q = n[f][i];
+                q.c = v[i];
+                q.xm = i > 0 ? v[i - 1] : left;
+                q.xp = i < VX - 1 ? v[i + 1] : right;
+                if (!FAST && xl + i == a.nx - 1) q.xp = R;
+                q.ym = r > 0 ? v0[f][r - 1][i] : up[f][i];
+                q.yp = r < RY - 1 ? v0[f][r + 1][i] : dn[f][i];
+                q.zm = vm[f][r][i];
+                q.zp = vp[f][r][i];
+            }
+        }
+        int s0 = 0, s1 = 0;
+        if (M::SOURCES && y < a.ny) {
+            s0 = a.src_row[z * a.ny + y];
+            s1 = a.src_row[z * a.ny + y + 1];
+        }
+        float o[NO][VX];
+#pragma unroll
+        for (int i = 0; i < VX; ++i) {
+            Nb ni[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) ni[f] = n[f][i];
+            Emission<NO> em{};
+            if (M::SOURCES && s0 < s1) em = cell_sources<NO>(a, xl + i, s0, s1);
+            float oi[NO];
+            M::cell(a, ni, uh, em.any, em.e, oi);
+#pragma unroll
+            for (int s = 0; s < NO; ++s) o[s][i] = held ? held_out(a, s, xl + i, y, z, oi[s]) : oi[s];
+        }
+        if (y < a.ny && xl < a.nx) {
+            const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
+#pragma unroll
+            for (int s = 0; s < NO; ++s) {
+                if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
+                else store_vec<S, VX>(a.out[s], idx, o[s]);
+            }
+        }
+    }
+}
+
+template <class M, class S, int VX, int RY, int W, int CZ, bool FAST>
+__device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 64 * VX>& sm, int lane, int w,
+                                              int x0, int yb, int y0, int z0, int xl, bool whole_row,
+                                              const Src (&rs)[M::NF][RY], const Src (&rh)[M::NF][W == 1 ? 2 : 1],
+                                              const Src (&ps)[M::NF][CZ + 2]) {
+    constexpr int NF = M::NF, TX = 64 * VX, NP = CZ + 2;
+    constexpr int NH = W == 1 ? 2 : 1;
+    const bool edge_wave = W == 1 || w == 0 || w == W - 1;
+    int xsl[NF], xsr[NF];
+    const bool need_edges = x_sides<M, FAST>(a, x0, TX, whole_row, xsl, xsr);
 
     // issue every load of the slab
-    float V[NF][NP][RY][VX];
-    float H[NF][CZ][NH][VX];
-    float E[NF][CZ][RY];
+    float V[NP][NF][RY][VX];
+    float H[CZ][NF][NH][VX];
+    float E[CZ][NF][RY];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -819,7 +669,7 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
             for (int r = 0; r < RY; ++r)
                 load_raw<M, S, VX>(a, f, (long long)ps[f][k].idx * a.plane +
-                                             (long long)rs[f][r].idx * a.pitch + xl, V[f][k][r]);
+                                             (long long)rs[f][r].idx * a.pitch + xl, V[k][f][r]);
     if (edge_wave) {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
@@ -828,9 +678,9 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
                 for (int h = 0; h < NH; ++h)
                     load_raw<M, S, VX>(a, f, (long long)ps[f][k + 1].idx * a.plane +
-                                                 (long long)rh[f][h].idx * a.pitch + xl, H[f][k][h]);
+                                                 (long long)rh[f][h].idx * a.pitch + xl, H[k][f][h]);
     }
-    if (!FAST ? !whole_row : need_edges) {
+    if (need_edges) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
@@ -839,11 +689,11 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
             for (int k = 0; k < CZ; ++k)
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
-                    E[f][k][r] = 0.f;
+                    E[k][f][r] = 0.f;
                     if (lane == 0 || lane == 63) {
                         const long long idx = (long long)ps[f][k + 1].idx * a.plane +
                                               (long long)rs[f][r].idx * a.pitch + sxi;
-                        E[f][k][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
+                        E[k][f][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
                     }
                 }
         }
@@ -864,12 +714,12 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
                 for (int k = 0; k < NP; ++k)
 #pragma unroll
-                    for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, ps[f][k], rs[f][r], xl, V[f][k][r]);
+                    for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, ps[f][k], rs[f][r], xl, V[k][f][r]);
                 if (edge_wave) {
 #pragma unroll
                     for (int k = 0; k < CZ; ++k)
 #pragma unroll
-                        for (int h = 0; h < NH; ++h) fix_row<VX>(a, f, ps[f][k + 1], rh[f][h], xl, H[f][k][h]);
+                        for (int h = 0; h < NH; ++h) fix_row<VX>(a, f, ps[f][k + 1], rh[f][h], xl, H[k][f][h]);
                 }
             }
             if (!whole_row) {
@@ -879,10 +729,7 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
                 for (int k = 0; k < CZ; ++k)
 #pragma unroll
                     for (int r = 0; r < RY; ++r) {
-                        const Src py = rs[f][r], pz = ps[f][k + 1];
-                        float v = E[f][k][r];
-                        v = py.cst ? py.v : (pz.cst ? pz.v : v);
-                        E[f][k][r] = sx.cst ? sx.v : v;
+                        E[k][f][r] = fixed_or(sx, rs[f][r], ps[f][k + 1], E[k][f][r]);
                     }
             }
         }
@@ -891,122 +738,9 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
     for (int k = 1; k <= CZ; ++k) {
         const int z = z0 + k - 1;
-        if (z < a.nz) {
-            float up[NF][VX], dn[NF][VX];
-            if (W > 1) {
-                const int par = k & 1;
-                constexpr int EXP = BlockLds<M, W, TX>::EXP;
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                    for (int i = 0; i < VX; ++i) {
-                        if (EXP == 1) {
-                            sm.row[par][f][w][0][lane * VX + i] = w == 0 ? V[f][k][RY - 1][i] : V[f][k][0][i];
-                        } else {
-                            sm.row[par][f][w][0][lane * VX + i] = V[f][k][0][i];
-                            sm.row[par][f][w][EXP - 1][lane * VX + i] = V[f][k][RY - 1][i];
-                        }
-                    }
-                __syncthreads();
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                    for (int i = 0; i < VX; ++i) {
-                        up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][EXP - 1][lane * VX + i]
-                                         : H[f][k - 1][0][i];
-                        dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i]
-                                             : H[f][k - 1][0][i];
-                    }
-            } else {
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                    for (int i = 0; i < VX; ++i) {
-                        up[f][i] = H[f][k - 1][0][i];
-                        dn[f][i] = H[f][k - 1][NH - 1][i];
-                    }
-            }
-            const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
-#pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                const int y = y0 + r;
-                Nb n[NF][VX];
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const float (&v)[VX] = V[f][k][r];
-                    float left, right, R = 0.f;
-                    if (FAST) {
-                        // fill value of lane 0 (left) / lane 63 (right): no lane reads
-                        if (xsl[f] == XS_ROT) {
-                            left = lane_from_left_wrap(v[VX - 1]);
-                        } else {
-                            const float fl = xsl[f] == XS_OWN ? v[0] : xsl[f] == XS_CONST ? a.bcv[f][0]
-                                                                                          : E[f][k - 1][r];
-                            left = lane_from_left(v[VX - 1], fl);
-                        }
-                        if (xsr[f] == XS_ROT) {
-                            right = lane_from_right_wrap(v[0]);
-                        } else {
-                            const float fr = xsr[f] == XS_OWN ? v[VX - 1] : xsr[f] == XS_CONST ? a.bcv[f][1]
-                                                                                               : E[f][k - 1][r];
-                            right = lane_from_right(v[0], fr);
-                        }
-                    } else {
-                        float L;
-                        if (whole_row) {
-                            const int klo = a.bck[f][0], khi = a.bck[f][1];
-                            const float first = bcast_lane(v[0], 0);
-                            const float last = row_element<VX>(v, a.nx - 1);
-                            L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
-                            R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
-                        } else {
-                            L = bcast_lane(E[f][k - 1][r], 0);
-                            R = bcast_lane(E[f][k - 1][r], 63);
-                        }
-                        left = lane_from_left(v[VX - 1], L);
-                        right = lane_from_right(v[0], R);
-                    }
-#pragma unroll
-                    for (int i = 0; i < VX; ++i) {
-                        Nb& q = n[f][i];
-                        q.c = v[i];
-                        q.xm = i > 0 ? v[i - 1] : left;
-                        q.xp = i < VX - 1 ? v[i + 1] : right;
-                        if (!FAST && xl + i == a.nx - 1) q.xp = R;
-                        q.ym = r > 0 ? V[f][k][r - 1][i] : up[f][i];
-                        q.yp = r < RY - 1 ? V[f][k][r + 1][i] : dn[f][i];
-                        q.zm = V[f][k - 1][r][i];
-                        q.zp = V[f][k + 1][r][i];
-                    }
-                }
-                int s0 = 0, s1 = 0;
-                if (M::SOURCES && y < a.ny) {
-                    s0 = a.src_row[z * a.ny + y];
-                    s1 = a.src_row[z * a.ny + y + 1];
-                }
-                float o[NO][VX];
-#pragma unroll
-                for (int i = 0; i < VX; ++i) {
-                    Nb ni[NF];
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) ni[f] = n[f][i];
-                    Emission<NO> em{};
-                    if (M::SOURCES && s0 < s1) em = cell_sources<NO>(a, xl + i, s0, s1);
-                    float oi[NO];
-                    M::cell(a, ni, uh, em.any, em.e, oi);
-#pragma unroll
-                    for (int s = 0; s < NO; ++s) o[s][i] = FAST ? oi[s] : held_out(a, s, xl + i, y, z, oi[s]);
-                }
-                if (y < a.ny && xl < a.nx) {
-                    const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
-#pragma unroll
-                    for (int s = 0; s < NO; ++s) {
-                        if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
-                        else store_vec<S, VX>(a.out[s], idx, o[s]);
-                    }
-                }
-            }
-        }
+        if (z < a.nz)
+            plane_cells<M, S, VX, RY, W, FAST>(a, sm, k & 1, lane, w, xl, y0, z, whole_row, !FAST, xsl, xsr,
+                                               V[k - 1], V[k], V[k + 1], H[k - 1], E[k - 1]);
     }
 }
 
@@ -1084,6 +818,182 @@ template <class M, class S, int VX, int RY, int W, int CZ>
 __global__ __launch_bounds__(64 * W) void block_kernel(const StepArgs* __restrict__ pa) {
     __shared__ BlockLds<M, W, 64 * VX> sm;
     block_step<M, S, VX, RY, W, CZ>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
+}
+
+// ---- z-march kernel -------------------------------------------------------
+//
+// A workgroup owns columns [x0, x0+TX) and rows [yb, yb+BY) and marches planes
+// [z0, z1), reading each plane of its rows once.  Each wave keeps NB = 3+PF
+// planes in a register ring: z-1, z, z+1 in use and PF more in flight.  The
+// march is unrolled by NB so that every ring slot is a fixed set of registers
+// (no moves).  Rows and x sides are resolved once per tile; a plane needs a
+// fix-up only where a rule replaces loaded values (a fixed or held z face, or
+// the tile's fixed rows and held x faces in the general path).
+
+template <class M, class S, int VX, int RY, int W, int PF, bool FAST>
+__device__ __forceinline__ void march_tile(const StepArgs& a, BlockLds<M, W, 64 * VX>& sm, int lane, int w,
+                                           int x0, int y0, int z0, int z1, int xl, bool whole_row,
+                                           const Src (&rs)[M::NF][RY], const Src (&rh)[M::NF][W == 1 ? 2 : 1],
+                                           bool rows_fix, bool xy_held, bool held_lo, bool held_hi) {
+    constexpr int NF = M::NF, TX = 64 * VX, NB = 3 + PF;
+    constexpr int NH = W == 1 ? 2 : 1;
+    const bool edge_wave = W == 1 || w == 0 || w == W - 1;
+    int xsl[NF], xsr[NF];
+    const bool need_edges = x_sides<M, FAST>(a, x0, TX, whole_row, xsl, xsr);
+    const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
+    int sxi[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+        sxi[f] = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]).idx;
+
+    float V[NB][NF][RY][VX];
+    float H[NB][NF][NH][VX];
+    float E[NB][NF][RY];
+
+    // request plane p (halo rows and x edges only for planes this tile computes)
+    auto issue = [&](float (&v)[NF][RY][VX], float (&hv)[NF][NH][VX], float (&e)[NF][RY], int p) {
+        const bool extras = p >= z0 && p < z1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const int pz = resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]).idx;
+            const long long pb = (long long)pz * a.plane;
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+                load_raw<M, S, VX>(a, f, pb + (long long)rs[f][r].idx * a.pitch + xl, v[f][r]);
+            if (extras && edge_wave) {
+#pragma unroll
+                for (int k = 0; k < NH; ++k)
+                    load_raw<M, S, VX>(a, f, pb + (long long)rh[f][k].idx * a.pitch + xl, hv[f][k]);
+            }
+            if (extras && need_edges) {
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    e[f][r] = 0.f;
+                    if (lane == 0 || lane == 63) {
+                        const long long idx = pb + (long long)rs[f][r].idx * a.pitch + sxi[f];
+                        e[f][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
+                    }
+                }
+            }
+        }
+    };
+    // replace loaded values of plane p where a boundary rule fixes them
+    auto finish = [&](float (&v)[NF][RY][VX], float (&hv)[NF][NH][VX], float (&e)[NF][RY], int p) {
+        bool any = rows_fix;
+        if (p <= 0 || p >= a.nz - 1) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                any = any || resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]).cst;
+        }
+        if (any) {
+            const bool extras = p >= z0 && p < z1;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const Src pz = resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+#pragma unroll
+                for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, pz, rs[f][r], xl, v[f][r]);
+                if (extras && edge_wave) {
+#pragma unroll
+                    for (int k = 0; k < NH; ++k) fix_row<VX>(a, f, pz, rh[f][k], xl, hv[f][k]);
+                }
+                if (extras && need_edges) {
+                    const Src sx = resolve_axis(q, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
+#pragma unroll
+                    for (int r = 0; r < RY; ++r) e[f][r] = fixed_or(sx, rs[f][r], pz, e[f][r]);
+                }
+            }
+        }
+    };
+
+    // planes z0-1 .. z0+1+PF go to slots 0 .. NB-1; plane p lives in slot (p - z0 + 1) % NB
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        if (z0 - 1 + k <= z1) issue(V[k], H[k], E[k], z0 - 1 + k);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) finish(V[k], H[k], E[k], z0 - 1 + k);
+
+    for (int zb = z0; zb < z1; zb += NB) {
+#pragma unroll
+        for (int J = 0; J < NB; ++J) {
+            const int z = zb + J;
+            if (z < z1) {
+                const bool held = xy_held || (held_lo && z == 0) || (held_hi && z == a.nz - 1);
+                plane_cells<M, S, VX, RY, W, FAST>(a, sm, (z - z0) & 1, lane, w, xl, y0, z, whole_row, held,
+                                                   xsl, xsr, V[J], V[(J + 1) % NB], V[(J + 2) % NB],
+                                                   H[(J + 1) % NB], E[(J + 1) % NB]);
+                // the slot of plane z-1 is free: request plane z+2+PF into it
+                if (z + 2 + PF <= z1) issue(V[J], H[J], E[J], z + 2 + PF);
+                if (z + 2 <= z1) finish(V[(J + 3) % NB], H[(J + 3) % NB], E[(J + 3) % NB], z + 2);
+            }
+        }
+    }
+}
+
+template <class M, class S, int VX, int RY, int W, int PF>
+__device__ __forceinline__ void tile_step(const StepArgs& a, int t, BlockLds<M, W, 64 * VX>& sm) {
+    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, BY = RY * W;
+    constexpr int NH = W == 1 ? 2 : 1;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TileXYZ tc = tile_coords(a, t);
+    const int x0 = tc.x * TX;
+    const int yb = tc.y * BY;
+    const int y0 = yb + w * RY;
+    const int z0 = tc.z * a.cz;
+    const int z1 = min(z0 + a.cz, a.nz);
+    const int xl = x0 + lane * VX;
+    const bool whole_row = a.tiles_x == 1;
+    const int hrow0 = (W == 1 || w == 0) ? yb - 1 : yb + BY;
+
+    // rows of this wave and its halo rows, resolved once for the whole march
+    Src rs[NF][RY], rh[NF][NH];
+    bool rows_fix = false;
+    const int ql = x0 - 1, qr = min(x0 + TX, a.nx);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            rs[f][r] = resolve_axis(y0 + r, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
+            rows_fix = rows_fix || rs[f][r].cst;
+        }
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            rh[f][h] = resolve_axis(h == 0 ? hrow0 : yb + BY, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2],
+                                    a.bcv[f][3]);
+            rows_fix = rows_fix || rh[f][h].cst;
+        }
+        rows_fix = rows_fix || (a.held[f] & 3) != 0;
+        if (!whole_row)
+            rows_fix = rows_fix ||
+                       resolve_axis(ql, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]).cst ||
+                       resolve_axis(qr, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]).cst;
+    }
+    // held output faces: x and y faces this tile touches hold on every plane
+    bool xy_held = false, held_lo = false, held_hi = false;
+#pragma unroll
+    for (int s = 0; s < NO; ++s) {
+        const int hm = a.out_held[s];
+        xy_held = xy_held || ((hm & 1) && x0 == 0) || ((hm & 2) && x0 + TX >= a.nx) || ((hm & 4) && yb == 0) ||
+                  ((hm & 8) && yb + BY >= a.ny);
+        held_lo = held_lo || (hm & 16);
+        held_hi = held_hi || (hm & 32);
+    }
+    const bool fast = a.nx % TX == 0 && !rows_fix;
+    if (fast)
+        march_tile<M, S, VX, RY, W, PF, true>(a, sm, lane, w, x0, y0, z0, z1, xl, whole_row, rs, rh, false,
+                                              xy_held, held_lo, held_hi);
+    else
+        march_tile<M, S, VX, RY, W, PF, false>(a, sm, lane, w, x0, y0, z0, z1, xl, whole_row, rs, rh, rows_fix,
+                                               xy_held, held_lo, held_hi);
+    if (W > 1) __syncthreads();   // the LDS rows may be reused by the next tile
+}
+
+// Step arguments live in device memory (not the kernel-argument segment) so
+// that boundary values picked by runtime conditions are plain scalar loads.
+template <class M, class S, int VX, int RY, int W, int PF>
+__global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restrict__ pa) {
+    __shared__ BlockLds<M, W, 64 * VX> sm;
+    tile_step<M, S, VX, RY, W, PF>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
 // ------------------------------------------------------------ batched kernel

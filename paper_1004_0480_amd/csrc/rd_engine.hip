@@ -863,7 +863,7 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     for (int i = 0; i < kNumTileCfgs; ++i) {
         if (!((mask >> i) & 1u)) continue;
         const TileCfg c = kTileCfgs[i];
-        for (int cz : {0, 32, 16, 8, 4}) {
+        for (int cz : {0, 64, 32, 16, 8, 4}) {
             if (cz != 0 && cz >= g->nz) continue;
             rd_plan p{};
             p.kernel = RD_KERNEL_TILED;

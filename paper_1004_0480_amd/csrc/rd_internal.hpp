@@ -25,7 +25,7 @@ enum Storage { ST_F32 = 0, ST_BF16 = 1, ST_F16 = 2, ST_COUNT };
 // wave, waves per workgroup, planes kept in flight ahead of the z window.
 struct TileCfg { int vx, ry, w, pf; };
 constexpr TileCfg kTileCfgs[] = {
-    {4, 2, 4, 1}, {4, 1, 4, 2}, {2, 2, 4, 2}, {1, 4, 4, 2},
+    {4, 1, 4, 1}, {4, 1, 4, 2}, {2, 2, 4, 2}, {2, 1, 4, 2}, {4, 2, 4, 1}, {1, 4, 4, 2}, {2, 1, 4, 1},
 };
 constexpr int kNumTileCfgs = sizeof(kTileCfgs) / sizeof(kTileCfgs[0]);
 
@@ -51,9 +51,11 @@ constexpr unsigned bits(std::initializer_list<int> l) {
 // update so both passes of a step share one plan.
 constexpr unsigned cfg_mask(int storage, int pm) {
     const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
-    if (storage == ST_F32) return light ? bits({0, 1, 2, 3}) : bits({0, 1, 2});
-    if (storage == ST_BF16) return light ? bits({0, 1, 2}) : bits({1, 2});
-    return bits({1, 2});
+    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2;
+    if (storage == ST_F32)
+        return light ? bits({0, 1, 2, 3, 4, 5, 6}) : medium ? bits({0, 1, 2, 3, 5, 6}) : bits({0, 3, 6});
+    if (storage == ST_BF16) return light ? bits({0, 1, 2, 3, 6}) : bits({0, 3, 6});
+    return light ? bits({1, 2, 3, 6}) : bits({3, 6});
 }
 constexpr unsigned block_mask(int storage, int pm) {
     const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;

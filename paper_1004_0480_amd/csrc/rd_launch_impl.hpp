@@ -82,12 +82,15 @@ hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, 
         default: return hipErrorInvalidValue;
         }
     }
-    static_assert(kNumTileCfgs == 4, "dispatch below lists every tile shape");
+    static_assert(kNumTileCfgs == 7, "dispatch below lists every tile shape");
     switch (cfg) {
     case 0: return run_cfg<M, 0>(d, blocks, s);
     case 1: return run_cfg<M, 1>(d, blocks, s);
     case 2: return run_cfg<M, 2>(d, blocks, s);
     case 3: return run_cfg<M, 3>(d, blocks, s);
+    case 4: return run_cfg<M, 4>(d, blocks, s);
+    case 5: return run_cfg<M, 5>(d, blocks, s);
+    case 6: return run_cfg<M, 6>(d, blocks, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -21,7 +21,8 @@ TOL = 1e-5          # FP32 rel-L2 bound per species against the FP64 oracle
 
 # candidate (vx, ry, waves, prefetch) z-march shapes and (vx, ry, waves, cz)
 # slab shapes; the library rejects the ones it did not compile for a model
-TILE_SHAPES = [(4, 2, 4, 1), (4, 1, 4, 2), (2, 2, 4, 2), (1, 4, 4, 2)]
+TILE_SHAPES = [(4, 1, 4, 1), (4, 1, 4, 2), (2, 2, 4, 2), (2, 1, 4, 2), (4, 2, 4, 1), (1, 4, 4, 2),
+               (2, 1, 4, 1)]
 BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
                 (2, 1, 4, 4), (4, 2, 1, 2), (4, 1, 1, 2), (4, 2, 1, 4), (4, 4, 1, 2), (4, 2, 2, 2),
                 (4, 3, 1, 2)]
@@ -145,6 +146,41 @@ def test_front_chemical_potential_pass():
     g.close()
     ref = oracle.chemical_potential(w.spec, fields)
     assert np.max(np.abs(mu - ref)) <= 1e-5 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("nx", [70, 128])
+def test_front_held_and_ghost_corners_every_plan(nx):
+    """C held on some faces and fixed ghosts on others: the chemical
+    potential (not held) is evaluated on held cells, where a ghost beyond a
+    face must win over a held layer of another axis.  Every plan matches the
+    oracle's first pass and its steps."""
+    w = W.make_workload("front384", shape=(9, 10, nx))
+    spec = w.spec
+    spec.bc[2] = [(HELD, 0.3), (GHOST, 0.1), (GHOST, -0.2), (HELD, 0.4), (HELD, 0.5), (GHOST, 0.0)]
+    spec.bc[1] = [(GHOST, 0.2), (HELD, 0.6), (MIRROR, 0), (GHOST, 0.3), (MIRROR, 0), (HELD, 0.1)]
+    rng = np.random.default_rng(11)
+    fields = [f.astype(np.float32).astype(np.float64) for f in w.fields]
+    fields[2] = rng.uniform(-1.0, 1.0, w.shape).astype(np.float32).astype(np.float64)
+    w = W.Workload("front_corners", w.shape, spec, fields, 4, 0)
+    mu_ref = oracle.chemical_potential(spec, fields)
+    ref = oracle.run(spec, fields, 4)
+    base = None
+    for plan in compiled_plans(w, czs=(0, 4)):
+        g = rd.Grid(w.shape, 3, 1.0)
+        g.set_model(spec)
+        g.set_plan(**plan)
+        for s in range(3):
+            g.write(s, fields[s])
+        mu = g.chemical_potential().astype(np.float64)
+        g.close()
+        assert np.max(np.abs(mu - mu_ref)) <= 1e-5 * max(1.0, np.max(np.abs(mu_ref))), plan
+        got, _ = gpu_run(w, 4, plan=plan)
+        if base is None:
+            base = got
+            for s in range(3):
+                assert rel_l2(got[s], ref[s]) <= TOL, (plan, s)
+        for s in range(3):
+            assert np.array_equal(got[s], base[s]), (plan, s)
 
 
 def test_front_conserves_b_plus_c_on_gpu():
@@ -359,6 +395,37 @@ def test_held_and_ghost_faces_every_axis():
         if base is None:
             base = got
         assert all(np.array_equal(a, b) for a, b in zip(got, base)), plan
+
+
+@pytest.mark.parametrize("case", ["bruss256", "poll128", "front128", "faces128"])
+def test_whole_tile_rows_every_plan(case):
+    """Rows a whole number of x tiles long take the kernels' fast x-ghost
+    path (whole periodic rows, split rows, mirror / fixed faces, fixed and
+    held z planes); every plan agrees bit for bit and with the oracle."""
+    if case == "bruss256":
+        w = W.make_workload("brusselator256", shape=(9, 10, 256))
+    elif case == "poll128":
+        w = W.make_workload("pollutant512", shape=(10, 11, 128))
+    elif case == "front128":
+        w = W.make_workload("front384", shape=(12, 10, 128))
+    else:
+        shape = (10, 12, 128)
+        rng = np.random.default_rng(9)
+        faces = [(GHOST, 0.5), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0), (HELD, 0.25), (GHOST, -1.0)]
+        spec = bc_spec(2, faces)
+        w = W.Workload("faces128", shape, spec, [rng.uniform(0, 1, shape) for _ in range(2)], 6, 0)
+    steps = 6
+    ref = oracle.run(w.spec, w.fields, steps)
+    base = None
+    for plan in compiled_plans(w, czs=(0, 4, 7)):
+        got, _ = gpu_run(w, steps, plan=plan)
+        if base is None:
+            base = got
+            for s in range(w.spec.ns):
+                assert rel_l2(got[s], ref[s]) <= TOL, (case, s)
+            continue
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], base[s]), (case, plan, s)
 
 
 def test_zero_steps_is_identity():
