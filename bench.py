@@ -48,8 +48,9 @@ def kernel_source_digest() -> str:
 
 
 def measured_traffic(name: str, digest: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current kernel sources; else None."""
+    """HBM bytes per step (per launch for a one-kernel step) from the
+    committed rocprofv3 PMC summary, if it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(PROFILES, "%s_pmc.json" % name)
     try:
         with open(path) as fh:
@@ -58,7 +59,7 @@ def measured_traffic(name: str, digest: str):
         return None
     if rec.get("source_digest") != digest:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("hbm_bytes_per_step")
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -78,6 +79,9 @@ def cpu_baseline(w, budget_s: float = 12.0):
                       % (w.name, w.shape[2], w.shape[1], w.shape[0], steps)}
 
 
+COPY_PROBE_BYTES = 2 * 256 * 1024 * 1024    # copy-ceiling probe: bytes read (and written)
+
+
 def copy_ceiling(torch, stream, nbytes: int, reps: int = 10):
     from paper_1004_0480_amd import rd
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -94,6 +98,128 @@ def copy_ceiling(torch, stream, nbytes: int, reps: int = 10):
     ms = e0.elapsed_time(e1) / reps
     del src, dst
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+# ------------------------------------------------ profile summaries (rocprofv3)
+
+STEP_KERNELS = ("rdk::block_kernel", "rdk::tiled_kernel", "rdk::direct_kernel")
+
+
+def _counter_rows(d: str):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no *counter_collection.csv under %s" % d)
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, counter: str, match):
+    vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and match(r["Kernel_Name"])]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def _step_kernels(rows):
+    """Step kernels of the run: every kernel family that runs once per step
+    (the most frequent dispatch count among them)."""
+    names = {}
+    for r in rows:
+        if any(k in r["Kernel_Name"] for k in STEP_KERNELS):
+            names[r["Kernel_Name"]] = names.get(r["Kernel_Name"], 0) + 1
+    if not names:
+        raise SystemExit("no step kernel dispatches in the counter output")
+    top = max(names.values())
+    return sorted(n for n, c in names.items() if c == top)
+
+
+def pmc_summary(args):
+    """profiles/<workload>_pmc.json from two rocprofv3 --pmc runs of this
+    script (FETCH_SIZE, then WRITE_SIZE).  Both counters are read in KiB per
+    dispatch and scaled by what they read for the copy kernel of the same run,
+    which moves a known number of bytes each way.  A step of several passes
+    sums its kernels."""
+    from paper_1004_0480_amd import workloads as W
+    fetch_rows, write_rows = _counter_rows(args.pmc_summary[0]), _counter_rows(args.pmc_summary[1])
+    knames = _step_kernels(fetch_rows)
+    is_copy = lambda n: n.startswith("rdk::copy_kernel")
+    f_c, _ = _per_dispatch(fetch_rows, "FETCH_SIZE", is_copy)
+    w_c, _ = _per_dispatch(write_rows, "WRITE_SIZE", is_copy)
+    if None in (f_c, w_c):
+        raise SystemExit("missing counter values for the copy kernel")
+    copy_bytes = float(COPY_PROBE_BYTES)
+    rs, ws = copy_bytes / (f_c * 1024.0), copy_bytes / (w_c * 1024.0)
+    per_kernel, rd_b, wr_b = [], 0.0, 0.0
+    for k in knames:
+        f_k, nf = _per_dispatch(fetch_rows, "FETCH_SIZE", lambda n: n == k)
+        w_k, nw = _per_dispatch(write_rows, "WRITE_SIZE", lambda n: n == k)
+        if None in (f_k, w_k):
+            raise SystemExit("missing counter values for %s" % k)
+        per_kernel.append({"kernel": k, "dispatches": {"FETCH_SIZE": nf, "WRITE_SIZE": nw},
+                           "fetch_kib_raw": f_k, "write_kib_raw": w_k,
+                           "hbm_read_bytes": f_k * 1024.0 * rs, "hbm_write_bytes": w_k * 1024.0 * ws})
+        rd_b += f_k * 1024.0 * rs
+        wr_b += w_k * 1024.0 * ws
+    cells = int(np.prod(W.DEFAULT_SHAPES[args.workload]))
+    alg = alg_bytes_per_cell(args.workload, args.storage) * cells
+    rec = {"kernel": knames[0] if len(knames) == 1 else knames,
+           "workload": "%s %s, %s storage" % (args.workload, W.DEFAULT_SHAPES[args.workload], args.storage),
+           "source_digest": kernel_source_digest(), "command": args.pmc_command,
+           "per_kernel": per_kernel,
+           "calibration": "copy_kernel moving %d bytes each way in the same run" % COPY_PROBE_BYTES,
+           "copy_fetch_kib_raw": f_c, "copy_write_kib_raw": w_c, "read_scale": rs, "write_scale": ws,
+           "hbm_read_bytes_per_step": rd_b, "hbm_write_bytes_per_step": wr_b,
+           "hbm_bytes_per_launch": (rd_b + wr_b) if len(knames) == 1 else None,
+           "hbm_bytes_per_step": rd_b + wr_b, "algorithmic_bytes_per_step": alg,
+           "traffic_over_algorithmic": (rd_b + wr_b) / alg}
+    out = os.path.join(PROFILES, "%s_pmc.json" % args.workload)
+    with open(out, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def trace_summary(args):
+    """profiles/<workload>_kernel_trace.md from a rocprofv3 --kernel-trace
+    --stats run of this script: the per-kernel table and the step kernel's
+    bandwidth at its traced average duration."""
+    import csv
+    import glob
+    from paper_1004_0480_amd import workloads as W
+    files = glob.glob(os.path.join(args.trace_summary, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no *kernel_stats.csv under %s" % args.trace_summary)
+    with open(files[0]) as fh:
+        rows = list(csv.DictReader(fh))
+    cells = int(np.prod(W.DEFAULT_SHAPES[args.workload]))
+    bpc = alg_bytes_per_cell(args.workload, args.storage)
+    lines = ["# rocprofv3 kernel trace: %s step kernel (MI355X)" % args.workload, "",
+             "Workload: %s, grid (z, y, x) = %s, %s storage." % (args.workload, W.DEFAULT_SHAPES[args.workload],
+                                                                 args.storage),
+             "", "Command:", "", "```", args.trace_command, "```", "",
+             "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+    step = None
+    for r in rows:
+        name = r["Name"]
+        avg = float(r["AverageNs"]) / 1e3
+        lines.append("| `%s` | %s | %.2f | %.2f | %.2f | %.2f%% |" % (
+            name[:100], r["Calls"], avg, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+            float(r["Percentage"])))
+        if step is None and any(k in name for k in STEP_KERNELS):
+            step = (name, avg)
+    lines.append("")
+    if step:
+        gbs = bpc * cells / (step[1] * 1e-6) / 1e9
+        lines += ["Step kernel `%s`: %d B/cell algorithmic x %d cells = %.1f MB per launch; at the traced"
+                  % (step[0][:80], bpc, cells, bpc * cells / 1e6),
+                  "average %.2f us that is %.0f GB/s, %.1f%% of the 8 TB/s HBM peak."
+                  % (step[1], gbs, 100.0 * gbs / HBM_PEAK_GBS)]
+    out = os.path.join(PROFILES, "%s_kernel_trace.md" % args.workload)
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def serve_bench(args):
@@ -152,7 +278,17 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--plan", default=None,
                     help="JSON plan (kernel, vx, ry, waves, cz) to use instead of autotuning")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/<workload>_pmc.json from rocprofv3 --pmc outputs")
+    ap.add_argument("--pmc-command", default="", help="the profiling command, recorded in the summary")
+    ap.add_argument("--trace-summary", metavar="STATS_DIR",
+                    help="write profiles/<workload>_kernel_trace.md from rocprofv3 --stats output")
+    ap.add_argument("--trace-command", default="", help="the profiling command, recorded in the summary")
     args = ap.parse_args()
+    if args.pmc_summary:
+        return pmc_summary(args)
+    if args.trace_summary:
+        return trace_summary(args)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
@@ -205,25 +341,25 @@ def main():
         g.reduce(s)
 
     bpc = alg_bytes_per_cell(w.name, args.storage)
-    launches_per_step = 2 if w.name == "front384" else 1
-    # dominant kernel: the (only, or second) step kernel; its average duration
-    # is the event-timed step time (one launch per step for single-pass models)
-    kernel_ms = ms_per_step if launches_per_step == 1 else None
-    achieved = (bpc * w.cells / (ms_per_step * 1e-3) / 1e9) if kernel_ms else None
+    launches_per_step = g.passes()
+    # dominant kernel: the step kernel.  With one pass per step its average
+    # launch duration is the event-timed step time; a step of several passes
+    # is reported per step (all its kernels together).
+    achieved = bpc * w.cells / (ms_per_step * 1e-3) / 1e9
     digest = kernel_source_digest()
     traffic = measured_traffic(w.name, digest)
-    ceiling = copy_ceiling(torch, stream, 2 * 256 * 1024 * 1024)
+    ceiling = copy_ceiling(torch, stream, COPY_PROBE_BYTES)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
-            "kernel_avg_ms": kernel_ms, "alg_bytes_per_cell": bpc,
-            "copy_ceiling_GBs": ceiling,
-            "frac_of_copy_ceiling": (achieved / ceiling) if achieved else None,
-            "source_digest": digest}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "per": "launch" if launches_per_step == 1 else "step (%d kernels)" % launches_per_step,
+            "kernel_avg_ms": ms_per_step / launches_per_step if launches_per_step == 1 else None,
+            "alg_bytes_per_cell": bpc, "copy_ceiling_GBs": ceiling,
+            "frac_of_copy_ceiling": achieved / ceiling, "source_digest": digest}
     out = {
         "metric": "Gcell-updates/s", "value": value, "unit": "Gcell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
                    "species": w.spec.ns, "storage": args.storage, "dt": w.spec.dt,
                    "plan": plan, "wall_s": wall},

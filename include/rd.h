@@ -206,6 +206,13 @@ int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t nspecies, doub
 int rd_set_plan(rd_grid *g, const rd_plan *p);   /* RD_EINVAL if unsupported */
 int rd_get_plan(const rd_grid *g, rd_plan *p);   /* the plan rd_step uses    */
 
+/* Kernel launches per step of the grid's model (*out): 1, or 2 for the
+ * front model (chemical-potential pass, then the update) and for more than
+ * two pollutants (the coupled pair, then the rest: species groups that share
+ * no term, section 2's Eq. (5) evaluated group by group).  RD_ESTATE
+ * without a model. */
+int rd_get_passes(const rd_grid *g, int32_t *out);
+
 /* Time candidate plans on this grid (trial_steps steps each, hipEvents on the
  * grid's stream), keep the fastest, store it in a per-process cache keyed by
  * shape, species, model and storage, and return it in *best.  The grid's state

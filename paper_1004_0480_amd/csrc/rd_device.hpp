@@ -44,6 +44,7 @@ struct StepArgs {
     const int* src_x;             // x of each source
     const int* src_sp;            // species of each source
     const float* src_rate;        // emission rate (duplicates merged)
+    int sp0;                      // species of field 0 (source species are global)
     int tiles_x, tiles_y, chunks_z, cz;   // tiled decomposition
     int zfast;                    // slab enumeration: z chunk fastest
 };
@@ -101,13 +102,33 @@ struct StF64 {
     static __device__ __forceinline__ float up(T v) { return float(v); }
 };
 
+// Field and table pointers reach the kernels inside the argument block in
+// device memory, so the compiler sees generic pointers and would emit flat
+// accesses, which also count against the LDS / scalar-load counter: every
+// LDS exchange or scalar load would then wait for all loads in flight.  They
+// always point to global memory; these casts say so.  (The host pass of the
+// compiler only parses this code; it gets no address space.)
+#ifdef __HIP_DEVICE_COMPILE__
+#define RD_GLOBAL __attribute__((address_space(1)))
+#else
+#define RD_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ const RD_GLOBAL T* gload_ptr(const void* p) {
+    return (const RD_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ RD_GLOBAL T* gstore_ptr(void* p) {
+    return (RD_GLOBAL T*)p;
+}
+
 // N contiguous elements of type T as one naturally aligned access.
 template <typename T, int N> struct alignas(sizeof(T) * N) Vec { T v[N]; };
 
 template <class S, int VX>
 __device__ __forceinline__ void load_vec(const void* base, long long idx, float (&o)[VX]) {
     using T = typename S::T;
-    const Vec<T, VX> r = *reinterpret_cast<const Vec<T, VX>*>(static_cast<const T*>(base) + idx);
+    const Vec<T, VX> r = *(const RD_GLOBAL Vec<T, VX>*)(gload_ptr<T>(base) + idx);
 #pragma unroll
     for (int i = 0; i < VX; ++i) o[i] = S::up(r.v[i]);
 }
@@ -118,30 +139,28 @@ __device__ __forceinline__ void store_vec(void* base, long long idx, const float
     Vec<T, VX> r;
 #pragma unroll
     for (int i = 0; i < VX; ++i) r.v[i] = S::down(o[i]);
+    RD_GLOBAL T* dst = gstore_ptr<T>(base) + idx;
 #if RD_NT_STORE
     // streaming store: the next step reads these values from HBM anyway
     if constexpr (sizeof(r) == 16) {
         typedef unsigned v4u __attribute__((ext_vector_type(4)));
-        __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(&r),
-                                    reinterpret_cast<v4u*>(static_cast<T*>(base) + idx));
+        __builtin_nontemporal_store(*reinterpret_cast<const v4u*>(&r), (RD_GLOBAL v4u*)dst);
     } else if constexpr (sizeof(r) == 8) {
         typedef unsigned v2u __attribute__((ext_vector_type(2)));
-        __builtin_nontemporal_store(*reinterpret_cast<const v2u*>(&r),
-                                    reinterpret_cast<v2u*>(static_cast<T*>(base) + idx));
+        __builtin_nontemporal_store(*reinterpret_cast<const v2u*>(&r), (RD_GLOBAL v2u*)dst);
     } else if constexpr (sizeof(r) == 4) {
-        __builtin_nontemporal_store(*reinterpret_cast<const unsigned*>(&r),
-                                    reinterpret_cast<unsigned*>(static_cast<T*>(base) + idx));
+        __builtin_nontemporal_store(*reinterpret_cast<const unsigned*>(&r), (RD_GLOBAL unsigned*)dst);
     } else {
-        *reinterpret_cast<Vec<T, VX>*>(static_cast<T*>(base) + idx) = r;
+        *(RD_GLOBAL Vec<T, VX>*)dst = r;
     }
 #else
-    *reinterpret_cast<Vec<T, VX>*>(static_cast<T*>(base) + idx) = r;
+    *(RD_GLOBAL Vec<T, VX>*)dst = r;
 #endif
 }
 
 template <class S>
 __device__ __forceinline__ float load1(const void* base, long long idx) {
-    return S::up(static_cast<const typename S::T*>(base)[idx]);
+    return S::up(gload_ptr<typename S::T>(base)[idx]);
 }
 
 // --------------------------------------------------------- cell arithmetic
@@ -229,8 +248,10 @@ struct FrontCH {
 };
 
 // Advection-diffusion of NS pollutants: upwind wind along +x (u(z)/h given),
-// first-order decay p[0], transfer p[1] from species 0 to species 1, sources.
-template <int NS> struct Pollutant {
+// first-order decay p[0], and (COUPLED) transfer p[1] from field 0 to field
+// 1, plus point sources.  A step of more species runs as several passes over
+// groups that share no term: the coupled pair, then the others.
+template <int NS, bool COUPLED> struct Pollutant {
     static constexpr int NF = NS, NO = NS;
     static constexpr bool SOURCES = true;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
@@ -244,8 +265,8 @@ template <int NS> struct Pollutant {
             float rate = lap7(n[s], a.kx[s], a.ky[s], a.kz[s]);
             rate = __fmaf_rn(uh, n[s].xm - c, rate);       // -u (c_i - c_{i-1}) / h
             rate = __fmaf_rn(-a.p[0], c, rate);             // decay
-            if (NS >= 2 && s == 0) rate = __fmaf_rn(-a.p[1], c0, rate);
-            if (NS >= 2 && s == 1) rate = __fmaf_rn(a.p[1], c0, rate);
+            if (COUPLED && NS >= 2 && s == 0) rate = __fmaf_rn(-a.p[1], c0, rate);
+            if (COUPLED && NS >= 2 && s == 1) rate = __fmaf_rn(a.p[1], c0, rate);
             if (has_e) rate = rate + e[s];
             o[s] = __fmaf_rn(a.dt, rate, c);
         }
@@ -286,17 +307,37 @@ __device__ __forceinline__ float fixed_or(const Src& sx, const Src& sy, const Sr
          : sx.cst ? sx.v : sy.cst ? sy.v : sz.cst ? sz.v : v;
 }
 
-// Value of field f at (x, y, z), where a coordinate may lie one cell outside
-// the grid: each axis is resolved by its face rules, one load is made from
-// the resolved (always valid) address, and a value fixed by a rule replaces
-// it.  Written as value selects so that no address depends on the rules.
+// The 7 stencil values of field f around in-range (x, y, z).  Each axis is
+// resolved by its face rules (the centre's resolution serves the two axes a
+// neighbour does not move along), one load is made from every resolved
+// (always valid) address, and a value fixed by a rule replaces it.  Written
+// as value selects so that no address depends on the rules.
 template <class S>
-__device__ __forceinline__ float stencil_value(const StepArgs& a, int f, int x, int y, int z) {
-    const Src sx = resolve_axis(x, a.nx, a.bck[f][0], a.bck[f][1], a.bcv[f][0], a.bcv[f][1]);
-    const Src sy = resolve_axis(y, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
-    const Src sz = resolve_axis(z, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
-    const float v = load1<S>(a.in[f], (long long)sz.idx * a.plane + (long long)sy.idx * a.pitch + sx.idx);
-    return fixed_or(sx, sy, sz, v);
+__device__ __forceinline__ Nb stencil(const StepArgs& a, int f, int x, int y, int z) {
+    const int* k = a.bck[f];
+    const float* v = a.bcv[f];
+    const Src sx = resolve_axis(x, a.nx, k[0], k[1], v[0], v[1]);
+    const Src sy = resolve_axis(y, a.ny, k[2], k[3], v[2], v[3]);
+    const Src sz = resolve_axis(z, a.nz, k[4], k[5], v[4], v[5]);
+    const Src xm = resolve_axis(x - 1, a.nx, k[0], k[1], v[0], v[1]);
+    const Src xp = resolve_axis(x + 1, a.nx, k[0], k[1], v[0], v[1]);
+    const Src ym = resolve_axis(y - 1, a.ny, k[2], k[3], v[2], v[3]);
+    const Src yp = resolve_axis(y + 1, a.ny, k[2], k[3], v[2], v[3]);
+    const Src zm = resolve_axis(z - 1, a.nz, k[4], k[5], v[4], v[5]);
+    const Src zp = resolve_axis(z + 1, a.nz, k[4], k[5], v[4], v[5]);
+    auto at = [&](const Src& qx, const Src& qy, const Src& qz) {
+        const float u = load1<S>(a.in[f], (long long)qz.idx * a.plane + (long long)qy.idx * a.pitch + qx.idx);
+        return fixed_or(qx, qy, qz, u);
+    };
+    Nb n;
+    n.c = at(sx, sy, sz);
+    n.xm = at(xm, sy, sz);
+    n.xp = at(xp, sy, sz);
+    n.ym = at(sx, ym, sz);
+    n.yp = at(sx, yp, sz);
+    n.zm = at(sx, sy, zm);
+    n.zp = at(sx, sy, zp);
+    return n;
 }
 
 // Merged emission rates of the cell at x of a row whose sources are
@@ -314,11 +355,11 @@ __device__ __forceinline__ Emission<NO> cell_sources(const StepArgs& a, int x, i
     for (int s = 0; s < NO; ++s) r.e[s] = 0.f;
     r.any = false;
     for (int q = s0; q < s1; ++q) {
-        if (a.src_x[q] == x) {
-            const int sp = a.src_sp[q];
-            const float rate = a.src_rate[q];
+        if (gload_ptr<int>(a.src_x)[q] == x) {
+            const int sp = gload_ptr<int>(a.src_sp)[q];
+            const float rate = gload_ptr<float>(a.src_rate)[q];
 #pragma unroll
-            for (int s = 0; s < NO; ++s) r.e[s] = sp == s ? rate : r.e[s];
+            for (int s = 0; s < NO; ++s) r.e[s] = sp - a.sp0 == s ? rate : r.e[s];
             r.any = true;
         }
     }
@@ -354,39 +395,21 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
     if (x >= a.nx || y >= a.ny) return;
     Nb n[M::NF];
 #pragma unroll
-    for (int f = 0; f < M::NF; ++f) {
-        if (M::f32_field(f)) {
-            n[f].c = stencil_value<StF32>(a, f, x, y, z);
-            n[f].xm = stencil_value<StF32>(a, f, x - 1, y, z);
-            n[f].xp = stencil_value<StF32>(a, f, x + 1, y, z);
-            n[f].ym = stencil_value<StF32>(a, f, x, y - 1, z);
-            n[f].yp = stencil_value<StF32>(a, f, x, y + 1, z);
-            n[f].zm = stencil_value<StF32>(a, f, x, y, z - 1);
-            n[f].zp = stencil_value<StF32>(a, f, x, y, z + 1);
-        } else {
-            n[f].c = stencil_value<S>(a, f, x, y, z);
-            n[f].xm = stencil_value<S>(a, f, x - 1, y, z);
-            n[f].xp = stencil_value<S>(a, f, x + 1, y, z);
-            n[f].ym = stencil_value<S>(a, f, x, y - 1, z);
-            n[f].yp = stencil_value<S>(a, f, x, y + 1, z);
-            n[f].zm = stencil_value<S>(a, f, x, y, z - 1);
-            n[f].zp = stencil_value<S>(a, f, x, y, z + 1);
-        }
-    }
+    for (int f = 0; f < M::NF; ++f) n[f] = M::f32_field(f) ? stencil<StF32>(a, f, x, y, z) : stencil<S>(a, f, x, y, z);
     Emission<M::NO> em{};
     if (M::SOURCES) {
         const int r = z * a.ny + y;
-        em = cell_sources<M::NO>(a, x, a.src_row[r], a.src_row[r + 1]);
+        em = cell_sources<M::NO>(a, x, gload_ptr<int>(a.src_row)[r], gload_ptr<int>(a.src_row)[r + 1]);
     }
-    const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+    const float uh = M::SOURCES ? gload_ptr<float>(a.wind_h)[z] : 0.f;
     float o[M::NO];
     M::cell(a, n, uh, em.any, em.e, o);
     const long long idx = (long long)z * a.plane + (long long)y * a.pitch + x;
 #pragma unroll
     for (int s = 0; s < M::NO; ++s) {
         const float v = held_out(a, s, x, y, z, o[s]);
-        if (M::f32_out(s)) static_cast<float*>(a.out[s])[idx] = v;
-        else static_cast<typename S::T*>(a.out[s])[idx] = S::down(v);
+        if (M::f32_out(s)) gstore_ptr<float>(a.out[s])[idx] = v;
+        else gstore_ptr<typename S::T>(a.out[s])[idx] = S::down(v);
     }
 }
 
@@ -567,7 +590,7 @@ __device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64
                 dn[f][i] = h[f][NH - 1][i];
             }
     }
-    const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+    const float uh = M::SOURCES ? gload_ptr<float>(a.wind_h)[z] : 0.f;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int y = y0 + r;
@@ -620,8 +643,8 @@ __device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64
         }
         int s0 = 0, s1 = 0;
         if (M::SOURCES && y < a.ny) {
-            s0 = a.src_row[z * a.ny + y];
-            s1 = a.src_row[z * a.ny + y + 1];
+            s0 = gload_ptr<int>(a.src_row)[z * a.ny + y];
+            s1 = gload_ptr<int>(a.src_row)[z * a.ny + y + 1];
         }
         float o[NO][VX];
 #pragma unroll
@@ -647,21 +670,41 @@ __device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64
     }
 }
 
+// The slab body keeps its own copy of the per-plane cell code (the same
+// arithmetic as plane_cells, field-major register arrays): the generated code
+// of this form is measurably faster for the slab kernel.
 template <class M, class S, int VX, int RY, int W, int CZ, bool FAST>
 __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 64 * VX>& sm, int lane, int w,
                                               int x0, int yb, int y0, int z0, int xl, bool whole_row,
                                               const Src (&rs)[M::NF][RY], const Src (&rh)[M::NF][W == 1 ? 2 : 1],
                                               const Src (&ps)[M::NF][CZ + 2]) {
-    constexpr int NF = M::NF, TX = 64 * VX, NP = CZ + 2;
+    constexpr int NF = M::NF, NO = M::NO, TX = 64 * VX, NP = CZ + 2;
     constexpr int NH = W == 1 ? 2 : 1;
     const bool edge_wave = W == 1 || w == 0 || w == W - 1;
+
+    // x sides of this tile, per field
     int xsl[NF], xsr[NF];
-    const bool need_edges = x_sides<M, FAST>(a, x0, TX, whole_row, xsl, xsr);
+    bool need_edges = false;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int klo = a.bck[f][0], khi = a.bck[f][1];
+        const bool left_face = x0 == 0, right_face = x0 + TX >= a.nx;
+        if (!FAST || whole_row) {
+            // general path (and whole rows): sides from the face rule
+            xsl[f] = klo == BC_MIRROR ? XS_OWN : klo == BC_PERIODIC ? XS_ROT : XS_CONST;
+            xsr[f] = khi == BC_MIRROR ? XS_OWN : khi == BC_PERIODIC ? XS_ROT : XS_CONST;
+        }
+        if (!whole_row) {
+            xsl[f] = !left_face ? XS_EDGE : klo == BC_MIRROR ? XS_OWN : klo == BC_PERIODIC ? XS_EDGE : XS_CONST;
+            xsr[f] = !right_face ? XS_EDGE : khi == BC_MIRROR ? XS_OWN : khi == BC_PERIODIC ? XS_EDGE : XS_CONST;
+        }
+        need_edges = need_edges || xsl[f] == XS_EDGE || xsr[f] == XS_EDGE;
+    }
 
     // issue every load of the slab
-    float V[NP][NF][RY][VX];
-    float H[CZ][NF][NH][VX];
-    float E[CZ][NF][RY];
+    float V[NF][NP][RY][VX];
+    float H[NF][CZ][NH][VX];
+    float E[NF][CZ][RY];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -669,7 +712,7 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
             for (int r = 0; r < RY; ++r)
                 load_raw<M, S, VX>(a, f, (long long)ps[f][k].idx * a.plane +
-                                             (long long)rs[f][r].idx * a.pitch + xl, V[k][f][r]);
+                                             (long long)rs[f][r].idx * a.pitch + xl, V[f][k][r]);
     if (edge_wave) {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
@@ -678,9 +721,9 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
                 for (int h = 0; h < NH; ++h)
                     load_raw<M, S, VX>(a, f, (long long)ps[f][k + 1].idx * a.plane +
-                                                 (long long)rh[f][h].idx * a.pitch + xl, H[k][f][h]);
+                                                 (long long)rh[f][h].idx * a.pitch + xl, H[f][k][h]);
     }
-    if (need_edges) {
+    if (!FAST ? !whole_row : need_edges) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int q = lane == 0 ? x0 - 1 : min(x0 + TX, a.nx);
@@ -689,11 +732,11 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
             for (int k = 0; k < CZ; ++k)
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
-                    E[k][f][r] = 0.f;
+                    E[f][k][r] = 0.f;
                     if (lane == 0 || lane == 63) {
                         const long long idx = (long long)ps[f][k + 1].idx * a.plane +
                                               (long long)rs[f][r].idx * a.pitch + sxi;
-                        E[k][f][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
+                        E[f][k][r] = M::f32_field(f) ? load1<StF32>(a.in[f], idx) : load1<S>(a.in[f], idx);
                     }
                 }
         }
@@ -714,12 +757,12 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
                 for (int k = 0; k < NP; ++k)
 #pragma unroll
-                    for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, ps[f][k], rs[f][r], xl, V[k][f][r]);
+                    for (int r = 0; r < RY; ++r) fix_row<VX>(a, f, ps[f][k], rs[f][r], xl, V[f][k][r]);
                 if (edge_wave) {
 #pragma unroll
                     for (int k = 0; k < CZ; ++k)
 #pragma unroll
-                        for (int h = 0; h < NH; ++h) fix_row<VX>(a, f, ps[f][k + 1], rh[f][h], xl, H[k][f][h]);
+                        for (int h = 0; h < NH; ++h) fix_row<VX>(a, f, ps[f][k + 1], rh[f][h], xl, H[f][k][h]);
                 }
             }
             if (!whole_row) {
@@ -729,7 +772,7 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
                 for (int k = 0; k < CZ; ++k)
 #pragma unroll
                     for (int r = 0; r < RY; ++r) {
-                        E[k][f][r] = fixed_or(sx, rs[f][r], ps[f][k + 1], E[k][f][r]);
+                        E[f][k][r] = fixed_or(sx, rs[f][r], ps[f][k + 1], E[f][k][r]);
                     }
             }
         }
@@ -738,9 +781,122 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
     for (int k = 1; k <= CZ; ++k) {
         const int z = z0 + k - 1;
-        if (z < a.nz)
-            plane_cells<M, S, VX, RY, W, FAST>(a, sm, k & 1, lane, w, xl, y0, z, whole_row, !FAST, xsl, xsr,
-                                               V[k - 1], V[k], V[k + 1], H[k - 1], E[k - 1]);
+        if (z < a.nz) {
+            float up[NF][VX], dn[NF][VX];
+            if (W > 1) {
+                const int par = k & 1;
+                constexpr int EXP = BlockLds<M, W, TX>::EXP;
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        if (EXP == 1) {
+                            sm.row[par][f][w][0][lane * VX + i] = w == 0 ? V[f][k][RY - 1][i] : V[f][k][0][i];
+                        } else {
+                            sm.row[par][f][w][0][lane * VX + i] = V[f][k][0][i];
+                            sm.row[par][f][w][EXP - 1][lane * VX + i] = V[f][k][RY - 1][i];
+                        }
+                    }
+                __syncthreads();
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        up[f][i] = w > 0 ? sm.row[par][f][w > 0 ? w - 1 : 0][EXP - 1][lane * VX + i]
+                                         : H[f][k - 1][0][i];
+                        dn[f][i] = w < W - 1 ? sm.row[par][f][w < W - 1 ? w + 1 : 0][0][lane * VX + i]
+                                             : H[f][k - 1][0][i];
+                    }
+            } else {
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        up[f][i] = H[f][k - 1][0][i];
+                        dn[f][i] = H[f][k - 1][NH - 1][i];
+                    }
+            }
+            const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+#pragma unroll
+            for (int r = 0; r < RY; ++r) {
+                const int y = y0 + r;
+                Nb n[NF][VX];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const float (&v)[VX] = V[f][k][r];
+                    float left, right, R = 0.f;
+                    if (FAST) {
+                        // fill value of lane 0 (left) / lane 63 (right): no lane reads
+                        if (xsl[f] == XS_ROT) {
+                            left = lane_from_left_wrap(v[VX - 1]);
+                        } else {
+                            const float fl = xsl[f] == XS_OWN ? v[0] : xsl[f] == XS_CONST ? a.bcv[f][0]
+                                                                                          : E[f][k - 1][r];
+                            left = lane_from_left(v[VX - 1], fl);
+                        }
+                        if (xsr[f] == XS_ROT) {
+                            right = lane_from_right_wrap(v[0]);
+                        } else {
+                            const float fr = xsr[f] == XS_OWN ? v[VX - 1] : xsr[f] == XS_CONST ? a.bcv[f][1]
+                                                                                               : E[f][k - 1][r];
+                            right = lane_from_right(v[0], fr);
+                        }
+                    } else {
+                        float L;
+                        if (whole_row) {
+                            const int klo = a.bck[f][0], khi = a.bck[f][1];
+                            const float first = bcast_lane(v[0], 0);
+                            const float last = row_element<VX>(v, a.nx - 1);
+                            L = klo == BC_MIRROR ? first : klo == BC_PERIODIC ? last : a.bcv[f][0];
+                            R = khi == BC_MIRROR ? last : khi == BC_PERIODIC ? first : a.bcv[f][1];
+                        } else {
+                            L = bcast_lane(E[f][k - 1][r], 0);
+                            R = bcast_lane(E[f][k - 1][r], 63);
+                        }
+                        left = lane_from_left(v[VX - 1], L);
+                        right = lane_from_right(v[0], R);
+                    }
+#pragma unroll
+                    for (int i = 0; i < VX; ++i) {
+                        Nb& q = n[f][i];
+                        q.c = v[i];
+                        q.xm = i > 0 ? v[i - 1] : left;
+                        q.xp = i < VX - 1 ? v[i + 1] : right;
+                        if (!FAST && xl + i == a.nx - 1) q.xp = R;
+                        q.ym = r > 0 ? V[f][k][r - 1][i] : up[f][i];
+                        q.yp = r < RY - 1 ? V[f][k][r + 1][i] : dn[f][i];
+                        q.zm = V[f][k - 1][r][i];
+                        q.zp = V[f][k + 1][r][i];
+                    }
+                }
+                int s0 = 0, s1 = 0;
+                if (M::SOURCES && y < a.ny) {
+                    s0 = a.src_row[z * a.ny + y];
+                    s1 = a.src_row[z * a.ny + y + 1];
+                }
+                float o[NO][VX];
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    Nb ni[NF];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) ni[f] = n[f][i];
+                    Emission<NO> em{};
+                    if (M::SOURCES && s0 < s1) em = cell_sources<NO>(a, xl + i, s0, s1);
+                    float oi[NO];
+                    M::cell(a, ni, uh, em.any, em.e, oi);
+#pragma unroll
+                    for (int s = 0; s < NO; ++s) o[s][i] = FAST ? oi[s] : held_out(a, s, xl + i, y, z, oi[s]);
+                }
+                if (y < a.ny && xl < a.nx) {
+                    const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
+#pragma unroll
+                    for (int s = 0; s < NO; ++s) {
+                        if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
+                        else store_vec<S, VX>(a.out[s], idx, o[s]);
+                    }
+                }
+            }
+        }
     }
 }
 

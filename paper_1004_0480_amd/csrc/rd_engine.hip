@@ -44,13 +44,33 @@ size_t field_elems(int64_t nx, int64_t ny, int64_t nz) {
 }
 bool is_finite(double v) { return std::isfinite(v); }
 
-int pm_of(int model, int ns) {
+// Species of a single-field-group model split into passes that share no
+// term, so that each pass carries few fields: the pollutant's coupled pair
+// (transfer from the first to the second) is one pass, the remaining species
+// another.  Every pass reads the old state only, so their order is free.
+struct PassGroups {
+    int n = 0;
+    int first[2] = {0, 0}, count[2] = {0, 0}, pm[2] = {-1, -1};
+};
+
+PassGroups pass_groups(int model, int ns) {
+    PassGroups p;
+    auto add = [&](int first, int count, int pm) {
+        p.first[p.n] = first;
+        p.count[p.n] = count;
+        p.pm[p.n] = pm;
+        ++p.n;
+    };
     switch (model) {
-    case RD_MODEL_DIFFUSION: return PM_DIFF1 + (ns - 1);
-    case RD_MODEL_BRUSSELATOR: return PM_BRUSS;
-    case RD_MODEL_POLLUTANT: return PM_POLL1 + (ns - 1);
-    default: return -1;
+    case RD_MODEL_DIFFUSION: add(0, ns, PM_DIFF1 + (ns - 1)); break;
+    case RD_MODEL_BRUSSELATOR: add(0, 2, PM_BRUSS); break;
+    case RD_MODEL_POLLUTANT:
+        add(0, ns >= 2 ? 2 : 1, ns >= 2 ? PM_POLL2 : PM_POLL1);
+        if (ns >= 3) add(2, ns - 2, ns == 3 ? PM_POLL1 : PM_POLL2U);
+        break;
+    default: break;
     }
+    return p;
 }
 
 int num_cus() {
@@ -573,6 +593,7 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
         RD_HIP(hipMemset(g->aux, 0, g->elems * sizeof(float)));
     }
 
+    const PassGroups groups = pass_groups(m->model, ns);
     for (int par = 0; par < 2; ++par) {
         for (int k = 0; k < 2; ++k) {
             StepArgs& a = g->args[par][k];
@@ -619,23 +640,29 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
                 a.p[4] = float(m->param[4]);   // gamma
             }
         } else {
-            StepArgs& a = g->args[par][0];
-            for (int s = 0; s < ns; ++s) {
-                a.in[s] = g->buf[par][s];
-                a.out[s] = g->buf[par ^ 1][s];
-                a.kx[s] = float(m->diff[s][0] * ih2);
-                a.ky[s] = float(m->diff[s][1] * ih2);
-                a.kz[s] = float(m->diff[s][2] * ih2);
-                fill_bc(a, s, m, s);
-                a.out_held[s] = a.held[s];
-            }
-            if (m->model == RD_MODEL_BRUSSELATOR) {
-                a.p[0] = float(m->param[0]);
-                a.p[1] = float(m->param[1]);
-                a.p[2] = float(-(m->param[1] + 1.0));
-            } else if (m->model == RD_MODEL_POLLUTANT) {
-                a.p[0] = float(m->param[0]);
-                a.p[1] = float(m->param[1]);
+            // one pass per group of species that share a term (see pass_groups)
+            for (int k = 0; k < groups.n; ++k) {
+                StepArgs& a = g->args[par][k];
+                const int s0 = groups.first[k];
+                for (int f = 0; f < groups.count[k]; ++f) {
+                    const int s = s0 + f;
+                    a.in[f] = g->buf[par][s];
+                    a.out[f] = g->buf[par ^ 1][s];
+                    a.kx[f] = float(m->diff[s][0] * ih2);
+                    a.ky[f] = float(m->diff[s][1] * ih2);
+                    a.kz[f] = float(m->diff[s][2] * ih2);
+                    fill_bc(a, f, m, s);
+                    a.out_held[f] = a.held[f];
+                }
+                a.sp0 = s0;
+                if (m->model == RD_MODEL_BRUSSELATOR) {
+                    a.p[0] = float(m->param[0]);
+                    a.p[1] = float(m->param[1]);
+                    a.p[2] = float(-(m->param[1] + 1.0));
+                } else if (m->model == RD_MODEL_POLLUTANT) {
+                    a.p[0] = float(m->param[0]);
+                    a.p[1] = float(m->param[1]);
+                }
             }
         }
     }
@@ -645,8 +672,8 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
         g->pass_pm[0] = PM_CHMU;
         g->pass_pm[1] = PM_FRONT;
     } else {
-        g->npass = 1;
-        g->pass_pm[0] = pm_of(m->model, ns);
+        g->npass = groups.n;
+        for (int k = 0; k < groups.n; ++k) g->pass_pm[k] = groups.pm[k];
     }
     rc = apply_plan(g);
     if (rc) return rc;
@@ -674,6 +701,13 @@ extern "C" int rd_get_plan(const rd_grid* g, rd_plan* p) {
     if (!g || !p) return fail(RD_EINVAL, "NULL argument");
     if (!g->has_model) return fail(RD_ESTATE, "no model set");
     *p = g->eff;
+    return RD_OK;
+}
+
+extern "C" int rd_get_passes(const rd_grid* g, int32_t* out) {
+    if (!g || !out) return fail(RD_EINVAL, "NULL argument");
+    if (!g->has_model) return fail(RD_ESTATE, "no model set");
+    *out = g->npass;
     return RD_OK;
 }
 

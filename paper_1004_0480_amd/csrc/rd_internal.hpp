@@ -15,7 +15,9 @@ enum PassModel {
     PM_BRUSS,
     PM_CHMU,        // Cahn-Hilliard chemical potential (first Laplacian pass)
     PM_FRONT,       // front + Cahn-Hilliard update (second pass)
-    PM_POLL1, PM_POLL2, PM_POLL3, PM_POLL4,
+    PM_POLL1,       // one pollutant
+    PM_POLL2,       // the coupled pair (transfer from the first to the second)
+    PM_POLL2U,      // two uncoupled pollutants
     PM_COUNT
 };
 
@@ -51,15 +53,15 @@ constexpr unsigned bits(std::initializer_list<int> l) {
 // update so both passes of a step share one plan.
 constexpr unsigned cfg_mask(int storage, int pm) {
     const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
-    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2;
+    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2 || pm == PM_POLL2U;
     if (storage == ST_F32)
-        return light ? bits({0, 1, 2, 3, 4, 5, 6}) : medium ? bits({0, 1, 2, 3, 5, 6}) : bits({0, 3, 6});
-    if (storage == ST_BF16) return light ? bits({0, 1, 2, 3, 6}) : bits({0, 3, 6});
+        return light ? bits({0, 1, 2, 3, 4, 5, 6}) : medium ? bits({0, 1, 2, 3, 5, 6}) : bits({3, 6});
+    if (storage == ST_BF16) return light ? bits({0, 1, 2, 3, 6}) : bits({3, 6});
     return light ? bits({1, 2, 3, 6}) : bits({3, 6});
 }
 constexpr unsigned block_mask(int storage, int pm) {
     const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
-    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2;
+    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2 || pm == PM_POLL2U;
     if (storage == ST_F32) {
         if (light) return bits({0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12});
         if (medium) return bits({0, 1, 2, 5, 6, 7, 8, 11});

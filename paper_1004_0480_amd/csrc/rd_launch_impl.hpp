@@ -9,6 +9,8 @@
 
 #include "rd_internal.hpp"
 
+#include <utility>
+
 namespace rdk {
 namespace {
 
@@ -23,10 +25,9 @@ template <> struct PmOf<Diffusion<4>> { static constexpr int v = PM_DIFF4; };
 template <> struct PmOf<Brusselator> { static constexpr int v = PM_BRUSS; };
 template <> struct PmOf<ChemPotential> { static constexpr int v = PM_CHMU; };
 template <> struct PmOf<FrontCH> { static constexpr int v = PM_FRONT; };
-template <> struct PmOf<Pollutant<1>> { static constexpr int v = PM_POLL1; };
-template <> struct PmOf<Pollutant<2>> { static constexpr int v = PM_POLL2; };
-template <> struct PmOf<Pollutant<3>> { static constexpr int v = PM_POLL3; };
-template <> struct PmOf<Pollutant<4>> { static constexpr int v = PM_POLL4; };
+template <> struct PmOf<Pollutant<1, false>> { static constexpr int v = PM_POLL1; };
+template <> struct PmOf<Pollutant<2, true>> { static constexpr int v = PM_POLL2; };
+template <> struct PmOf<Pollutant<2, false>> { static constexpr int v = PM_POLL2U; };
 
 template <class M>
 hipError_t run_direct(const StepArgs& h, const StepArgs* d, hipStream_t s) {
@@ -59,40 +60,29 @@ hipError_t run_block(const StepArgs* d, long long blocks, hipStream_t s) {
     }
 }
 
+// Launch table index `cfg` of a shape table: one branch per compiled entry.
+template <class M, int... I>
+hipError_t run_tiled_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
+                           std::integer_sequence<int, I...>) {
+    hipError_t r = hipErrorInvalidValue;
+    ((void)(cfg == I && ((r = run_cfg<M, I>(d, blocks, s)), true)), ...);
+    return r;
+}
+
+template <class M, int... I>
+hipError_t run_block_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
+                           std::integer_sequence<int, I...>) {
+    hipError_t r = hipErrorInvalidValue;
+    ((void)(cfg == I && ((r = run_block<M, I>(d, blocks, s)), true)), ...);
+    return r;
+}
+
 template <class M>
 hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, long long blocks,
                      hipStream_t s) {
     if (kernel == 1) return run_direct<M>(h, d, s);
-    if (kernel == 3) {
-        static_assert(kNumBlockCfgs == 13, "dispatch below lists every slab shape");
-        switch (cfg) {
-        case 0: return run_block<M, 0>(d, blocks, s);
-        case 1: return run_block<M, 1>(d, blocks, s);
-        case 2: return run_block<M, 2>(d, blocks, s);
-        case 3: return run_block<M, 3>(d, blocks, s);
-        case 4: return run_block<M, 4>(d, blocks, s);
-        case 5: return run_block<M, 5>(d, blocks, s);
-        case 6: return run_block<M, 6>(d, blocks, s);
-        case 7: return run_block<M, 7>(d, blocks, s);
-        case 8: return run_block<M, 8>(d, blocks, s);
-        case 9: return run_block<M, 9>(d, blocks, s);
-        case 10: return run_block<M, 10>(d, blocks, s);
-        case 11: return run_block<M, 11>(d, blocks, s);
-        case 12: return run_block<M, 12>(d, blocks, s);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    static_assert(kNumTileCfgs == 7, "dispatch below lists every tile shape");
-    switch (cfg) {
-    case 0: return run_cfg<M, 0>(d, blocks, s);
-    case 1: return run_cfg<M, 1>(d, blocks, s);
-    case 2: return run_cfg<M, 2>(d, blocks, s);
-    case 3: return run_cfg<M, 3>(d, blocks, s);
-    case 4: return run_cfg<M, 4>(d, blocks, s);
-    case 5: return run_cfg<M, 5>(d, blocks, s);
-    case 6: return run_cfg<M, 6>(d, blocks, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (kernel == 3) return run_block_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumBlockCfgs>{});
+    return run_tiled_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumTileCfgs>{});
 }
 
 }  // namespace
@@ -112,10 +102,9 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
     case PM_FRONT: return run_model<FrontCH>(kernel, cfg, h, d, blocks, s);
 #endif
 #ifdef RD_GROUP_POLL
-    case PM_POLL1: return run_model<Pollutant<1>>(kernel, cfg, h, d, blocks, s);
-    case PM_POLL2: return run_model<Pollutant<2>>(kernel, cfg, h, d, blocks, s);
-    case PM_POLL3: return run_model<Pollutant<3>>(kernel, cfg, h, d, blocks, s);
-    case PM_POLL4: return run_model<Pollutant<4>>(kernel, cfg, h, d, blocks, s);
+    case PM_POLL1: return run_model<Pollutant<1, false>>(kernel, cfg, h, d, blocks, s);
+    case PM_POLL2: return run_model<Pollutant<2, true>>(kernel, cfg, h, d, blocks, s);
+    case PM_POLL2U: return run_model<Pollutant<2, false>>(kernel, cfg, h, d, blocks, s);
 #endif
     default: return hipErrorNotSupported;
     }

@@ -78,6 +78,7 @@ _SIGS = {
                                     C.POINTER(ModelDesc)]),
     "rd_set_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
     "rd_get_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
+    "rd_get_passes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "rd_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Plan)]),
     "rd_batch_create": (C.c_int, [C.c_int32, C.c_size_t, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "rd_batch_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
@@ -292,6 +293,12 @@ class Grid:
         p = Plan()
         _check(lib().rd_get_plan(self._p, C.byref(p)))
         return p.as_dict()
+
+    def passes(self) -> int:
+        """Kernel launches per step."""
+        n = C.c_int32()
+        _check(lib().rd_get_passes(self._p, C.byref(n)))
+        return n.value
 
     def autotune(self, trial_steps: int = 10) -> Dict[str, int]:
         p = Plan()

@@ -55,6 +55,7 @@ def test_null_handles_rejected():
     assert L.rd_set_model(None, None) == rd.EINVAL
     assert L.rd_batch_step(None, 1, None, None) == rd.EINVAL
     assert L.rd_copy_probe(None, None, 16, None) == rd.EINVAL
+    assert L.rd_get_passes(None, None) == rd.EINVAL
     assert L.rd_create_grid(4, 4, 4, 1, 1.0, rd.F32, None, None) == rd.EINVAL
 
 

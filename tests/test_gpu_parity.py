@@ -202,6 +202,37 @@ def test_pollutant_parity():
     check_parity(w, 300)
 
 
+def test_pass_structure():
+    """One launch per step, or two: the front model's chemical-potential pass,
+    and more than two pollutants split into the coupled pair and the rest."""
+    expect = {"brusselator256": 1, "diffusion64": 1, "front384": 2, "pollutant512": 2}
+    for name, n in expect.items():
+        w = W.make_workload(name, shape=(6, 7, 9))
+        g = rd.Grid.from_workload(w)
+        assert g.passes() == n, name
+        g.close()
+    for ns, n in ((1, 1), (2, 1), (3, 2)):
+        shape = (6, 7, 9)
+        spec = W.pollutant_spec(shape, 1, ns=ns)
+        g = rd.Grid(shape, ns, 1.0)
+        g.set_model(spec)
+        assert g.passes() == n, ns
+        g.close()
+
+
+@pytest.mark.parametrize("ns", [1, 2, 3])
+def test_pollutant_species_groups_parity(ns):
+    """Fewer pollutants than the configured four: one pass (one or two
+    species) or two (the coupled pair, then a single species whose sources
+    are found by their global species index)."""
+    shape = (14, 20, 72)
+    spec = W.pollutant_spec(shape, 5, ns=ns, nsrc=40, rate=50.0)
+    rng = np.random.default_rng(ns)
+    fields = [rng.uniform(0, 1, shape) for _ in range(ns)]
+    w = W.Workload("pollutant_ns%d" % ns, shape, spec, fields, 80, 5)
+    check_parity(w, 80)
+
+
 def test_pollutant_ragged_multi_tile():
     w = W.make_workload("pollutant512", shape=(17, 21, 300))
     check_parity(w, 60)
