@@ -124,18 +124,25 @@ enum {
     RD_KERNEL_DIRECT = 1,  /* one thread per cell, neighbours through the cache */
     RD_KERNEL_TILED = 2,   /* xy tile per workgroup, z-march register window,
                               wave64 lane shifts for x, LDS for inter-wave rows */
-    RD_KERNEL_BLOCK = 3    /* xy tile x cz-plane slab per workgroup, all planes
+    RD_KERNEL_BLOCK = 3,   /* xy tile x cz-plane slab per workgroup, all planes
                               loaded up front; same lane shifts and LDS rows    */
+    RD_KERNEL_LDS = 4      /* FP32 rows of 256 or 512 cells: z-march over a ring
+                              of LDS plane slots filled by direct-to-LDS loads
+                              from one producer wave                           */
 };
 typedef struct rd_plan {
     int32_t kernel;       /* RD_KERNEL_*                                        */
-    int32_t vx;           /* TILED/BLOCK: cells per lane along x (1, 2 or 4)    */
-    int32_t ry;           /* TILED/BLOCK: rows per wave (1, 2 or 4)             */
-    int32_t waves;        /* TILED/BLOCK: waves per workgroup (1 or 4)          */
-    int32_t cz;           /* TILED: z planes per workgroup, 0 = whole z axis;
+    int32_t vx;           /* TILED/BLOCK: cells per lane along x (1, 2 or 4);
+                             LDS: 4 (rows of 256 cells) or 8 (rows of 512)     */
+    int32_t ry;           /* TILED/BLOCK: rows per wave (1, 2 or 4);
+                             LDS: rows per workgroup                           */
+    int32_t waves;        /* TILED/BLOCK: waves per workgroup (1 or 4);
+                             LDS: computing waves (plus one loading wave)      */
+    int32_t cz;           /* TILED/LDS: z planes per workgroup, 0 = whole z axis;
                              BLOCK: planes per slab (2, 4 or 8)                */
-    int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2) */
-    int32_t order;        /* BLOCK: slab enumeration, 0 = x, then y, then z chunk;
+    int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2);
+                             LDS: ring slots (planes in flight = slots - 3)    */
+    int32_t order;        /* BLOCK/LDS: tile enumeration, 0 = x, then y, then z chunk;
                              1 = z chunk fastest (z-neighbour slabs run together
                              on one XCD and share its L2)                       */
     int32_t graph_chunk;  /* rd_step replays hipGraphs of this many steps (even,

@@ -1152,6 +1152,276 @@ __global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restric
     tile_step<M, S, VX, RY, W, PF>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
+// ---- LDS-ring z-march kernel ------------------------------------------------
+//
+// Whole rows of nx = 256*NCH FP32 cells.  A workgroup owns rows [yb, yb+BY)
+// and marches planes [z0, z1).  One producer wave streams every plane it
+// needs (its BY rows plus one halo row on each side, every field) from HBM
+// into a ring of D plane slots in LDS with global_load_lds_dwordx4, so the
+// data in flight holds no registers; WC consumer waves compute from the ring.
+// The producer issues nothing but these loads, so it can wait for one plane
+// with an exact vmcnt, and one barrier per plane hands the plane over.  While
+// plane z is computed, planes z-1, z, z+1 are in use and D-3 more are in
+// flight.  The consumers' LDS reads and the producer's loads sit in separate
+// loops, so the compiler never drains the loads for an LDS read.
+
+template <int K>
+__device__ __forceinline__ void vm_wait_imm() {
+    static_assert(K >= 0 && K <= 63, "vmcnt holds 6 bits");
+    // s_waitcnt fields: vmcnt [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]
+    __builtin_amdgcn_s_waitcnt((K & 15) | (((K >> 4) & 3) << 14) | (7 << 4) | (15 << 8));
+}
+
+// vmcnt(n * STEP) for a run-time n in [0, N]
+template <int STEP, int N>
+__device__ __forceinline__ void vm_wait_steps(int n) {
+    if (n >= N) {
+        vm_wait_imm<N * STEP>();
+    } else if constexpr (N > 0) {
+        vm_wait_steps<STEP, N - 1>(n);
+    }
+}
+
+// A workgroup barrier the compiler may not move memory accesses across, with
+// no fence: a fence would wait for every load in flight.
+__device__ __forceinline__ void ring_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <int NF, int NCH, int BY, int D>
+struct LdsRing {
+    static constexpr int ROWS = BY + 2, TXT = 256 * NCH, SLOT = NF * ROWS * TXT;
+    static constexpr int CH = NF * ROWS * NCH;                 // 1 KB loads per plane
+    static constexpr long long BYTES = 4LL * D * SLOT;
+    static constexpr bool FITS = BYTES <= 160 * 1024 && (D - 4) * CH <= 63 && D >= 4;
+};
+
+template <class M, int NCH, int BY, int WC, int D>
+__device__ __forceinline__ void lds_producer(const StepArgs& a, float (*ring)[LdsRing<M::NF, NCH, BY, D>::SLOT],
+                                             int yb, int z0, int z1) {
+    using R = LdsRing<M::NF, NCH, BY, D>;
+    constexpr int NF = M::NF, ROWS = R::ROWS, TXT = R::TXT;
+    const int lane = threadIdx.x & 63;
+    // grid row of LDS row j is yb - 1 + j, resolved by the face rules
+    int ridx[NF][ROWS];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j)
+            ridx[f][j] = resolve_axis(yb - 1 + j, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]).idx;
+    auto issue = [&](float* slot, int p) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const int pz = resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]).idx;
+            const RD_GLOBAL float* base = gload_ptr<float>(a.in[f]) + (long long)pz * a.plane + lane * 4;
+#pragma unroll
+            for (int j = 0; j < ROWS; ++j)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+                    __builtin_amdgcn_global_load_lds(base + (long long)ridx[f][j] * a.pitch + c * 256,
+                                                     (__attribute__((address_space(3))) void*)(slot + (f * ROWS + j) * TXT + c * 256),
+                                                     16, 0, 0);
+        }
+    };
+    // planes z0-1 .. z0+D-3 into slots 0 .. D-2; plane p lives in slot (p - z0 + 1) % D
+#pragma unroll
+    for (int k = 0; k < D - 1; ++k)
+        if (z0 - 1 + k <= z1) issue(ring[k], z0 - 1 + k);
+    for (int zb = z0; zb < z1; zb += D) {
+#pragma unroll
+        for (int J = 0; J < D; ++J) {
+            const int z = zb + J;
+            if (z < z1) {
+                // plane z+1 complete: the loads issued after it are planes z+2 ..
+                vm_wait_steps<R::CH, D - 4>(min(D - 4, z1 - z - 1));
+                ring_barrier();
+                // every consumer is past plane z-1, so the slot of plane z-2 is free
+                if (z + D - 2 <= z1) issue(ring[(J + D - 1) % D], z + D - 2);
+            }
+        }
+    }
+}
+
+template <class M, int NCH, int BY, int WC, int D>
+__device__ __forceinline__ void lds_consumer(const StepArgs& a, const float (*ring)[LdsRing<M::NF, NCH, BY, D>::SLOT],
+                                             int cw, int yb, int z0, int z1) {
+    using R = LdsRing<M::NF, NCH, BY, D>;
+    constexpr int NF = M::NF, NO = M::NO, TXT = R::TXT, RY = BY / WC;
+    const int lane = threadIdx.x & 63;
+    const int r0 = cw * RY;                   // first tile row of this wave
+    // rows r0-1 .. r0+RY of the tile (LDS rows r0 .. r0+RY+1), for fix-ups
+    Src rs[NF][RY + 2];
+    bool rows_fix = false;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int r = 0; r < RY + 2; ++r) {
+            rs[f][r] = resolve_axis(yb + r0 - 1 + r, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]);
+            rows_fix = rows_fix || rs[f][r].cst;
+        }
+        rows_fix = rows_fix || (a.held[f] & 3) != 0;
+    }
+    int xsl[NF], xsr[NF];
+    (void)x_sides<M, true>(a, 0, TXT, true, xsl, xsr);
+    bool xy_held = false, held_lo = false, held_hi = false;
+#pragma unroll
+    for (int s = 0; s < NO; ++s) {
+        const int hm = a.out_held[s];
+        xy_held = xy_held || (hm & 3) || ((hm & 4) && yb + r0 == 0) || ((hm & 8) && yb + r0 + RY >= a.ny);
+        held_lo = held_lo || (hm & 16);
+        held_hi = held_hi || (hm & 32);
+    }
+
+    for (int zb = z0; zb < z1; zb += D) {
+#pragma unroll
+        for (int J = 0; J < D; ++J) {
+            const int z = zb + J;
+            if (z < z1) {
+                // scalar loads of this plane's wind and source range go out
+                // before the barrier so their latency hides behind it
+                const float uh = M::SOURCES ? gload_ptr<float>(a.wind_h)[z] : 0.f;
+                bool plane_src = false;
+                if (M::SOURCES) {
+                    const int pa0 = gload_ptr<int>(a.src_row)[z * a.ny];
+                    const int pa1 = gload_ptr<int>(a.src_row)[(z + 1) * a.ny];
+                    plane_src = pa0 < pa1;
+                }
+                ring_barrier();
+                const float* Sm = ring[J % D];
+                const float* S0 = ring[(J + 1) % D];
+                const float* Sp = ring[(J + 2) % D];
+                // rows r0-1 .. r0+RY of plane z, rows r0 .. r0+RY-1 of planes z-1 and z+1
+                float v0[NF][RY + 2][NCH][4], vm[NF][RY][NCH][4], vp[NF][RY][NCH][4];
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+                        for (int r = 0; r < RY + 2; ++r) {
+                            const float4 q = *reinterpret_cast<const float4*>(S0 + (f * R::ROWS + r0 + r) * TXT + c * 256 + lane * 4);
+                            v0[f][r][c][0] = q.x; v0[f][r][c][1] = q.y; v0[f][r][c][2] = q.z; v0[f][r][c][3] = q.w;
+                        }
+#pragma unroll
+                        for (int r = 0; r < RY; ++r) {
+                            const float4 qm = *reinterpret_cast<const float4*>(Sm + (f * R::ROWS + r0 + 1 + r) * TXT + c * 256 + lane * 4);
+                            const float4 qp = *reinterpret_cast<const float4*>(Sp + (f * R::ROWS + r0 + 1 + r) * TXT + c * 256 + lane * 4);
+                            vm[f][r][c][0] = qm.x; vm[f][r][c][1] = qm.y; vm[f][r][c][2] = qm.z; vm[f][r][c][3] = qm.w;
+                            vp[f][r][c][0] = qp.x; vp[f][r][c][1] = qp.y; vp[f][r][c][2] = qp.z; vp[f][r][c][3] = qp.w;
+                        }
+                    }
+                // boundary rules that replace loaded values (fixed or held rows,
+                // planes and x faces)
+                const bool near_face = z - 1 <= 0 || z + 1 >= a.nz - 1;
+                if (rows_fix || near_face) {
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        const Src pm = resolve_axis(z - 1, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+                        const Src p0 = resolve_axis(z, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+                        const Src pp = resolve_axis(z + 1, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            const int xl = c * 256 + lane * 4;
+#pragma unroll
+                            for (int r = 0; r < RY + 2; ++r) fix_row<4>(a, f, p0, rs[f][r], xl, v0[f][r][c]);
+#pragma unroll
+                            for (int r = 0; r < RY; ++r) {
+                                fix_row<4>(a, f, pm, rs[f][r + 1], xl, vm[f][r][c]);
+                                fix_row<4>(a, f, pp, rs[f][r + 1], xl, vp[f][r][c]);
+                            }
+                        }
+                    }
+                }
+                const bool held = xy_held || (held_lo && z == 0) || (held_hi && z == a.nz - 1);
+#pragma unroll
+                for (int r = 0; r < RY; ++r) {
+                    const int y = yb + r0 + r;
+                    Nb n[NF][NCH][4];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            const float (&v)[4] = v0[f][r + 1][c];
+                            // x neighbours across lanes, chunks and the x faces
+                            float fl, fr;
+                            if (c > 0) {
+                                fl = lane_from_left_wrap(v0[f][r + 1][c - 1][3]);
+                            } else if (xsl[f] == XS_ROT) {
+                                fl = lane_from_left_wrap(v0[f][r + 1][NCH - 1][3]);
+                            } else {
+                                fl = xsl[f] == XS_OWN ? v[0] : a.bcv[f][0];
+                            }
+                            if (c < NCH - 1) {
+                                fr = lane_from_right_wrap(v0[f][r + 1][c + 1][0]);
+                            } else if (xsr[f] == XS_ROT) {
+                                fr = lane_from_right_wrap(v0[f][r + 1][0][0]);
+                            } else {
+                                fr = xsr[f] == XS_OWN ? v[3] : a.bcv[f][1];
+                            }
+                            const float left = lane_from_left(v[3], fl);
+                            const float right = lane_from_right(v[0], fr);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                Nb& q = n[f][c][i];
+                                q.c = v[i];
+                                q.xm = i > 0 ? v[i - 1] : left;
+                                q.xp = i < 3 ? v[i + 1] : right;
+                                q.ym = v0[f][r][c][i];
+                                q.yp = v0[f][r + 2][c][i];
+                                q.zm = vm[f][r][c][i];
+                                q.zp = vp[f][r][c][i];
+                            }
+                        }
+                    }
+                    int s0 = 0, s1 = 0;
+                    if (M::SOURCES && plane_src && y < a.ny) {
+                        s0 = gload_ptr<int>(a.src_row)[z * a.ny + y];
+                        s1 = gload_ptr<int>(a.src_row)[z * a.ny + y + 1];
+                    }
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        const int xl = c * 256 + lane * 4;
+                        float o[NO][4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            Nb ni[NF];
+#pragma unroll
+                            for (int f = 0; f < NF; ++f) ni[f] = n[f][c][i];
+                            Emission<NO> em{};
+                            if (M::SOURCES && s0 < s1) em = cell_sources<NO>(a, xl + i, s0, s1);
+                            float oi[NO];
+                            M::cell(a, ni, uh, em.any, em.e, oi);
+#pragma unroll
+                            for (int s = 0; s < NO; ++s) o[s][i] = held ? held_out(a, s, xl + i, y, z, oi[s]) : oi[s];
+                        }
+                        if (y < a.ny) {
+                            const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
+#pragma unroll
+                            for (int s = 0; s < NO; ++s) store_vec<StF32, 4>(a.out[s], idx, o[s]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <class M, int NCH, int BY, int WC, int D>
+__global__ __launch_bounds__(64 * (WC + 1)) void lds_kernel(const StepArgs* __restrict__ pa) {
+    using R = LdsRing<M::NF, NCH, BY, D>;
+    static_assert(R::FITS && BY % WC == 0, "ring shape does not fit");
+    __shared__ __attribute__((aligned(16))) float ring[D][R::SLOT];
+    const StepArgs& a = *pa;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TileXYZ tc = tile_coords(a, xcd_tile(blockIdx.x, gridDim.x));
+    const int yb = tc.y * BY;
+    const int z0 = tc.z * a.cz;
+    const int z1 = min(z0 + a.cz, a.nz);
+    if (w == 0) lds_producer<M, NCH, BY, WC, D>(a, ring, yb, z0, z1);
+    else lds_consumer<M, NCH, BY, WC, D>(a, ring, w - 1, yb, z0, z1);
+}
+
 // ------------------------------------------------------------ batched kernel
 // A persistent launch walks the (grid, slab) work items of many grids.  The
 // host writes, before each tick, `meta` = {ngrids, total_items, first_item[0..

@@ -103,6 +103,13 @@ int tile_cfg_index(int vx, int ry, int w, int pf) {
     return -1;
 }
 
+int lds_cfg_index(int nch, int by, int wc, int d) {
+    for (int i = 0; i < kNumLdsCfgs; ++i)
+        if (kLdsCfgs[i].nch == nch && kLdsCfgs[i].by == by && kLdsCfgs[i].wc == wc && kLdsCfgs[i].d == d)
+            return i;
+    return -1;
+}
+
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h, const StepArgs* d,
                        long long blocks, hipStream_t s) {
     const bool diff = pm <= PM_DIFF4;
@@ -224,13 +231,14 @@ void fill_mirror(StepArgs& a, int f) {
 
 // Decomposition of a tiled plan: fills tiles_* / cz, returns workgroups.
 long long set_tiling(StepArgs& a, const rd_plan& p) {
-    const int tx = 64 * p.vx, by = p.ry * p.waves;
+    // LDS ring: whole rows (vx cells per lane), ry rows per workgroup
+    const int tx = 64 * p.vx, by = p.kernel == RD_KERNEL_LDS ? p.ry : p.ry * p.waves;
     const int cz = (p.cz <= 0 || p.cz > a.nz) ? a.nz : p.cz;
     a.tiles_x = (a.nx + tx - 1) / tx;
     a.tiles_y = (a.ny + by - 1) / by;
     a.cz = cz;
     a.chunks_z = (a.nz + cz - 1) / cz;
-    a.zfast = p.kernel == RD_KERNEL_BLOCK && p.order == 1;
+    a.zfast = (p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS) && p.order == 1;
     return (long long)a.tiles_x * a.tiles_y * a.chunks_z;
 }
 
@@ -291,6 +299,17 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
         *cfg_out = cfg;
         return RD_OK;
     }
+    if (p.kernel == RD_KERNEL_LDS) {
+        const int cfg = (p.vx == 4 || p.vx == 8) ? lds_cfg_index(p.vx / 4, p.ry, p.waves, p.prefetch) : -1;
+        if (cfg < 0) return fail(RD_EINVAL, "LDS ring shape not available");
+        if (g->nx != 64 * p.vx) return fail(RD_EINVAL, "the LDS ring kernel needs rows of exactly 64*vx cells");
+        for (int k = 0; k < g->npass; ++k)
+            if (!lds_ok(g->storage, g->pass_pm[k], cfg))
+                return fail(RD_EINVAL, "LDS ring shape not compiled for this model and storage");
+        if (p.cz < 0) return fail(RD_EINVAL, "cz must be >= 0");
+        *cfg_out = cfg;
+        return RD_OK;
+    }
     if (p.kernel != RD_KERNEL_TILED) return fail(RD_EINVAL, "unknown kernel kind");
     const int cfg = tile_cfg_index(p.vx, p.ry, p.waves, p.prefetch);
     if (cfg < 0) return fail(RD_EINVAL, "tile shape not available");
@@ -318,7 +337,8 @@ int apply_plan(rd_grid* g) {
     for (int par = 0; par < 2; ++par)
         for (int k = 0; k < g->npass; ++k) {
             StepArgs& a = g->args[par][k];
-            if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK) g->blocks[k] = set_tiling(a, p);
+            if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS)
+                g->blocks[k] = set_tiling(a, p);
             else g->blocks[k] = 0;
         }
     for (int k = 0; k < g->npass; ++k)
@@ -923,6 +943,24 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
         cands.push_back(p);
         p.order = 1;
         cands.push_back(p);
+    }
+    for (int i = 0; i < kNumLdsCfgs; ++i) {
+        const LdsCfg c = kLdsCfgs[i];
+        if (g->nx != 256 * c.nch) continue;
+        bool ok = true;
+        for (int k = 0; k < g->npass; ++k) ok = ok && lds_ok(g->storage, g->pass_pm[k], i);
+        if (!ok) continue;
+        for (int cz : {0, 64, 32, 16}) {
+            if (cz != 0 && cz >= g->nz) continue;
+            rd_plan p{};
+            p.kernel = RD_KERNEL_LDS;
+            p.vx = 4 * c.nch;
+            p.ry = c.by;
+            p.waves = c.wc;
+            p.prefetch = c.d;
+            p.cz = cz;
+            cands.push_back(p);
+        }
     }
     hipEvent_t e0, e1;
     RD_HIP(hipEventCreate(&e0));

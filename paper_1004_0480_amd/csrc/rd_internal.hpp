@@ -41,6 +41,15 @@ constexpr BlockCfg kBlockCfgs[] = {
 };
 constexpr int kNumBlockCfgs = sizeof(kBlockCfgs) / sizeof(kBlockCfgs[0]);
 
+// Ring shapes of the LDS-ring z-march (FP32, rows of 256*nch cells): 256-cell
+// chunks per row, rows per workgroup, consumer waves, ring slots.
+struct LdsCfg { int nch, by, wc, d; };
+constexpr LdsCfg kLdsCfgs[] = {
+    {1, 8, 4, 7}, {1, 8, 8, 7}, {2, 8, 4, 6}, {2, 4, 4, 6}, {2, 8, 8, 6}, {2, 4, 4, 7},
+    {2, 8, 8, 7}, {1, 12, 6, 5}, {2, 12, 6, 5}, {2, 6, 6, 5},
+};
+constexpr int kNumLdsCfgs = sizeof(kLdsCfgs) / sizeof(kLdsCfgs[0]);
+
 constexpr unsigned bits(std::initializer_list<int> l) {
     unsigned m = 0;
     for (int i : l) m |= 1u << i;
@@ -76,11 +85,29 @@ constexpr unsigned block_mask(int storage, int pm) {
     return bits({0, 5});
 }
 
+// Stencil fields a pass model reads.
+constexpr int pm_fields(int pm) {
+    return pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_POLL1 ? 1
+         : pm == PM_DIFF2 || pm == PM_BRUSS || pm == PM_POLL2 || pm == PM_POLL2U ? 2
+         : pm == PM_DIFF3 ? 3 : 4;
+}
+
+// LDS-ring shape i is compiled for this storage and pass model: FP32 fields,
+// at most two of them, and a ring that fits the LDS and the vmcnt range.
+constexpr bool lds_ok(int storage, int pm, int i) {
+    if (storage != ST_F32 || pm_fields(pm) > 2 || pm == PM_CHMU || i < 0 || i >= kNumLdsCfgs) return false;
+    const LdsCfg c = kLdsCfgs[i];
+    const int nf = pm_fields(pm), rows = c.by + 2;
+    const long long bytes = 4LL * c.d * nf * rows * 256 * c.nch;
+    return bytes <= 160 * 1024 && (c.d - 4) * nf * rows * c.nch <= 63 && c.d >= 4 && c.by % c.wc == 0;
+}
+
 int tile_cfg_index(int vx, int ry, int w, int pf);   // -1 if no such shape
+int lds_cfg_index(int nch, int by, int wc, int d);   // -1 if no such shape
 int block_cfg_index(int vx, int ry, int w, int cz);  // -1 if no such shape
 
 // Launch one pass.  kernel: 1 direct, 2 tiled (cfg = kTileCfgs index),
-// 3 plane block (cfg = kBlockCfgs index).
+// 3 plane block (cfg = kBlockCfgs index), 4 LDS ring (cfg = kLdsCfgs index).
 // `h` is the host copy of the arguments (for the launch shape), `d` the same
 // arguments in device memory (what the kernel reads).
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h,

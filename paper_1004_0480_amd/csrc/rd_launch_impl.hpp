@@ -60,6 +60,18 @@ hipError_t run_block(const StepArgs* d, long long blocks, hipStream_t s) {
     }
 }
 
+template <class M, int I>
+hipError_t run_lds(const StepArgs* d, long long blocks, hipStream_t s) {
+    if constexpr (lds_ok(kStorage, PmOf<M>::v, I)) {
+        constexpr LdsCfg c = kLdsCfgs[I];
+        hipLaunchKernelGGL((lds_kernel<M, c.nch, c.by, c.wc, c.d>), dim3((unsigned)blocks), dim3(64 * (c.wc + 1)),
+                           0, s, d);
+        return hipGetLastError();
+    } else {
+        return hipErrorNotSupported;
+    }
+}
+
 // Launch table index `cfg` of a shape table: one branch per compiled entry.
 template <class M, int... I>
 hipError_t run_tiled_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
@@ -77,10 +89,19 @@ hipError_t run_block_index(int cfg, const StepArgs* d, long long blocks, hipStre
     return r;
 }
 
+template <class M, int... I>
+hipError_t run_lds_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
+                         std::integer_sequence<int, I...>) {
+    hipError_t r = hipErrorInvalidValue;
+    ((void)(cfg == I && ((r = run_lds<M, I>(d, blocks, s)), true)), ...);
+    return r;
+}
+
 template <class M>
 hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, long long blocks,
                      hipStream_t s) {
     if (kernel == 1) return run_direct<M>(h, d, s);
+    if (kernel == 4) return run_lds_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLdsCfgs>{});
     if (kernel == 3) return run_block_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumBlockCfgs>{});
     return run_tiled_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumTileCfgs>{});
 }

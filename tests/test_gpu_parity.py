@@ -23,6 +23,10 @@ TOL = 1e-5          # FP32 rel-L2 bound per species against the FP64 oracle
 # slab shapes; the library rejects the ones it did not compile for a model
 TILE_SHAPES = [(4, 1, 4, 1), (4, 1, 4, 2), (2, 2, 4, 2), (2, 1, 4, 2), (4, 2, 4, 1), (1, 4, 4, 2),
                (2, 1, 4, 1)]
+# LDS-ring shapes (cells per lane = 4 * 256-cell chunks, rows per workgroup,
+# computing waves, ring slots); only rows of exactly 64 * vx cells take them
+LDS_SHAPES = [(4, 8, 4, 7), (4, 8, 8, 7), (8, 8, 4, 6), (8, 4, 4, 6), (8, 8, 8, 6), (8, 4, 4, 7),
+              (8, 8, 8, 7), (4, 12, 6, 5), (8, 12, 6, 5), (8, 6, 6, 5)]
 BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
                 (2, 1, 4, 4), (4, 2, 1, 2), (4, 1, 1, 2), (4, 2, 1, 4), (4, 4, 1, 2), (4, 2, 2, 2),
                 (4, 3, 1, 2)]
@@ -55,6 +59,8 @@ def compiled_plans(w, storage="f32", czs=(0, 8)):
              for vx, ry, wv, pf in TILE_SHAPES for cz in czs]
     cands += [dict(kernel="block", vx=vx, ry=ry, waves=wv, cz=cz, order=o)
               for vx, ry, wv, cz in BLOCK_SHAPES for o in (0, 1)]
+    cands += [dict(kernel="lds", vx=vx, ry=by, waves=wc, prefetch=d, cz=cz, order=o)
+              for vx, by, wc, d in LDS_SHAPES for cz in czs for o in (0, 1)]
     for p in cands:
         try:
             g.set_plan(**p)
@@ -428,7 +434,8 @@ def test_held_and_ghost_faces_every_axis():
         assert all(np.array_equal(a, b) for a, b in zip(got, base)), plan
 
 
-@pytest.mark.parametrize("case", ["bruss256", "poll128", "front128", "faces128"])
+@pytest.mark.parametrize("case", ["bruss256", "poll128", "front128", "faces128", "diff512", "poll512",
+                                  "faces256", "held256", "bruss256ragged"])
 def test_whole_tile_rows_every_plan(case):
     """Rows a whole number of x tiles long take the kernels' fast x-ghost
     path (whole periodic rows, split rows, mirror / fixed faces, fixed and
@@ -439,6 +446,24 @@ def test_whole_tile_rows_every_plan(case):
         w = W.make_workload("pollutant512", shape=(10, 11, 128))
     elif case == "front128":
         w = W.make_workload("front384", shape=(12, 10, 128))
+    elif case == "diff512":
+        w = W.make_workload("diffusion512", shape=(7, 13, 512))
+    elif case == "poll512":
+        w = W.make_workload("pollutant512", shape=(9, 11, 512))
+    elif case == "bruss256ragged":
+        w = W.make_workload("brusselator256", shape=(5, 19, 256))
+    elif case == "held256":
+        shape = (9, 13, 256)
+        rng = np.random.default_rng(3)
+        faces = [(HELD, 1.0), (GHOST, -0.5), (HELD, 0.25), (MIRROR, 0), (GHOST, 2.0), (HELD, -1.0)]
+        spec = bc_spec(2, faces)
+        w = W.Workload("held256", shape, spec, [rng.uniform(0, 1, shape) for _ in range(2)], 6, 0)
+    elif case == "faces256":
+        shape = (10, 12, 256)
+        rng = np.random.default_rng(9)
+        faces = [(GHOST, 0.5), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0), (HELD, 0.25), (GHOST, -1.0)]
+        spec = bc_spec(1, faces)
+        w = W.Workload("faces256", shape, spec, [rng.uniform(0, 1, shape)], 6, 0)
     else:
         shape = (10, 12, 128)
         rng = np.random.default_rng(9)
@@ -448,7 +473,10 @@ def test_whole_tile_rows_every_plan(case):
     steps = 6
     ref = oracle.run(w.spec, w.fields, steps)
     base = None
-    for plan in compiled_plans(w, czs=(0, 4, 7)):
+    plans = compiled_plans(w, czs=(0, 4, 7))
+    if w.shape[2] in (256, 512) and w.spec.model in ("diffusion", "brusselator", "pollutant"):
+        assert any(p["kernel"] == "lds" for p in plans), case
+    for plan in plans:
         got, _ = gpu_run(w, steps, plan=plan)
         if base is None:
             base = got
