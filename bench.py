@@ -341,18 +341,22 @@ def main():
         g.reduce(s)
 
     bpc = alg_bytes_per_cell(w.name, args.storage)
-    launches_per_step = g.passes()
-    # dominant kernel: the step kernel.  With one pass per step its average
-    # launch duration is the event-timed step time; a step of several passes
-    # is reported per step (all its kernels together).
-    achieved = bpc * w.cells / (ms_per_step * 1e-3) / 1e9
+    passes = g.passes()
+    steps_per_launch = 2 if plan.get("kernel") == 5 else 1     # two-step (temporally blocked) plan
+    # dominant kernel: the step kernel.  A launch reads and writes every field
+    # once (for one step, or two with a two-step plan); with one pass its
+    # average launch duration is the event-timed time of the steps it covers.
+    # A step of several passes is reported per step (all its kernels).
+    launch_ms = ms_per_step * steps_per_launch
+    achieved = bpc * w.cells / (launch_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
     traffic = measured_traffic(w.name, digest)
     ceiling = copy_ceiling(torch, stream, COPY_PROBE_BYTES)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "per": "launch" if launches_per_step == 1 else "step (%d kernels)" % launches_per_step,
-            "kernel_avg_ms": ms_per_step / launches_per_step if launches_per_step == 1 else None,
+            "per": "launch" if passes == 1 else "step (%d kernels)" % passes,
+            "steps_per_launch": steps_per_launch,
+            "kernel_avg_ms": launch_ms if passes == 1 else None,
             "alg_bytes_per_cell": bpc, "copy_ceiling_GBs": ceiling,
             "frac_of_copy_ceiling": achieved / ceiling, "source_digest": digest}
     out = {

@@ -126,23 +126,27 @@ enum {
                               wave64 lane shifts for x, LDS for inter-wave rows */
     RD_KERNEL_BLOCK = 3,   /* xy tile x cz-plane slab per workgroup, all planes
                               loaded up front; same lane shifts and LDS rows    */
-    RD_KERNEL_LDS = 4      /* FP32 rows of 256 or 512 cells: z-march over a ring
+    RD_KERNEL_LDS = 4,     /* FP32 rows of 256 or 512 cells: z-march over a ring
                               of LDS plane slots filled by direct-to-LDS loads
                               from one producer wave                           */
+    RD_KERNEL_LDS2 = 5     /* as RD_KERNEL_LDS, two time steps per launch
+                              (temporal blocking; diffusion and Brusselator).
+                              rd_step with an odd count finishes with one
+                              direct-kernel step                               */
 };
 typedef struct rd_plan {
     int32_t kernel;       /* RD_KERNEL_*                                        */
     int32_t vx;           /* TILED/BLOCK: cells per lane along x (1, 2 or 4);
-                             LDS: 4 (rows of 256 cells) or 8 (rows of 512)     */
+                             LDS/LDS2: 4 (rows of 256 cells) or 8 (of 512)     */
     int32_t ry;           /* TILED/BLOCK: rows per wave (1, 2 or 4);
-                             LDS: rows per workgroup                           */
+                             LDS/LDS2: rows per workgroup                      */
     int32_t waves;        /* TILED/BLOCK: waves per workgroup (1 or 4);
-                             LDS: computing waves (plus one loading wave)      */
-    int32_t cz;           /* TILED/LDS: z planes per workgroup, 0 = whole z axis;
+                             LDS/LDS2: computing waves (plus one loading wave) */
+    int32_t cz;           /* TILED/LDS/LDS2: z planes per workgroup, 0 = all;
                              BLOCK: planes per slab (2, 4 or 8)                */
     int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2);
-                             LDS: ring slots (planes in flight = slots - 3)    */
-    int32_t order;        /* BLOCK/LDS: tile enumeration, 0 = x, then y, then z chunk;
+                             LDS/LDS2: input ring slots                        */
+    int32_t order;        /* BLOCK/LDS/LDS2: tile enumeration, 0 = x, then y, then z chunk;
                              1 = z chunk fastest (z-neighbour slabs run together
                              on one XCD and share its L2)                       */
     int32_t graph_chunk;  /* rd_step replays hipGraphs of this many steps (even,

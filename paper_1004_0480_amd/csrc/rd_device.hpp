@@ -1422,6 +1422,340 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds_kernel(const StepArgs* __re
     else lds_consumer<M, NCH, BY, WC, D>(a, ring, w - 1, yb, z0, z1);
 }
 
+// ---- two steps per launch (temporal blocking) on the LDS ring ---------------
+//
+// The same producer / consumer split, two time levels per pass over HBM: the
+// input ring holds planes of rows yb-2 .. yb+BY+1 (a halo of two), and the
+// consumers first compute the intermediate level ("mid") on rows yb-1 ..
+// yb+BY into a ring of four LDS planes, then the output level on rows yb ..
+// yb+BY-1 from the mid ring.  Iteration q computes mid plane q and output
+// plane q-2, so one barrier per plane covers both rings.  A mid value the
+// output needs from outside the grid follows the face rule: periodic ones
+// are computed from wrapped inputs, mirror ones are the edge row or plane,
+// fixed ones the face value.  Every cell goes through the same cell function
+// as a single step, so two steps here give the bits of two single steps.
+// Models with point sources are not blocked.
+
+template <int NF, int NCH, int BY, int D>
+struct Lds2Ring {
+    static constexpr int IROWS = BY + 4, MROWS = BY + 2, TXT = 256 * NCH;
+    static constexpr int ISLOT = NF * IROWS * TXT, MSLOT = NF * MROWS * TXT;
+    static constexpr int CH = NF * IROWS * NCH;                // 1 KB loads per input plane
+    static constexpr long long BYTES = 4LL * (D * ISLOT + 4 * MSLOT);
+    static constexpr bool FITS = BYTES <= 160 * 1024 && (D - 4) * CH <= 63 && D >= 4;
+};
+
+// Index of grid row / plane q for the input ring: periodic axes wrap (up to
+// two cells beyond a face), other axes clamp (the rules that replace those
+// values are applied by the consumers).
+__device__ __forceinline__ int wrap_or_clamp(int q, int n, bool periodic) {
+    if (periodic) return ((q % n) + n) % n;
+    return min(max(q, 0), n - 1);
+}
+
+// LDS operations of this wave complete (before a barrier publishes them).
+__device__ __forceinline__ void lds_done() {
+    // vmcnt and expcnt at their maxima, lgkmcnt(0)
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
+}
+
+template <class M, int NCH, int BY, int WC, int D>
+__device__ __forceinline__ void lds2_producer(const StepArgs& a, float* iring, int yb, int z0, int z1) {
+    using R = Lds2Ring<M::NF, NCH, BY, D>;
+    constexpr int NF = M::NF, IROWS = R::IROWS, TXT = R::TXT;
+    const int lane = threadIdx.x & 63;
+    int ridx[NF][IROWS];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int j = 0; j < IROWS; ++j)
+            ridx[f][j] = wrap_or_clamp(yb - 2 + j, a.ny, a.bck[f][2] == BC_PERIODIC);
+    auto issue = [&](int slot, int p) {
+        float* base_l = iring + slot * R::ISLOT;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const int pz = wrap_or_clamp(p, a.nz, a.bck[f][4] == BC_PERIODIC);
+            const RD_GLOBAL float* base = gload_ptr<float>(a.in[f]) + (long long)pz * a.plane + lane * 4;
+#pragma unroll
+            for (int j = 0; j < IROWS; ++j)
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+                    __builtin_amdgcn_global_load_lds(
+                        base + (long long)ridx[f][j] * a.pitch + c * 256,
+                        (__attribute__((address_space(3))) void*)(base_l + (f * IROWS + j) * TXT + c * 256), 16, 0, 0);
+        }
+    };
+    // input planes z0-2 .. z1+1; plane p lives in slot (p - z0 + 2) % D
+    const int p_first = z0 - 2, p_last = z1 + 1;
+    for (int k = 0; k < D - 1 && p_first + k <= p_last; ++k) issue(k, p_first + k);
+    int slot_next = (D - 1) % D;        // slot of plane q + D - 2 at iteration q = z0 - 1
+    for (int q = z0 - 1; q <= z1 + 1; ++q) {
+        if (q <= z1) vm_wait_steps<R::CH, D - 4>(min(D - 4, z1 - q));   // plane q+1 complete
+        ring_barrier();
+        if (q + D - 2 <= p_last) issue(slot_next, q + D - 2);
+        slot_next = slot_next + 1 == D ? 0 : slot_next + 1;
+    }
+}
+
+// Mid-ring row for output neighbour row yn (grid index) of a tile starting at
+// yb, by the y face rules; cst: use value v.
+struct MidSrc { int idx; int cst; float v; };
+
+__device__ __forceinline__ MidSrc mid_src(int q, int n, int base, int klo, int khi, float vlo, float vhi) {
+    if (q >= 0 && q < n) return MidSrc{q - base, 0, 0.f};
+    const int k = q < 0 ? klo : khi;
+    if (k == BC_PERIODIC) return MidSrc{q - base, 0, 0.f};
+    if (k == BC_MIRROR) return MidSrc{(q < 0 ? 0 : n - 1) - base, 0, 0.f};
+    return MidSrc{0, 1, q < 0 ? vlo : vhi};
+}
+
+template <class M, int NCH, int BY, int WC, int D>
+__device__ __forceinline__ void lds2_consumer(const StepArgs& a, const float* iring, float* mring, int cw, int yb,
+                                              int z0, int z1) {
+    static_assert(!M::SOURCES && M::NO == M::NF, "point sources and extra fields are not blocked");
+    using R = Lds2Ring<M::NF, NCH, BY, D>;
+    constexpr int NF = M::NF, NO = M::NO, TXT = R::TXT, IROWS = R::IROWS, MROWS = R::MROWS;
+    constexpr int MPW = (MROWS + WC - 1) / WC;     // mid rows per wave (the last ones may idle)
+    constexpr int OPW = (BY + WC - 1) / WC;        // output rows per wave
+    const int lane = threadIdx.x & 63;
+    int xsl[NF], xsr[NF];
+    (void)x_sides<M, true>(a, 0, TXT, true, xsl, xsr);
+    bool any_held = false, in_fix = false;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        any_held = any_held || a.held[f] != 0 || a.out_held[f] != 0;
+        for (int k = 0; k < 6; ++k) in_fix = in_fix || a.bck[f][k] == BC_GHOST || a.bck[f][k] == BC_HELD;
+    }
+    in_fix = in_fix || any_held;
+
+    // x neighbours of lane values v (chunks of 4 per lane) by the x face rules
+    auto xnb = [&](int f, const float (&v)[NCH][4], int c, float& left, float& right) {
+        float fl, fr;
+        if (c > 0) fl = lane_from_left_wrap(v[c - 1][3]);
+        else if (xsl[f] == XS_ROT) fl = lane_from_left_wrap(v[NCH - 1][3]);
+        else fl = xsl[f] == XS_OWN ? v[0][0] : a.bcv[f][0];
+        if (c < NCH - 1) fr = lane_from_right_wrap(v[c + 1][0]);
+        else if (xsr[f] == XS_ROT) fr = lane_from_right_wrap(v[0][0]);
+        else fr = xsr[f] == XS_OWN ? v[NCH - 1][3] : a.bcv[f][1];
+        left = lane_from_left(v[c][3], fl);
+        right = lane_from_right(v[c][0], fr);
+    };
+    auto ld4 = [&](const float* p, float (&o)[4]) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+    };
+
+    int islot0 = 0;              // input slot of plane q-1 at iteration q (plane z0-2 is slot 0)
+    int mslot = 0;               // mid slot of plane q (mid plane z0-1 is slot 0)
+    for (int q = z0 - 1; q <= z1 + 1; ++q) {
+        lds_done();
+        ring_barrier();
+        // ---- mid plane q on rows yb-1 .. yb+BY (mid row m = grid row yb-1+m)
+        if (q <= z1) {
+            const int sm = islot0, s0 = islot0 + 1 == D ? 0 : islot0 + 1, sp = s0 + 1 == D ? 0 : s0 + 1;
+            const float* Im = iring + sm * R::ISLOT;
+            const float* I0 = iring + s0 * R::ISLOT;
+            const float* Ip = iring + sp * R::ISLOT;
+            float* Mq = mring + mslot * R::MSLOT;
+#pragma unroll
+            for (int k = 0; k < MPW; ++k) {
+                const int m = cw + k * WC;
+                if (m < MROWS) {
+                    const int y = yb - 1 + m;
+                    float v0[NF][3][NCH][4], vm[NF][NCH][4], vp[NF][NCH][4];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f)
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+                            for (int r = 0; r < 3; ++r)
+                                ld4(I0 + (f * IROWS + m + r) * TXT + c * 256 + lane * 4, v0[f][r][c]);
+                            ld4(Im + (f * IROWS + m + 1) * TXT + c * 256 + lane * 4, vm[f][c]);
+                            ld4(Ip + (f * IROWS + m + 1) * TXT + c * 256 + lane * 4, vp[f][c]);
+                        }
+                    if (in_fix) {
+                        // input values fixed by a rule (ghost or held rows, planes, x faces)
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) {
+                            const int* kk = a.bck[f];
+                            const float* vv = a.bcv[f];
+                            const Src pm = resolve_axis(q - 1, a.nz, kk[4], kk[5], vv[4], vv[5]);
+                            const Src p0 = resolve_axis(q, a.nz, kk[4], kk[5], vv[4], vv[5]);
+                            const Src pp = resolve_axis(q + 1, a.nz, kk[4], kk[5], vv[4], vv[5]);
+                            Src ry[3];
+#pragma unroll
+                            for (int r = 0; r < 3; ++r) ry[r] = resolve_axis(y - 1 + r, a.ny, kk[2], kk[3], vv[2], vv[3]);
+#pragma unroll
+                            for (int c = 0; c < NCH; ++c) {
+                                const int xl = c * 256 + lane * 4;
+#pragma unroll
+                                for (int r = 0; r < 3; ++r) fix_row<4>(a, f, p0, ry[r], xl, v0[f][r][c]);
+                                fix_row<4>(a, f, pm, ry[1], xl, vm[f][c]);
+                                fix_row<4>(a, f, pp, ry[1], xl, vp[f][c]);
+                            }
+                        }
+                    }
+                    Nb n[NF][NCH][4];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        float cen[NCH][4];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) cen[c][i] = v0[f][1][c][i];
+#pragma unroll
+                        for (int c = 0; c < NCH; ++c) {
+                            float left, right;
+                            xnb(f, cen, c, left, right);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                Nb& t = n[f][c][i];
+                                t.c = cen[c][i];
+                                t.xm = i > 0 ? cen[c][i - 1] : left;
+                                t.xp = i < 3 ? cen[c][i + 1] : right;
+                                t.ym = v0[f][0][c][i];
+                                t.yp = v0[f][2][c][i];
+                                t.zm = vm[f][c][i];
+                                t.zp = vp[f][c][i];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        const int xl = c * 256 + lane * 4;
+                        float o[NO][4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            Nb ni[NF];
+#pragma unroll
+                            for (int f = 0; f < NF; ++f) ni[f] = n[f][c][i];
+                            const float e[NO] = {};
+                            float oi[NO];
+                            M::cell(a, ni, 0.f, false, e, oi);
+#pragma unroll
+                            for (int s = 0; s < NO; ++s) o[s][i] = any_held ? held_out(a, s, xl + i, y, q, oi[s]) : oi[s];
+                        }
+#pragma unroll
+                        for (int s = 0; s < NO; ++s)
+                            *reinterpret_cast<float4*>(Mq + (s * MROWS + m) * TXT + c * 256 + lane * 4) =
+                                make_float4(o[s][0], o[s][1], o[s][2], o[s][3]);
+                    }
+                }
+            }
+        }
+        // ---- output plane z = q-2 on rows yb .. yb+BY-1, from mid planes z-1, z, z+1
+        const int z = q - 2;
+        if (z >= z0) {
+            const int ms_z = (mslot + 2) & 3;          // mid plane q-2
+            const int ms_m = (mslot + 1) & 3;          // mid plane q-3
+            const int ms_p = (mslot + 3) & 3;          // mid plane q-1
+#pragma unroll
+            for (int rr = 0; rr < OPW; ++rr) {
+                const int r = cw + rr * WC;
+                if (r >= BY) break;
+                const int y = yb + r;
+                float v0[NF][3][NCH][4], vm[NF][NCH][4], vp[NF][NCH][4];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int* kk = a.bck[f];
+                    const float* vv = a.bcv[f];
+                    // mid rows y-1, y, y+1 and mid planes z-1, z+1 by the face rules
+                    MidSrc ry[3];
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) ry[t] = mid_src(y - 1 + t, a.ny, yb - 1, kk[2], kk[3], vv[2], vv[3]);
+                    const MidSrc pzm = mid_src(z - 1, a.nz, z - 1, kk[4], kk[5], vv[4], vv[5]);
+                    const MidSrc pzp = mid_src(z + 1, a.nz, z - 1, kk[4], kk[5], vv[4], vv[5]);
+                    // pzm.idx / pzp.idx: 0 = plane z-1, 1 = plane z, 2 = plane z+1
+                    const float* Mz = mring + ms_z * R::MSLOT + f * MROWS * TXT;
+                    const float* Mm = mring + (pzm.idx == 1 ? ms_z : ms_m) * R::MSLOT + f * MROWS * TXT;
+                    const float* Mp = mring + (pzp.idx == 1 ? ms_z : ms_p) * R::MSLOT + f * MROWS * TXT;
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+#pragma unroll
+                        for (int t = 0; t < 3; ++t) {
+                            ld4(Mz + ry[t].idx * TXT + c * 256 + lane * 4, v0[f][t][c]);
+                            if (ry[t].cst)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) v0[f][t][c][i] = ry[t].v;
+                        }
+                        ld4(Mm + ry[1].idx * TXT + c * 256 + lane * 4, vm[f][c]);
+                        ld4(Mp + ry[1].idx * TXT + c * 256 + lane * 4, vp[f][c]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (pzm.cst) vm[f][c][i] = pzm.v;
+                            if (pzp.cst) vp[f][c][i] = pzp.v;
+                        }
+                    }
+                }
+                Nb n[NF][NCH][4];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    float cen[NCH][4];
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) cen[c][i] = v0[f][1][c][i];
+#pragma unroll
+                    for (int c = 0; c < NCH; ++c) {
+                        float left, right;
+                        xnb(f, cen, c, left, right);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            Nb& t = n[f][c][i];
+                            t.c = cen[c][i];
+                            t.xm = i > 0 ? cen[c][i - 1] : left;
+                            t.xp = i < 3 ? cen[c][i + 1] : right;
+                            t.ym = v0[f][0][c][i];
+                            t.yp = v0[f][2][c][i];
+                            t.zm = vm[f][c][i];
+                            t.zp = vp[f][c][i];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    const int xl = c * 256 + lane * 4;
+                    float o[NO][4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        Nb ni[NF];
+#pragma unroll
+                        for (int f = 0; f < NF; ++f) ni[f] = n[f][c][i];
+                        const float e[NO] = {};
+                        float oi[NO];
+                        M::cell(a, ni, 0.f, false, e, oi);
+#pragma unroll
+                        for (int s = 0; s < NO; ++s) o[s][i] = any_held ? held_out(a, s, xl + i, y, z, oi[s]) : oi[s];
+                    }
+                    if (y < a.ny) {
+                        const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
+#pragma unroll
+                        for (int s = 0; s < NO; ++s) store_vec<StF32, 4>(a.out[s], idx, o[s]);
+                    }
+                }
+            }
+        }
+        islot0 = islot0 + 1 == D ? 0 : islot0 + 1;
+        mslot = (mslot + 1) & 3;
+    }
+}
+
+template <class M, int NCH, int BY, int WC, int D>
+__global__ __launch_bounds__(64 * (WC + 1)) void lds2_kernel(const StepArgs* __restrict__ pa) {
+    using R = Lds2Ring<M::NF, NCH, BY, D>;
+    static_assert(R::FITS, "ring shape does not fit");
+    __shared__ __attribute__((aligned(16))) float iring[D * R::ISLOT];
+    __shared__ __attribute__((aligned(16))) float mring[4 * R::MSLOT];
+    const StepArgs& a = *pa;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const TileXYZ tc = tile_coords(a, xcd_tile(blockIdx.x, gridDim.x));
+    const int yb = tc.y * BY;
+    const int z0 = tc.z * a.cz;
+    const int z1 = min(z0 + a.cz, a.nz);
+    if (w == 0) lds2_producer<M, NCH, BY, WC, D>(a, iring, yb, z0, z1);
+    else lds2_consumer<M, NCH, BY, WC, D>(a, iring, mring, w - 1, yb, z0, z1);
+}
+
 // ------------------------------------------------------------ batched kernel
 // A persistent launch walks the (grid, slab) work items of many grids.  The
 // host writes, before each tick, `meta` = {ngrids, total_items, first_item[0..

@@ -110,6 +110,13 @@ int lds_cfg_index(int nch, int by, int wc, int d) {
     return -1;
 }
 
+int lds2_cfg_index(int nch, int by, int wc, int d) {
+    for (int i = 0; i < kNumLds2Cfgs; ++i)
+        if (kLds2Cfgs[i].nch == nch && kLds2Cfgs[i].by == by && kLds2Cfgs[i].wc == wc && kLds2Cfgs[i].d == d)
+            return i;
+    return -1;
+}
+
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h, const StepArgs* d,
                        long long blocks, hipStream_t s) {
     const bool diff = pm <= PM_DIFF4;
@@ -232,13 +239,14 @@ void fill_mirror(StepArgs& a, int f) {
 // Decomposition of a tiled plan: fills tiles_* / cz, returns workgroups.
 long long set_tiling(StepArgs& a, const rd_plan& p) {
     // LDS ring: whole rows (vx cells per lane), ry rows per workgroup
-    const int tx = 64 * p.vx, by = p.kernel == RD_KERNEL_LDS ? p.ry : p.ry * p.waves;
+    const bool ring = p.kernel == RD_KERNEL_LDS || p.kernel == RD_KERNEL_LDS2;
+    const int tx = 64 * p.vx, by = ring ? p.ry : p.ry * p.waves;
     const int cz = (p.cz <= 0 || p.cz > a.nz) ? a.nz : p.cz;
     a.tiles_x = (a.nx + tx - 1) / tx;
     a.tiles_y = (a.ny + by - 1) / by;
     a.cz = cz;
     a.chunks_z = (a.nz + cz - 1) / cz;
-    a.zfast = (p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS) && p.order == 1;
+    a.zfast = (p.kernel == RD_KERNEL_BLOCK || ring) && p.order == 1;
     return (long long)a.tiles_x * a.tiles_y * a.chunks_z;
 }
 
@@ -310,6 +318,16 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
         *cfg_out = cfg;
         return RD_OK;
     }
+    if (p.kernel == RD_KERNEL_LDS2) {
+        const int cfg = (p.vx == 4 || p.vx == 8) ? lds2_cfg_index(p.vx / 4, p.ry, p.waves, p.prefetch) : -1;
+        if (cfg < 0) return fail(RD_EINVAL, "two-step LDS ring shape not available");
+        if (g->nx != 64 * p.vx) return fail(RD_EINVAL, "the LDS ring kernel needs rows of exactly 64*vx cells");
+        if (g->npass != 1 || !lds2_ok(g->storage, g->pass_pm[0], cfg))
+            return fail(RD_EINVAL, "two-step LDS ring shape not compiled for this model and storage");
+        if (p.cz < 0) return fail(RD_EINVAL, "cz must be >= 0");
+        *cfg_out = cfg;
+        return RD_OK;
+    }
     if (p.kernel != RD_KERNEL_TILED) return fail(RD_EINVAL, "unknown kernel kind");
     const int cfg = tile_cfg_index(p.vx, p.ry, p.waves, p.prefetch);
     if (cfg < 0) return fail(RD_EINVAL, "tile shape not available");
@@ -337,7 +355,8 @@ int apply_plan(rd_grid* g) {
     for (int par = 0; par < 2; ++par)
         for (int k = 0; k < g->npass; ++k) {
             StepArgs& a = g->args[par][k];
-            if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS)
+            if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS ||
+                p.kernel == RD_KERNEL_LDS2)
                 g->blocks[k] = set_tiling(a, p);
             else g->blocks[k] = 0;
         }
@@ -361,10 +380,10 @@ int launch_one_step(rd_grid* g, int parity) {
     return RD_OK;
 }
 
-int build_graph(rd_grid* g, int parity, int chunk, hipGraphExec_t* out) {
+int build_graph(rd_grid* g, int parity, int launches, hipGraphExec_t* out) {
     RD_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
     int rc = RD_OK;
-    for (int i = 0; i < chunk && rc == RD_OK; ++i) rc = launch_one_step(g, (parity + i) & 1);
+    for (int i = 0; i < launches && rc == RD_OK; ++i) rc = launch_one_step(g, (parity + i) & 1);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(g->stream, &graph);
     if (rc != RD_OK) {
@@ -378,13 +397,28 @@ int build_graph(rd_grid* g, int parity, int chunk, hipGraphExec_t* out) {
     return RD_OK;
 }
 
+// Time steps one launch of the plan advances.
+int steps_per_launch(const rd_grid* g) { return g->eff.kernel == RD_KERNEL_LDS2 ? 2 : 1; }
+
+// One step with the direct kernel (the odd step left over by a two-step plan).
+int launch_direct_step(rd_grid* g, int parity) {
+    for (int k = 0; k < g->npass; ++k) {
+        const hipError_t e = launch_pass(g->storage, g->pass_pm[k], RD_KERNEL_DIRECT, -1, g->args[parity][k],
+                                         g->d_args + parity * 2 + k, 0, g->stream);
+        if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return RD_OK;
+}
+
 int step_grid(rd_grid* g, int64_t n) {
-    const int chunk = g->eff.graph_chunk;
+    const int chunk = g->eff.graph_chunk;          // steps per graph (even)
+    const int sp = steps_per_launch(g);
+    const int launches = chunk / sp;               // launches per graph
     if (chunk >= 2 && g->stream != nullptr && n >= chunk) {
         if (g->gchunk != chunk) {
             drop_graphs(g);
             for (int par = 0; par < 2; ++par) {
-                const int rc = build_graph(g, par, chunk, &g->gexec[par]);
+                const int rc = build_graph(g, par, launches, &g->gexec[par]);
                 if (rc) {
                     drop_graphs(g);
                     return rc;
@@ -393,12 +427,18 @@ int step_grid(rd_grid* g, int64_t n) {
             g->gchunk = chunk;
         }
         while (n >= chunk) {
-            RD_HIP(hipGraphLaunch(g->gexec[g->cur], g->stream));   // chunk is even: parity unchanged
+            RD_HIP(hipGraphLaunch(g->gexec[g->cur], g->stream));
+            g->cur ^= launches & 1;
             n -= chunk;
         }
     }
-    for (int64_t i = 0; i < n; ++i) {
+    for (; n >= sp; n -= sp) {
         const int rc = launch_one_step(g, g->cur);
+        if (rc) return rc;
+        g->cur ^= 1;
+    }
+    if (n > 0) {
+        const int rc = launch_direct_step(g, g->cur);
         if (rc) return rc;
         g->cur ^= 1;
     }
@@ -944,6 +984,21 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
         p.order = 1;
         cands.push_back(p);
     }
+    for (int i = 0; i < kNumLds2Cfgs && g->npass == 1; ++i) {
+        const LdsCfg c = kLds2Cfgs[i];
+        if (g->nx != 256 * c.nch || !lds2_ok(g->storage, g->pass_pm[0], i)) continue;
+        for (int cz : {0, 64, 32, 16}) {
+            if (cz != 0 && cz >= g->nz) continue;
+            rd_plan p{};
+            p.kernel = RD_KERNEL_LDS2;
+            p.vx = 4 * c.nch;
+            p.ry = c.by;
+            p.waves = c.wc;
+            p.prefetch = c.d;
+            p.cz = cz;
+            cands.push_back(p);
+        }
+    }
     for (int i = 0; i < kNumLdsCfgs; ++i) {
         const LdsCfg c = kLdsCfgs[i];
         if (g->nx != 256 * c.nch) continue;
@@ -971,9 +1026,9 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     for (const rd_plan& p : cands) {
         g->plan = p;
         if (apply_plan(g) != RD_OK) continue;
-        if ((rc = step_grid(g, 1)) != RD_OK) break;
+        if ((rc = step_grid(g, 2)) != RD_OK) break;
         if (hipEventRecord(e0, g->stream) != hipSuccess) { rc = fail(RD_EDEVICE, "event"); break; }
-        if ((rc = step_grid(g, trial_steps)) != RD_OK) break;
+        if ((rc = step_grid(g, trial_steps + (trial_steps & 1))) != RD_OK) break;
         if (hipEventRecord(e1, g->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rc = fail(RD_EDEVICE, "event sync failed");
             break;

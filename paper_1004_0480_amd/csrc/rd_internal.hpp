@@ -50,6 +50,12 @@ constexpr LdsCfg kLdsCfgs[] = {
 };
 constexpr int kNumLdsCfgs = sizeof(kLdsCfgs) / sizeof(kLdsCfgs[0]);
 
+// Ring shapes of the two-steps-per-launch LDS kernel (same fields).
+constexpr LdsCfg kLds2Cfgs[] = {
+    {1, 4, 8, 6}, {2, 4, 8, 6}, {1, 8, 8, 5}, {2, 6, 6, 4}, {1, 6, 12, 4}, {2, 6, 12, 4}, {2, 4, 12, 6}, {1, 4, 12, 6},
+};
+constexpr int kNumLds2Cfgs = sizeof(kLds2Cfgs) / sizeof(kLds2Cfgs[0]);
+
 constexpr unsigned bits(std::initializer_list<int> l) {
     unsigned m = 0;
     for (int i : l) m |= 1u << i;
@@ -102,12 +108,26 @@ constexpr bool lds_ok(int storage, int pm, int i) {
     return bytes <= 160 * 1024 && (c.d - 4) * nf * rows * c.nch <= 63 && c.d >= 4 && c.by % c.wc == 0;
 }
 
+// Two-steps-per-launch shape i: FP32, diffusion or Brusselator (no point
+// sources), input ring of by+4 rows and four intermediate planes of by+2
+// rows within the LDS and the vmcnt range.
+constexpr bool lds2_ok(int storage, int pm, int i) {
+    if (storage != ST_F32 || !(pm == PM_DIFF1 || pm == PM_DIFF2 || pm == PM_BRUSS) || i < 0 || i >= kNumLds2Cfgs)
+        return false;
+    const LdsCfg c = kLds2Cfgs[i];
+    const int nf = pm_fields(pm);
+    const long long bytes = 4LL * 256 * c.nch * nf * (c.d * (c.by + 4) + 4 * (c.by + 2));
+    return bytes <= 160 * 1024 && (c.d - 4) * nf * (c.by + 4) * c.nch <= 63 && c.d >= 4 && c.wc <= 15;
+}
+
 int tile_cfg_index(int vx, int ry, int w, int pf);   // -1 if no such shape
 int lds_cfg_index(int nch, int by, int wc, int d);   // -1 if no such shape
+int lds2_cfg_index(int nch, int by, int wc, int d);  // -1 if no such shape
 int block_cfg_index(int vx, int ry, int w, int cz);  // -1 if no such shape
 
 // Launch one pass.  kernel: 1 direct, 2 tiled (cfg = kTileCfgs index),
-// 3 plane block (cfg = kBlockCfgs index), 4 LDS ring (cfg = kLdsCfgs index).
+// 3 plane block (cfg = kBlockCfgs index), 4 LDS ring (cfg = kLdsCfgs index),
+// 5 LDS ring with two steps per launch (cfg = kLds2Cfgs index).
 // `h` is the host copy of the arguments (for the launch shape), `d` the same
 // arguments in device memory (what the kernel reads).
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h,

@@ -72,6 +72,18 @@ hipError_t run_lds(const StepArgs* d, long long blocks, hipStream_t s) {
     }
 }
 
+template <class M, int I>
+hipError_t run_lds2(const StepArgs* d, long long blocks, hipStream_t s) {
+    if constexpr (lds2_ok(kStorage, PmOf<M>::v, I)) {
+        constexpr LdsCfg c = kLds2Cfgs[I];
+        hipLaunchKernelGGL((lds2_kernel<M, c.nch, c.by, c.wc, c.d>), dim3((unsigned)blocks), dim3(64 * (c.wc + 1)),
+                           0, s, d);
+        return hipGetLastError();
+    } else {
+        return hipErrorNotSupported;
+    }
+}
+
 // Launch table index `cfg` of a shape table: one branch per compiled entry.
 template <class M, int... I>
 hipError_t run_tiled_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
@@ -97,9 +109,18 @@ hipError_t run_lds_index(int cfg, const StepArgs* d, long long blocks, hipStream
     return r;
 }
 
+template <class M, int... I>
+hipError_t run_lds2_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
+                          std::integer_sequence<int, I...>) {
+    hipError_t r = hipErrorInvalidValue;
+    ((void)(cfg == I && ((r = run_lds2<M, I>(d, blocks, s)), true)), ...);
+    return r;
+}
+
 template <class M>
 hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, long long blocks,
                      hipStream_t s) {
+    if (kernel == 5) return run_lds2_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLds2Cfgs>{});
     if (kernel == 1) return run_direct<M>(h, d, s);
     if (kernel == 4) return run_lds_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLdsCfgs>{});
     if (kernel == 3) return run_block_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumBlockCfgs>{});

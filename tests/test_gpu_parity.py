@@ -27,6 +27,9 @@ TILE_SHAPES = [(4, 1, 4, 1), (4, 1, 4, 2), (2, 2, 4, 2), (2, 1, 4, 2), (4, 2, 4,
 # computing waves, ring slots); only rows of exactly 64 * vx cells take them
 LDS_SHAPES = [(4, 8, 4, 7), (4, 8, 8, 7), (8, 8, 4, 6), (8, 4, 4, 6), (8, 8, 8, 6), (8, 4, 4, 7),
               (8, 8, 8, 7), (4, 12, 6, 5), (8, 12, 6, 5), (8, 6, 6, 5)]
+# two-steps-per-launch shapes (same fields)
+LDS2_SHAPES = [(4, 4, 8, 6), (8, 4, 8, 6), (4, 8, 8, 5), (8, 6, 6, 4), (4, 6, 12, 4), (8, 6, 12, 4),
+               (8, 4, 12, 6), (4, 4, 12, 6)]
 BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
                 (2, 1, 4, 4), (4, 2, 1, 2), (4, 1, 1, 2), (4, 2, 1, 4), (4, 4, 1, 2), (4, 2, 2, 2),
                 (4, 3, 1, 2)]
@@ -61,6 +64,8 @@ def compiled_plans(w, storage="f32", czs=(0, 8)):
               for vx, ry, wv, cz in BLOCK_SHAPES for o in (0, 1)]
     cands += [dict(kernel="lds", vx=vx, ry=by, waves=wc, prefetch=d, cz=cz, order=o)
               for vx, by, wc, d in LDS_SHAPES for cz in czs for o in (0, 1)]
+    cands += [dict(kernel="lds2", vx=vx, ry=by, waves=wc, prefetch=d, cz=cz, order=o)
+              for vx, by, wc, d in LDS2_SHAPES for cz in czs for o in (0, 1)]
     for p in cands:
         try:
             g.set_plan(**p)
@@ -476,6 +481,8 @@ def test_whole_tile_rows_every_plan(case):
     plans = compiled_plans(w, czs=(0, 4, 7))
     if w.shape[2] in (256, 512) and w.spec.model in ("diffusion", "brusselator", "pollutant"):
         assert any(p["kernel"] == "lds" for p in plans), case
+    if w.shape[2] in (256, 512) and w.spec.model in ("diffusion", "brusselator"):
+        assert any(p["kernel"] == "lds2" for p in plans), case
     for plan in plans:
         got, _ = gpu_run(w, steps, plan=plan)
         if base is None:
@@ -485,6 +492,33 @@ def test_whole_tile_rows_every_plan(case):
             continue
         for s in range(w.spec.ns):
             assert np.array_equal(got[s], base[s]), (case, plan, s)
+
+
+@pytest.mark.parametrize("name,shape", [("brusselator256", (6, 12, 256)), ("diffusion512", (9, 7, 512))])
+def test_two_step_plans_with_graphs_and_odd_counts(name, shape):
+    """Two steps per launch: graph chunks of 2, 4 and 6 steps and odd step
+    counts (the last step then runs on the direct kernel) give the bits of
+    single steps."""
+    w = W.make_workload(name, shape=shape)
+    ref, _ = gpu_run(w, 9, plan=dict(kernel="direct"))
+    for vx, by, wc, d in LDS2_SHAPES:
+        for chunk in (0, 2, 4, 6):
+            plan = dict(kernel="lds2", vx=vx, ry=by, waves=wc, prefetch=d, cz=0, graph_chunk=chunk)
+            g = rd.Grid(w.shape, w.spec.ns, w.spec.h)
+            g.set_model(w.spec)
+            try:
+                g.set_plan(**plan)
+            except rd.RDError:
+                g.close()
+                continue
+            for s_, f in enumerate(w.fields):
+                g.write(s_, f)
+            g.step(3)
+            g.step(6)          # 9 steps in two calls: odd, then even
+            got = g.read_all()
+            g.close()
+            for s_ in range(w.spec.ns):
+                assert np.array_equal(got[s_], ref[s_]), (plan, s_)
 
 
 def test_zero_steps_is_identity():
