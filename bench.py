@@ -48,9 +48,8 @@ def kernel_source_digest() -> str:
 
 
 def measured_traffic(name: str, digest: str):
-    """HBM bytes per step (per launch for a one-kernel step) from the
-    committed rocprofv3 PMC summary, if it was taken on the current kernel
-    sources; else None."""
+    """The committed rocprofv3 PMC summary of this workload, if it was taken
+    on the current kernel sources; else None."""
     path = os.path.join(PROFILES, "%s_pmc.json" % name)
     try:
         with open(path) as fh:
@@ -59,7 +58,7 @@ def measured_traffic(name: str, digest: str):
         return None
     if rec.get("source_digest") != digest:
         return None
-    return rec.get("hbm_bytes_per_step")
+    return rec
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
@@ -102,7 +101,8 @@ def copy_ceiling(torch, stream, nbytes: int, reps: int = 10):
 
 # ------------------------------------------------ profile summaries (rocprofv3)
 
-STEP_KERNELS = ("rdk::block_kernel", "rdk::tiled_kernel", "rdk::direct_kernel")
+STEP_KERNELS = ("rdk::block_kernel", "rdk::tiled_kernel", "rdk::direct_kernel", "rdk::lds_kernel",
+                "rdk::lds2_kernel")
 
 
 def _counter_rows(d: str):
@@ -164,16 +164,20 @@ def pmc_summary(args):
         rd_b += f_k * 1024.0 * rs
         wr_b += w_k * 1024.0 * ws
     cells = int(np.prod(W.DEFAULT_SHAPES[args.workload]))
+    # one launch set reads and writes every field once: one step, or two for
+    # the two-step (temporally blocked) kernel
+    spl = 2 if any("rdk::lds2_kernel" in k for k in knames) else 1
     alg = alg_bytes_per_cell(args.workload, args.storage) * cells
     rec = {"kernel": knames[0] if len(knames) == 1 else knames,
            "workload": "%s %s, %s storage" % (args.workload, W.DEFAULT_SHAPES[args.workload], args.storage),
            "source_digest": kernel_source_digest(), "command": args.pmc_command,
-           "per_kernel": per_kernel,
+           "per_kernel": per_kernel, "steps_per_launch": spl,
            "calibration": "copy_kernel moving %d bytes each way in the same run" % COPY_PROBE_BYTES,
            "copy_fetch_kib_raw": f_c, "copy_write_kib_raw": w_c, "read_scale": rs, "write_scale": ws,
-           "hbm_read_bytes_per_step": rd_b, "hbm_write_bytes_per_step": wr_b,
+           "hbm_read_bytes_per_launch_set": rd_b, "hbm_write_bytes_per_launch_set": wr_b,
            "hbm_bytes_per_launch": (rd_b + wr_b) if len(knames) == 1 else None,
-           "hbm_bytes_per_step": rd_b + wr_b, "algorithmic_bytes_per_step": alg,
+           "hbm_bytes_per_step": (rd_b + wr_b) / spl,
+           "algorithmic_bytes_per_launch_set": alg,
            "traffic_over_algorithmic": (rd_b + wr_b) / alg}
     out = os.path.join(PROFILES, "%s_pmc.json" % args.workload)
     with open(out, "w") as fh:
@@ -350,7 +354,10 @@ def main():
     launch_ms = ms_per_step * steps_per_launch
     achieved = bpc * w.cells / (launch_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
-    traffic = measured_traffic(w.name, digest)
+    pmc = measured_traffic(w.name, digest)
+    traffic = None
+    if pmc is not None and pmc.get("steps_per_launch", 1) == steps_per_launch:
+        traffic = pmc.get("hbm_bytes_per_launch") if passes == 1 else pmc.get("hbm_bytes_per_step")
     ceiling = copy_ceiling(torch, stream, COPY_PROBE_BYTES)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
