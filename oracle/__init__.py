@@ -6,8 +6,9 @@ with the HIP path: it reads a problem description made of plain numbers
 (a ``workloads.ModelSpec``-like object) and numpy float64 arrays.
 
 The arithmetic lives in ``rd_oracle.c`` (section 2, Eqs. (2) and (5), the
-7-point Laplacian, the boundary handling of section 4.1 and the four Table 1
-model families); see its header for the exact definition.
+7-point Laplacian or the 19-point one of Eqs. (3)-(4), the boundary handling
+of section 4.1 and the four Table 1 model families); see its header for the
+exact definition.
 """
 from __future__ import annotations
 
@@ -45,6 +46,7 @@ class _Problem(C.Structure):
         ("src_cell", C.POINTER(C.c_int64)),
         ("src_species", C.POINTER(C.c_int32)),
         ("src_rate", C.POINTER(C.c_double)),
+        ("stencil", C.c_int32),
     ]
 
 
@@ -82,6 +84,7 @@ def _problem(spec, shape):
     P.model = _MODEL[spec.model]
     P.h = float(spec.h)
     P.dt = float(spec.dt)
+    P.stencil = int(getattr(spec, "stencil", 7))
     for s in range(spec.ns):
         for d in range(3):
             P.K[s][d] = float(spec.K[s][d])

@@ -93,6 +93,36 @@ static double laplacian(const double *f, int64_t nx, int64_t ny, int64_t nz,
     return (K[0] * dx + K[1] * dy + K[2] * dz) / (h * h);
 }
 
+/* 19-point Laplacian of Eqs. (3)-(4), isotropic coefficient D:
+ *   D/(6h^2) * sum over the 3x3x3 block of T_pqr c[i+p][j+q][k+r]
+ * with T = -24 at the centre, 2 at the six face neighbours, 1 at the twelve
+ * edge neighbours (|p|+|q|+|r| = 2) and 0 at the eight corners. */
+static double laplacian19(const double *f, int64_t nx, int64_t ny, int64_t nz,
+                          const int32_t kind[6], const double val[6], double h,
+                          double D, int64_t i, int64_t j, int64_t k)
+{
+    double sum = 0.0;
+    for (int r = -1; r <= 1; ++r)
+        for (int q = -1; q <= 1; ++q)
+            for (int p = -1; p <= 1; ++p) {
+                const int order = abs(p) + abs(q) + abs(r);
+                const double T = order == 0 ? -24.0 : order == 1 ? 2.0 : order == 2 ? 1.0 : 0.0;
+                if (T != 0.0)
+                    sum += T * sample(f, nx, ny, nz, kind, val, i + p, j + q, k + r);
+            }
+    return D * sum / (6.0 * h * h);
+}
+
+/* The Laplacian the problem asks for (K: per-axis coefficients; the 19-point
+ * form uses K[0]). */
+static double lap_of(const or_problem *P, const double *f, const int32_t kind[6],
+                     const double val[6], const double K[3], int64_t i, int64_t j, int64_t k)
+{
+    if (P->stencil == 19)
+        return laplacian19(f, P->nx, P->ny, P->nz, kind, val, P->h, K[0], i, j, k);
+    return laplacian(f, P->nx, P->ny, P->nz, kind, val, P->h, K, i, j, k);
+}
+
 /* ---------------------------------------------------------------- sources */
 
 typedef struct { int64_t cell; int32_t species; double rate; } source_t;
@@ -128,6 +158,10 @@ static int valid(const or_problem *P)
     if (P->model == OR_FRONT_CH && P->ns != 3) return 0;
     if (P->model < OR_DIFFUSION || P->model > OR_POLLUTANT) return 0;
     if (P->model == OR_POLLUTANT && !P->wind) return 0;
+    if (P->stencil != 7 && P->stencil != 19) return 0;
+    if (P->stencil == 19)
+        for (int s = 0; s < P->ns; ++s)
+            if (P->K[s][1] != P->K[s][0] || P->K[s][2] != P->K[s][0]) return 0;
     for (int s = 0; s < P->ns; ++s)
         for (int a = 0; a < 3; ++a) {
             const int lo = P->bc_kind[s][2 * a], hi = P->bc_kind[s][2 * a + 1];
@@ -154,8 +188,7 @@ static void chemical_potential(const or_problem *P, const double *C, double *mu)
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
                 const double c = sample(C, nx, ny, nz, P->bc_kind[2], P->bc_value[2], i, j, k);
-                const double lap = laplacian(C, nx, ny, nz, P->bc_kind[2], P->bc_value[2],
-                                             P->h, unit, i, j, k);
+                const double lap = lap_of(P, C, P->bc_kind[2], P->bc_value[2], unit, i, j, k);
                 mu[(k * ny + j) * nx + i] = gamma * c * c * c - eps * c - kappa * lap;
             }
 }
@@ -180,8 +213,7 @@ static void step(const or_problem *P, const double *in, double *out, double *mu,
                 double c[OR_MAX_SPECIES], rate[OR_MAX_SPECIES];
                 for (int s = 0; s < ns; ++s) {
                     c[s] = sample(in + s * N, nx, ny, nz, P->bc_kind[s], P->bc_value[s], i, j, k);
-                    rate[s] = laplacian(in + s * N, nx, ny, nz, P->bc_kind[s], P->bc_value[s],
-                                        h, P->K[s], i, j, k);
+                    rate[s] = lap_of(P, in + s * N, P->bc_kind[s], P->bc_value[s], P->K[s], i, j, k);
                 }
                 switch (P->model) {
                 case OR_BRUSSELATOR: {
@@ -192,7 +224,7 @@ static void step(const or_problem *P, const double *in, double *out, double *mu,
                 }
                 case OR_FRONT_CH: {
                     const double r = P->p[0] * c[0] * c[1];
-                    const double lap_mu = laplacian(mu, nx, ny, nz, MU_KIND, MU_VAL, h, unit, i, j, k);
+                    const double lap_mu = lap_of(P, mu, MU_KIND, MU_VAL, unit, i, j, k);
                     rate[0] += -r;
                     rate[1] += -r;
                     rate[2] += r + P->p[1] * lap_mu;

@@ -12,7 +12,8 @@
  *   c_s(t+dt) = c_s(t) + dt * [ L_s(c_s) + A_s(c_s) + R_s(c(t)) + E_s ]
  * with L_s the 7-point Laplacian (the "more commonly used seven-point
  * stencil" mentioned beside Eqs. (3)-(4)), allowing a different coefficient
- * per axis, A_s the first-order upwind advection term of section 4.1, R_s the
+ * per axis, or the 19-point Laplacian of Eqs. (3)-(4) (isotropic
+ * coefficient), A_s the first-order upwind advection term of section 4.1, R_s the
  * reaction term evaluated at the old time level, and E_s point emissions
  * (Table 1, advection-diffusion row).  Boundary values are fixed before each
  * step from the boundary conditions (section 4.1, Table 3 lines 4-5).
@@ -25,7 +26,10 @@
  *   OR_HELD      the face's own layer of cells is held at a fixed value and
  *                never updated (a Dirichlet layer); its ghost is that value.
  * A cell lying on several held faces takes the value of the first such face
- * in the order x-, x+, y-, y+, z-, z+.
+ * in the order x-, x+, y-, y+, z-, z+.  A 19-point edge neighbour may lie
+ * outside along two axes (the edge ghosts of section 4.1): the rule of the
+ * first such axis in the order x, y, z applies first (a mirror or periodic
+ * rule moves that coordinate inside and the next axis is resolved).
  *
  * Arrays: one species is a float64 array [nz][ny][nx] (x fastest), as in the
  * paper's C[Depth][Height][Width]; a state is ns such arrays back to back.
@@ -73,6 +77,7 @@ typedef struct or_problem {
     const int64_t *src_cell;              /* linear index (k*ny + j)*nx + i   */
     const int32_t *src_species;
     const double *src_rate;
+    int32_t stencil;                      /* 7, or 19 (needs K[s][0]=K[s][1]=K[s][2]) */
 } or_problem;
 
 /* Advance `state` (ns*nz*ny*nx doubles) by nsteps explicit Euler steps in

@@ -53,7 +53,9 @@ class ModelSpec:
     ``f``.  ``params`` holds the model's named reaction constants.  ``wind``
     (pollutant only) is the +x wind speed per z-layer, length nz.  ``sources``
     (pollutant only) is a tuple (cell, species, rate) of equal-length arrays,
-    ``cell`` the linear index z*ny*nx + y*nx + x.
+    ``cell`` the linear index z*ny*nx + y*nx + x.  ``stencil`` is the
+    Laplacian: 7 (the workloads' 7-point form) or 19 (the paper's 19-point
+    form, isotropic coefficients only).
     """
     model: str
     ns: int
@@ -64,6 +66,7 @@ class ModelSpec:
     params: Dict[str, float] = field(default_factory=dict)
     wind: Optional[np.ndarray] = None
     sources: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
+    stencil: int = 7
 
     def copy(self) -> "ModelSpec":
         return ModelSpec(self.model, self.ns, self.dt, self.h,
@@ -71,7 +74,7 @@ class ModelSpec:
                          [list(r) for r in self.bc], dict(self.params),
                          None if self.wind is None else self.wind.copy(),
                          None if self.sources is None else
-                         tuple(a.copy() for a in self.sources))
+                         tuple(a.copy() for a in self.sources), self.stencil)
 
 
 @dataclass

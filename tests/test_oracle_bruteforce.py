@@ -66,7 +66,7 @@ class Exact:
 UNIT = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
 
 
-def lap(get, p, K, h):
+def lap7(get, p, K, h):
     total = F(0)
     for axis, e in enumerate(UNIT):
         up = tuple(a + b for a, b in zip(p, e))
@@ -75,9 +75,26 @@ def lap(get, p, K, h):
     return total / (h * h)
 
 
+# Eq. (4): the 19-point weights T_{p,q,r} as three 3x3 layers r = -1, 0, +1
+# (each layer: rows q = -1..1, columns p = -1..1); Eq. (3) divides by 6h^2.
+T_OUTER = [[0, 1, 0], [1, 2, 1], [0, 1, 0]]
+T_MIDDLE = [[1, 2, 1], [2, -24, 2], [1, 2, 1]]
+
+
+def lap19(get, p, K, h):
+    total = F(0)
+    for r, layer in ((-1, T_OUTER), (0, T_MIDDLE), (1, T_OUTER)):
+        for qi, row in enumerate(layer):
+            for pi, t in enumerate(row):
+                if t:
+                    total += t * get((p[0] + pi - 1, p[1] + qi - 1, p[2] + r))
+    return K[0] * total / (6 * h * h)
+
+
 def exact_step(spec, state):
     ns, h, dt = spec.ns, fr(spec.h), fr(spec.dt)
     K = [[fr(v) for v in row] for row in spec.K]
+    lap = lap19 if getattr(spec, "stencil", 7) == 19 else lap7
     P = {k: fr(v) for k, v in spec.params.items()}
     gets = [Exact(state[s], spec.bc[s]) for s in range(ns)]
     cells = [(x, y, z) for z in range(N) for y in range(N) for x in range(N)]
@@ -163,6 +180,29 @@ CASES = {
         [[(PERIODIC, 0), (PERIODIC, 0), (MIRROR, 0), (GHOST, 1.0), (MIRROR, 0), (MIRROR, 0)]] * 2,
         {"decay": 0.125, "kab": 0.25}, wind=np.array([0.5, 1.0, 2.0, 4.0]),
         sources=(np.array([0, 63], np.int64), np.array([0, 1], np.int32), np.array([1.0, 3.0]))),
+    # the 19-point Laplacian of Eqs. (3)-(4): edge neighbours reach the edge ghosts
+    "diffusion19_ghost_held": lambda: ModelSpec(
+        "diffusion", 2, 1 / 16, 1.0, [[1.0] * 3, [0.5] * 3],
+        [[(GHOST, 0.25), (MIRROR, 0), (HELD, 1.5), (GHOST, -1.0), (MIRROR, 0), (HELD, 0.75)],
+         [(HELD, 2.0), (HELD, -0.5), (MIRROR, 0), (MIRROR, 0), (GHOST, 3.0), (GHOST, 0.0)]], stencil=19),
+    "diffusion19_periodic_h2": lambda: ModelSpec(
+        "diffusion", 1, 1 / 8, 2.0, [[1.0] * 3],
+        [[(PERIODIC, 0.0), (PERIODIC, 0.0), (MIRROR, 0), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0)]],
+        stencil=19),
+    "brusselator19_mixed": lambda: ModelSpec(
+        "brusselator", 2, 1 / 128, 1.0, [[1.0] * 3, [8.0] * 3],
+        [[(PERIODIC, 0), (PERIODIC, 0), (MIRROR, 0), (MIRROR, 0), (GHOST, 4.5), (GHOST, 1.5)]] * 2,
+        {"a": 4.5, "b": 6.75}, stencil=19),
+    "front19_held": lambda: ModelSpec(
+        "front_ch", 3, 1 / 64, 1.0, [[1.0] * 3, [1.0] * 3, [0.25] * 3],
+        [[(MIRROR, 0)] * 4 + [(HELD, 1.0), (MIRROR, 0)], [(MIRROR, 0)] * 6, [(MIRROR, 0)] * 6],
+        {"k": 1.0, "M": 0.1, "kappa": 1.0, "eps": 1.0, "gamma": 1.0}, stencil=19),
+    "pollutant19_inflow": lambda: ModelSpec(
+        "pollutant", 2, 1 / 32, 1.0, [[0.5] * 3] * 2,
+        [[(GHOST, 0.0)] + [(MIRROR, 0)] * 5] * 2, {"decay": 0.01, "kab": 0.02},
+        wind=np.array([0.0, 0.5, 0.75, 1.0]),
+        sources=(np.array([5, 37], np.int64), np.array([1, 0], np.int32), np.array([10.0, 2.0])),
+        stencil=19),
 }
 
 

@@ -97,6 +97,78 @@ def test_fourier_mode_decay_factor(oracle, kinds):
     assert np.max(np.abs(out - g**n * mode)) < 1e-14
 
 
+# 19-point Laplacian of Eqs. (3)-(4).  Each 1D mode above satisfies
+# v(i-1) + v(i+1) = s v(i) with s = 2 + h^2 lambda, so a separable mode is an
+# eigenvector of the 19-point sum: centre -24, faces 2 s_d, edges s_d s_e.
+# For periodic modes s = 2 cos(theta) and the symbol is the paper's
+# (4 sum cos + 4 sum cos cos - 24) / (6 h^2).
+
+def spec19(D, dt, h, bc, ns=1):
+    return ModelSpec("diffusion", ns, dt, h, [[D, D, D]] * ns, bc, stencil=19)
+
+
+@pytest.mark.parametrize("kinds", [(MIRROR, MIRROR, MIRROR), (PERIODIC, PERIODIC, PERIODIC),
+                                   (GHOST, GHOST, GHOST), (PERIODIC, MIRROR, GHOST),
+                                   (GHOST, PERIODIC, MIRROR), (MIRROR, GHOST, PERIODIC)])
+def test_fourier_mode_decay_factor_19(oracle, kinds):
+    shape = (5, 6, 11)
+    nz, ny, nx = shape
+    h, D, dt, n = 1.3, 0.6, 0.2, 25
+    vx, lx = mode_1d(kinds[0], nx, 2, h)
+    vy, ly = mode_1d(kinds[1], ny, 1, h)
+    vz, lz = mode_1d(kinds[2], nz, 3, h)
+    sx, sy, sz = (2 + h * h * l for l in (lx, ly, lz))
+    mode = vz[:, None, None] * vy[None, :, None] * vx[None, None, :]
+    lam = (-24 + 2 * (sx + sy + sz) + (sx * sy + sx * sz + sy * sz)) / (6 * h * h)
+    g = 1 + dt * D * lam
+    out = oracle.run(spec19(D, dt, h, axis_bc(kinds)), [mode], n)[0]
+    assert np.max(np.abs(out - g**n * mode)) < 1e-14
+
+
+def test_periodic_symbol_19_is_the_papers():
+    """The closed form used above equals the paper's cosine symbol."""
+    th = np.linspace(0, np.pi, 7)
+    a, b, c = np.meshgrid(th, th, th, indexing="ij")
+    s = [2 * np.cos(t) for t in (a, b, c)]
+    ours = -24 + 2 * sum(s) + (s[0] * s[1] + s[0] * s[2] + s[1] * s[2])
+    papers = 4 * (np.cos(a) + np.cos(b) + np.cos(c)) + 4 * (
+        np.cos(a) * np.cos(b) + np.cos(a) * np.cos(c) + np.cos(b) * np.cos(c)) - 24
+    assert np.allclose(ours, papers, atol=1e-12)
+
+
+@pytest.mark.parametrize("h", [1.0, 2.0])
+def test_quadratic_field_exact_laplacian_19(oracle, h):
+    """The 19-point form is exact on quadratics, cross terms included (they
+    vanish), so one step adds dt * D * 2 (alpha + beta + gamma) / h^2."""
+    shape = (6, 7, 9)
+    k, j, i = grid_idx(shape)
+    al, be, ga = 3, -2, 5
+    c0 = (al * i**2 + be * j**2 + ga * k**2 + 2 * i * j - 3 * j * k + i * k
+          + 4 * i - 7 * j + 2 * k + 11).astype(float)
+    D, dt = 2.0, 0.125
+    bc = uniform_bc(1, MIRROR)
+    out = oracle.run(spec19(D, dt, h, bc), [c0], 1)[0]
+    expect = c0 + dt * D * 2.0 * (al + be + ga) / (h * h)
+    inner = (slice(1, -1),) * 3
+    assert np.array_equal(out[inner], expect[inner])
+
+
+def test_stencil19_mass_conserved(oracle):
+    """No-flux (mirror, edge ghosts included) and periodic faces conserve sum(c)."""
+    rng = np.random.default_rng(19)
+    shape = (7, 8, 9)
+    c0 = rng.uniform(0, 1, shape)
+    for kind in (MIRROR, PERIODIC):
+        out = oracle.run(spec19(1.0, 0.1, 1.0, uniform_bc(1, kind)), [c0], 20)[0]
+        assert abs(out.sum() - c0.sum()) <= 1e-12 * c0.sum()
+
+
+def test_stencil19_needs_isotropic_coefficients(oracle):
+    spec = ModelSpec("diffusion", 1, 0.1, 1.0, [[1.0, 1.0, 0.5]], uniform_bc(1, MIRROR), stencil=19)
+    with pytest.raises(Exception):
+        oracle.run(spec, [np.zeros((3, 3, 3))], 1)
+
+
 # ------------------------------------------------------------------ P3
 
 def dct_basis(n):
