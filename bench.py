@@ -37,6 +37,21 @@ def alg_bytes_per_cell(name: str, storage: str) -> int:
     return b
 
 
+def with_stencil(w, stencil: int):
+    """The workload on the 19-point Laplacian of Eqs. (3)-(4) when asked:
+    every species keeps its x coefficient on all three axes."""
+    if stencil == 7:
+        return w
+    w.spec.stencil = stencil
+    w.spec.K = [[k[0]] * 3 for k in w.spec.K]
+    w.name = w.name + "_19pt"
+    return w
+
+
+def profile_name(args) -> str:
+    return args.workload + ("_19pt" if getattr(args, "stencil", 7) == 19 else "")
+
+
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1004_0480_amd", "csrc")
@@ -169,7 +184,8 @@ def pmc_summary(args):
     spl = 2 if any("rdk::lds2_kernel" in k for k in knames) else 1
     alg = alg_bytes_per_cell(args.workload, args.storage) * cells
     rec = {"kernel": knames[0] if len(knames) == 1 else knames,
-           "workload": "%s %s, %s storage" % (args.workload, W.DEFAULT_SHAPES[args.workload], args.storage),
+           "workload": "%s %s, %s storage, %d-point Laplacian" % (args.workload, W.DEFAULT_SHAPES[args.workload],
+                                                                  args.storage, args.stencil),
            "source_digest": kernel_source_digest(), "command": args.pmc_command,
            "per_kernel": per_kernel, "steps_per_launch": spl,
            "calibration": "copy_kernel moving %d bytes each way in the same run" % COPY_PROBE_BYTES,
@@ -179,7 +195,7 @@ def pmc_summary(args):
            "hbm_bytes_per_step": (rd_b + wr_b) / spl,
            "algorithmic_bytes_per_launch_set": alg,
            "traffic_over_algorithmic": (rd_b + wr_b) / alg}
-    out = os.path.join(PROFILES, "%s_pmc.json" % args.workload)
+    out = os.path.join(PROFILES, "%s_pmc.json" % profile_name(args))
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -199,9 +215,9 @@ def trace_summary(args):
         rows = list(csv.DictReader(fh))
     cells = int(np.prod(W.DEFAULT_SHAPES[args.workload]))
     bpc = alg_bytes_per_cell(args.workload, args.storage)
-    lines = ["# rocprofv3 kernel trace: %s step kernel (MI355X)" % args.workload, "",
-             "Workload: %s, grid (z, y, x) = %s, %s storage." % (args.workload, W.DEFAULT_SHAPES[args.workload],
-                                                                 args.storage),
+    lines = ["# rocprofv3 kernel trace: %s step kernel (MI355X)" % profile_name(args), "",
+             "Workload: %s, grid (z, y, x) = %s, %s storage, %d-point Laplacian."
+             % (args.workload, W.DEFAULT_SHAPES[args.workload], args.storage, args.stencil),
              "", "Command:", "", "```", args.trace_command, "```", "",
              "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
     step = None
@@ -220,7 +236,7 @@ def trace_summary(args):
                   % (step[0][:80], bpc, cells, bpc * cells / 1e6),
                   "average %.2f us that is %.0f GB/s, %.1f%% of the 8 TB/s HBM peak."
                   % (step[1], gbs, 100.0 * gbs / HBM_PEAK_GBS)]
-    out = os.path.join(PROFILES, "%s_kernel_trace.md" % args.workload)
+    out = os.path.join(PROFILES, "%s_kernel_trace.md" % profile_name(args))
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -273,6 +289,8 @@ def main():
                     choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64",
                              "serve"])
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16", "both"])
+    ap.add_argument("--stencil", type=int, default=7, choices=[7, 19],
+                    help="Laplacian: 7-point, or the 19-point form of Eqs. (3)-(4) (x coefficient on every axis)")
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--max-resident", type=int, default=256)
     ap.add_argument("--hbm-budget", type=int, default=16 << 30)
@@ -307,10 +325,10 @@ def main():
     from paper_1004_0480_amd import rd
     from paper_1004_0480_amd import workloads as W
 
-    w = W.make_workload(args.workload)
+    w = with_stencil(W.make_workload(args.workload), args.stencil)
     stream = torch.cuda.Stream()
-    print("bench: %s %s storage=%s steps=%d warmup=%d" % (w.name, w.shape, args.storage,
-                                                          args.steps, args.warmup),
+    print("bench: %s %s storage=%s stencil=%d steps=%d warmup=%d" % (w.name, w.shape, args.storage, args.stencil,
+                                                                     args.steps, args.warmup),
           file=sys.stderr, flush=True)
     g = rd.Grid.from_workload(w, storage=args.storage, stream=stream)
     if args.plan:
@@ -344,7 +362,7 @@ def main():
     for s in range(w.spec.ns):
         g.reduce(s)
 
-    bpc = alg_bytes_per_cell(w.name, args.storage)
+    bpc = alg_bytes_per_cell(args.workload, args.storage)
     passes = g.passes()
     steps_per_launch = 2 if plan.get("kernel") == 5 else 1     # two-step (temporally blocked) plan
     # dominant kernel: the step kernel.  A launch reads and writes every field
@@ -354,7 +372,7 @@ def main():
     launch_ms = ms_per_step * steps_per_launch
     achieved = bpc * w.cells / (launch_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
-    pmc = measured_traffic(w.name, digest)
+    pmc = measured_traffic(profile_name(args), digest)
     traffic = None
     if pmc is not None and pmc.get("steps_per_launch", 1) == steps_per_launch:
         traffic = pmc.get("hbm_bytes_per_launch") if passes == 1 else pmc.get("hbm_bytes_per_step")
@@ -372,7 +390,7 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
-                   "species": w.spec.ns, "storage": args.storage, "dt": w.spec.dt,
+                   "species": w.spec.ns, "storage": args.storage, "stencil": args.stencil, "dt": w.spec.dt,
                    "plan": plan, "wall_s": wall},
         "roofline": roof,
     }

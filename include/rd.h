@@ -98,9 +98,18 @@ enum { RD_FACE_XLO = 0, RD_FACE_XHI, RD_FACE_YLO, RD_FACE_YHI, RD_FACE_ZLO, RD_F
  * src_*        POLLUTANT: nsrc point sources, host arrays read during the
  *              call: linear cell index (k*ny + j)*nx + i, species, rate
  *              (added to dc/dt; duplicates add up).
+ * stencil      7 (or 0): the 7-point Laplacian with per-axis coefficients;
+ *              19: the 19-point Laplacian of Eqs. (3)-(4), weights -24 (centre),
+ *              2 (faces), 1 (edges) over 6h^2, for isotropic diff[s][0..2]
+ *              only (RD_EINVAL otherwise).  An edge neighbour outside two
+ *              faces takes the rule of the first of them in x, y, z order.
+ *              19-point grids run on the direct and LDS-ring plans and are
+ *              not batched.
  * dt           time step; rd_set_model rejects a dt outside the stable range
- *              (RD_EUNSTABLE): per species dt*(2*sum_d K_d/h^2 + max u/h) <= 1,
- *              and for FRONT_CH also dt*M*(kappa*(12/h^2)^2 + |eps|*12/h^2) <= 1.
+ *              (RD_EUNSTABLE): per species dt*(2*sum_d K_d/h^2 + max u/h) <= 1
+ *              (19-point: dt*(4 D/h^2 + max u/h) <= 1), and for FRONT_CH also
+ *              dt*M*(kappa*L^2 + |eps|*L) <= 1 with L = 12/h^2 (19-point:
+ *              16/(3h^2)), the largest magnitude of the discrete Laplacian.
  */
 typedef struct rd_model_desc {
     int32_t model;
@@ -116,6 +125,7 @@ typedef struct rd_model_desc {
     const int64_t *src_cell;
     const int32_t *src_species;
     const double *src_rate;
+    int32_t stencil;
 } rd_model_desc;
 
 /* kernel plan of a grid (all plans give bitwise-identical fields) */

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace rdk {
 
 enum { BC_MIRROR = 0, BC_PERIODIC = 1, BC_GHOST = 2, BC_HELD = 3 };
@@ -45,6 +47,7 @@ struct StepArgs {
     const int* src_sp;            // species of each source
     const float* src_rate;        // emission rate (duplicates merged)
     int sp0;                      // species of field 0 (source species are global)
+    int s19;                      // 19-point Laplacian: kx = ky = kz = K/(6h^2)
     int tiles_x, tiles_y, chunks_z, cz;   // tiled decomposition
     int zfast;                    // slab enumeration: z chunk fastest
 };
@@ -110,8 +113,10 @@ struct StF64 {
 // compiler only parses this code; it gets no address space.)
 #ifdef __HIP_DEVICE_COMPILE__
 #define RD_GLOBAL __attribute__((address_space(1)))
+#define RD_LDS __attribute__((address_space(3)))
 #else
 #define RD_GLOBAL
+#define RD_LDS
 #endif
 template <typename T>
 __device__ __forceinline__ const RD_GLOBAL T* gload_ptr(const void* p) {
@@ -120,6 +125,19 @@ __device__ __forceinline__ const RD_GLOBAL T* gload_ptr(const void* p) {
 template <typename T>
 __device__ __forceinline__ RD_GLOBAL T* gstore_ptr(void* p) {
     return (RD_GLOBAL T*)p;
+}
+
+// The LDS-ring kernels address their rings through LDS pointers taken from
+// the __shared__ arrays themselves, never through generic pointers.
+typedef float lds_v4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void lds_ld4(const RD_LDS float* p, float (&o)[4]) {
+    const lds_v4 t = *(const RD_LDS lds_v4*)p;
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+}
+__device__ __forceinline__ void lds_st4(RD_LDS float* p, float x, float y, float z, float w) {
+    lds_v4 t;
+    t.x = x; t.y = y; t.z = z; t.w = w;
+    *(RD_LDS lds_v4*)p = t;
 }
 
 // N contiguous elements of type T as one naturally aligned access.
@@ -176,17 +194,42 @@ __device__ __forceinline__ float lap7(const Nb& n, float kx, float ky, float kz)
     return __fmaf_rn(kx, dx, __fmaf_rn(ky, dy, kz * dz));
 }
 
+// The 19 points of Eqs. (3)-(4): the 7 above plus the twelve edge
+// neighbours, carried as three partial sums that both kernel families form
+// in the same order:
+//   s   = (c[y-1] + c[y+1]) + (c[z-1] + c[z+1])            (the centre's cross)
+//   sxm = the same cross sum one cell to the left (the four x- edges),
+//   sxp = the same one cell to the right (the four x+ edges),
+//   q   = (c[y-1,z-1] + c[y+1,z-1]) + (c[y-1,z+1] + c[y+1,z+1]).
+// Beyond an x face every term of a cross sum follows the face rule of x, so
+// sxm / sxp there are the cross sum at the mirrored or wrapped cell, or four
+// times the face value.
+struct Nb19 : Nb { float s, sxm, sxp, q; };
+
+// K/(6h^2) * (-24 c + 2 * faces + edges), K/(6h^2) given (isotropic)
+__device__ __forceinline__ float lap19(const Nb19& n, float k6) {
+    const float faces = (n.xm + n.xp) + n.s;
+    const float edges = (n.sxm + n.sxp) + n.q;
+    return k6 * __fmaf_rn(-24.f, n.c, __fmaf_rn(2.f, faces, edges));
+}
+
+// The Laplacian of a neighbourhood: 7-point (per-axis K/h^2) or 19-point
+// (all three coefficients hold K/(6h^2)).
+__device__ __forceinline__ float lap(const Nb& n, float kx, float ky, float kz) { return lap7(n, kx, ky, kz); }
+__device__ __forceinline__ float lap(const Nb19& n, float kx, float, float) { return lap19(n, kx); }
+
 // Pure diffusion of NS independent species (Table 1, first row).
 template <int NS> struct Diffusion {
     static constexpr int NF = NS, NO = NS;
     static constexpr bool SOURCES = false;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[NF], float,
+    template <class NB>
+    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[NF], float,
                                                 bool, const float (&)[NO], float (&o)[NO]) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            o[s] = __fmaf_rn(a.dt, lap7(n[s], a.kx[s], a.ky[s], a.kz[s]), n[s].c);
+            o[s] = __fmaf_rn(a.dt, lap(n[s], a.kx[s], a.ky[s], a.kz[s]), n[s].c);
     }
 };
 
@@ -196,14 +239,15 @@ struct Brusselator {
     static constexpr bool SOURCES = false;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[2], float,
+    template <class NB>
+    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[2], float,
                                                 bool, const float (&)[2], float (&o)[2]) {
         const float u = n[0].c, v = n[1].c;
         const float uuv = (u * u) * v;
         const float ru = __fmaf_rn(a.p[2], u, a.p[0] + uuv);   // a - (b+1) u + u^2 v
         const float rv = __fmaf_rn(a.p[1], u, -uuv);            // b u - u^2 v
-        const float lu = lap7(n[0], a.kx[0], a.ky[0], a.kz[0]);
-        const float lv = lap7(n[1], a.kx[1], a.ky[1], a.kz[1]);
+        const float lu = lap(n[0], a.kx[0], a.ky[0], a.kz[0]);
+        const float lv = lap(n[1], a.kx[1], a.ky[1], a.kz[1]);
         o[0] = __fmaf_rn(a.dt, lu + ru, u);
         o[1] = __fmaf_rn(a.dt, lv + rv, v);
     }
@@ -217,11 +261,12 @@ struct ChemPotential {
     static constexpr bool SOURCES = false;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return true; }
-    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[1], float,
+    template <class NB>
+    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[1], float,
                                                 bool, const float (&)[1], float (&o)[1]) {
         const float c = n[0].c;
-        const float lap = lap7(n[0], a.kx[0], a.ky[0], a.kz[0]);
-        o[0] = __fmaf_rn(-a.p[2], lap, __fmaf_rn(a.p[4] * c, c * c, -(a.p[3] * c)));
+        const float lc = lap(n[0], a.kx[0], a.ky[0], a.kz[0]);
+        o[0] = __fmaf_rn(-a.p[2], lc, __fmaf_rn(a.p[4] * c, c * c, -(a.p[3] * c)));
     }
 };
 
@@ -233,14 +278,15 @@ struct FrontCH {
     static constexpr bool SOURCES = false;
     static __host__ __device__ constexpr bool f32_field(int f) { return f == 3; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[4], float,
+    template <class NB>
+    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[4], float,
                                                 bool, const float (&)[3], float (&o)[3]) {
         const float A = n[0].c, B = n[1].c, C = n[2].c;
         const float r = (a.p[0] * A) * B;
-        const float la = lap7(n[0], a.kx[0], a.ky[0], a.kz[0]);
-        const float lb = lap7(n[1], a.kx[1], a.ky[1], a.kz[1]);
-        const float lc = lap7(n[2], a.kx[2], a.ky[2], a.kz[2]);
-        const float lmu = lap7(n[3], a.kx[3], a.ky[3], a.kz[3]);
+        const float la = lap(n[0], a.kx[0], a.ky[0], a.kz[0]);
+        const float lb = lap(n[1], a.kx[1], a.ky[1], a.kz[1]);
+        const float lc = lap(n[2], a.kx[2], a.ky[2], a.kz[2]);
+        const float lmu = lap(n[3], a.kx[3], a.ky[3], a.kz[3]);
         o[0] = __fmaf_rn(a.dt, la - r, A);
         o[1] = __fmaf_rn(a.dt, lb - r, B);
         o[2] = __fmaf_rn(a.dt, __fmaf_rn(a.p[1], lmu, lc + r), C);
@@ -256,13 +302,14 @@ template <int NS, bool COUPLED> struct Pollutant {
     static constexpr bool SOURCES = true;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    static __device__ __forceinline__ void cell(const StepArgs& a, const Nb (&n)[NF], float uh,
+    template <class NB>
+    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[NF], float uh,
                                                 bool has_e, const float (&e)[NO], float (&o)[NO]) {
         const float c0 = n[0].c;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const float c = n[s].c;
-            float rate = lap7(n[s], a.kx[s], a.ky[s], a.kz[s]);
+            float rate = lap(n[s], a.kx[s], a.ky[s], a.kz[s]);
             rate = __fmaf_rn(uh, n[s].xm - c, rate);       // -u (c_i - c_{i-1}) / h
             rate = __fmaf_rn(-a.p[0], c, rate);             // decay
             if (COUPLED && NS >= 2 && s == 0) rate = __fmaf_rn(-a.p[1], c0, rate);
@@ -312,8 +359,8 @@ __device__ __forceinline__ float fixed_or(const Src& sx, const Src& sy, const Sr
 // neighbour does not move along), one load is made from every resolved
 // (always valid) address, and a value fixed by a rule replaces it.  Written
 // as value selects so that no address depends on the rules.
-template <class S>
-__device__ __forceinline__ Nb stencil(const StepArgs& a, int f, int x, int y, int z) {
+template <class S, bool S19>
+__device__ __forceinline__ std::conditional_t<S19, Nb19, Nb> stencil(const StepArgs& a, int f, int x, int y, int z) {
     const int* k = a.bck[f];
     const float* v = a.bcv[f];
     const Src sx = resolve_axis(x, a.nx, k[0], k[1], v[0], v[1]);
@@ -325,11 +372,13 @@ __device__ __forceinline__ Nb stencil(const StepArgs& a, int f, int x, int y, in
     const Src yp = resolve_axis(y + 1, a.ny, k[2], k[3], v[2], v[3]);
     const Src zm = resolve_axis(z - 1, a.nz, k[4], k[5], v[4], v[5]);
     const Src zp = resolve_axis(z + 1, a.nz, k[4], k[5], v[4], v[5]);
-    auto at = [&](const Src& qx, const Src& qy, const Src& qz) {
+    // an edge neighbour leaves along two axes: fixed_or takes the ghost of
+    // the first of them (x, y, z), a mirror or periodic axis its resolved index
+    auto at = [&](const Src& qx, const Src& qy, const Src& qz) __attribute__((always_inline)) {
         const float u = load1<S>(a.in[f], (long long)qz.idx * a.plane + (long long)qy.idx * a.pitch + qx.idx);
         return fixed_or(qx, qy, qz, u);
     };
-    Nb n;
+    std::conditional_t<S19, Nb19, Nb> n;
     n.c = at(sx, sy, sz);
     n.xm = at(xm, sy, sz);
     n.xp = at(xp, sy, sz);
@@ -337,6 +386,12 @@ __device__ __forceinline__ Nb stencil(const StepArgs& a, int f, int x, int y, in
     n.yp = at(sx, yp, sz);
     n.zm = at(sx, sy, zm);
     n.zp = at(sx, sy, zp);
+    if constexpr (S19) {
+        n.s = (n.ym + n.yp) + (n.zm + n.zp);
+        n.sxm = (at(xm, ym, sz) + at(xm, yp, sz)) + (at(xm, sy, zm) + at(xm, sy, zp));
+        n.sxp = (at(xp, ym, sz) + at(xp, yp, sz)) + (at(xp, sy, zm) + at(xp, sy, zp));
+        n.q = (at(sx, ym, zm) + at(sx, yp, zm)) + (at(sx, ym, zp) + at(sx, yp, zp));
+    }
     return n;
 }
 
@@ -383,19 +438,20 @@ __device__ __forceinline__ float held_out(const StepArgs& a, int s, int x, int y
 }
 
 // ------------------------------------------------------------ direct kernel
-// One thread per cell; all 7 stencil points come through the cache.  The
+// One thread per cell; all 7 (or 19) stencil points come through the cache.  The
 // simple baseline the tiled plans are checked against bit for bit.
 
-template <class M, class S>
+template <class M, class S, bool S19>
 __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict__ pa) {
     const StepArgs& a = *pa;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int z = blockIdx.z;
     if (x >= a.nx || y >= a.ny) return;
-    Nb n[M::NF];
+    std::conditional_t<S19, Nb19, Nb> n[M::NF];
 #pragma unroll
-    for (int f = 0; f < M::NF; ++f) n[f] = M::f32_field(f) ? stencil<StF32>(a, f, x, y, z) : stencil<S>(a, f, x, y, z);
+    for (int f = 0; f < M::NF; ++f)
+        n[f] = M::f32_field(f) ? stencil<StF32, S19>(a, f, x, y, z) : stencil<S, S19>(a, f, x, y, z);
     Emission<M::NO> em{};
     if (M::SOURCES) {
         const int r = z * a.ny + y;
@@ -1007,7 +1063,7 @@ __device__ __forceinline__ void march_tile(const StepArgs& a, BlockLds<M, W, 64 
     float E[NB][NF][RY];
 
     // request plane p (halo rows and x edges only for planes this tile computes)
-    auto issue = [&](float (&v)[NF][RY][VX], float (&hv)[NF][NH][VX], float (&e)[NF][RY], int p) {
+    auto issue = [&](float (&v)[NF][RY][VX], float (&hv)[NF][NH][VX], float (&e)[NF][RY], int p) __attribute__((always_inline)) {
         const bool extras = p >= z0 && p < z1;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -1034,7 +1090,7 @@ __device__ __forceinline__ void march_tile(const StepArgs& a, BlockLds<M, W, 64 
         }
     };
     // replace loaded values of plane p where a boundary rule fixes them
-    auto finish = [&](float (&v)[NF][RY][VX], float (&hv)[NF][NH][VX], float (&e)[NF][RY], int p) {
+    auto finish = [&](float (&v)[NF][RY][VX], float (&hv)[NF][NH][VX], float (&e)[NF][RY], int p) __attribute__((always_inline)) {
         bool any = rows_fix;
         if (p <= 0 || p >= a.nz - 1) {
 #pragma unroll
@@ -1199,8 +1255,7 @@ struct LdsRing {
 };
 
 template <class M, int NCH, int BY, int WC, int D>
-__device__ __forceinline__ void lds_producer(const StepArgs& a, float (*ring)[LdsRing<M::NF, NCH, BY, D>::SLOT],
-                                             int yb, int z0, int z1) {
+__device__ __forceinline__ void lds_producer(const StepArgs& a, RD_LDS float* ring, int yb, int z0, int z1) {
     using R = LdsRing<M::NF, NCH, BY, D>;
     constexpr int NF = M::NF, ROWS = R::ROWS, TXT = R::TXT;
     const int lane = threadIdx.x & 63;
@@ -1211,7 +1266,7 @@ __device__ __forceinline__ void lds_producer(const StepArgs& a, float (*ring)[Ld
 #pragma unroll
         for (int j = 0; j < ROWS; ++j)
             ridx[f][j] = resolve_axis(yb - 1 + j, a.ny, a.bck[f][2], a.bck[f][3], a.bcv[f][2], a.bcv[f][3]).idx;
-    auto issue = [&](float* slot, int p) {
+    auto issue = [&](RD_LDS float* slot, int p) __attribute__((always_inline)) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int pz = resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]).idx;
@@ -1221,14 +1276,13 @@ __device__ __forceinline__ void lds_producer(const StepArgs& a, float (*ring)[Ld
 #pragma unroll
                 for (int c = 0; c < NCH; ++c)
                     __builtin_amdgcn_global_load_lds(base + (long long)ridx[f][j] * a.pitch + c * 256,
-                                                     (__attribute__((address_space(3))) void*)(slot + (f * ROWS + j) * TXT + c * 256),
-                                                     16, 0, 0);
+                                                     (RD_LDS void*)(slot + (f * ROWS + j) * TXT + c * 256), 16, 0, 0);
         }
     };
     // planes z0-1 .. z0+D-3 into slots 0 .. D-2; plane p lives in slot (p - z0 + 1) % D
 #pragma unroll
     for (int k = 0; k < D - 1; ++k)
-        if (z0 - 1 + k <= z1) issue(ring[k], z0 - 1 + k);
+        if (z0 - 1 + k <= z1) issue(ring + k * R::SLOT, z0 - 1 + k);
     for (int zb = z0; zb < z1; zb += D) {
 #pragma unroll
         for (int J = 0; J < D; ++J) {
@@ -1238,17 +1292,18 @@ __device__ __forceinline__ void lds_producer(const StepArgs& a, float (*ring)[Ld
                 vm_wait_steps<R::CH, D - 4>(min(D - 4, z1 - z - 1));
                 ring_barrier();
                 // every consumer is past plane z-1, so the slot of plane z-2 is free
-                if (z + D - 2 <= z1) issue(ring[(J + D - 1) % D], z + D - 2);
+                if (z + D - 2 <= z1) issue(ring + ((J + D - 1) % D) * R::SLOT, z + D - 2);
             }
         }
     }
 }
 
-template <class M, int NCH, int BY, int WC, int D>
-__device__ __forceinline__ void lds_consumer(const StepArgs& a, const float (*ring)[LdsRing<M::NF, NCH, BY, D>::SLOT],
-                                             int cw, int yb, int z0, int z1) {
+template <class M, int NCH, int BY, int WC, int D, bool S19>
+__device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS float* ring, int cw, int yb, int z0,
+                                             int z1) {
     using R = LdsRing<M::NF, NCH, BY, D>;
     constexpr int NF = M::NF, NO = M::NO, TXT = R::TXT, RY = BY / WC;
+    using NBT = std::conditional_t<S19, Nb19, Nb>;
     const int lane = threadIdx.x & 63;
     const int r0 = cw * RY;                   // first tile row of this wave
     // rows r0-1 .. r0+RY of the tile (LDS rows r0 .. r0+RY+1), for fix-ups
@@ -1263,8 +1318,21 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const float (*ri
         }
         rows_fix = rows_fix || (a.held[f] & 3) != 0;
     }
+    // x sides of a whole row: rotate (periodic), own edge value (mirror) or
+    // the face value, held in registers across the plane loop
     int xsl[NF], xsr[NF];
     (void)x_sides<M, true>(a, 0, TXT, true, xsl, xsr);
+    bool rot_l[NF], own_l[NF], rot_r[NF], own_r[NF];
+    float fill_l[NF], fill_r[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        rot_l[f] = xsl[f] == XS_ROT;
+        own_l[f] = xsl[f] == XS_OWN;
+        rot_r[f] = xsr[f] == XS_ROT;
+        own_r[f] = xsr[f] == XS_OWN;
+        fill_l[f] = a.bcv[f][0];
+        fill_r[f] = a.bcv[f][1];
+    }
     bool xy_held = false, held_lo = false, held_hi = false;
 #pragma unroll
     for (int s = 0; s < NO; ++s) {
@@ -1274,11 +1342,46 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const float (*ri
         held_hi = held_hi || (hm & 32);
     }
 
-    for (int zb = z0; zb < z1; zb += D) {
+    // Rows r0-1 .. r0+RY of planes z-1, z, z+1 (LDS rows r0 .. r0+RY+1), with
+    // the face rules applied.  Plane z of one step is plane z-1 of the next,
+    // with the same rules, so each step reads plane z+1 alone from the ring;
+    // the plane loop is unrolled three times so that the three register
+    // planes trade roles without copies.  The first plane z0-1 needs only the
+    // wave's own rows for the 7-point form (halo = false).
+    using Plane = float[NF][RY + 2][NCH][4];
+    Plane PA, PB, PC;
+    auto load_plane = [&](const RD_LDS float* S, Plane& v, bool halo) __attribute__((always_inline)) {
 #pragma unroll
-        for (int J = 0; J < D; ++J) {
-            const int z = zb + J;
-            if (z < z1) {
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int r = 0; r < RY + 2; ++r)
+                    if (halo || (r > 0 && r <= RY))
+                        lds_ld4(S + (f * R::ROWS + r0 + r) * TXT + c * 256 + lane * 4, v[f][r][c]);
+    };
+    // boundary rules that replace loaded values (fixed or held rows, the
+    // planes at and beyond the z faces, x faces)
+    auto fix_plane = [&](int p, Plane& v, bool halo) __attribute__((always_inline)) {
+        if (rows_fix || p <= 0 || p >= a.nz - 1) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const Src ps = resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int r = 0; r < RY + 2; ++r)
+                        if (halo || (r > 0 && r <= RY))
+                            fix_row<4>(a, f, ps, rs[f][r], c * 256 + lane * 4, v[f][r][c]);
+            }
+        }
+    };
+
+    int sp_slot = 2;                 // slot of plane z+1 (plane z0-1 is slot 0)
+    // one plane: vm, v0 hold planes z-1, z; plane z+1 is read into vp
+    auto plane = [&](int z, Plane& vm, Plane& v0, Plane& vp, bool first) __attribute__((always_inline)) {
+        {
+            {
                 // scalar loads of this plane's wind and source range go out
                 // before the barrier so their latency hides behind it
                 const float uh = M::SOURCES ? gload_ptr<float>(a.wind_h)[z] : 0.f;
@@ -1289,88 +1392,67 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const float (*ri
                     plane_src = pa0 < pa1;
                 }
                 ring_barrier();
-                const float* Sm = ring[J % D];
-                const float* S0 = ring[(J + 1) % D];
-                const float* Sp = ring[(J + 2) % D];
-                // rows r0-1 .. r0+RY of plane z, rows r0 .. r0+RY-1 of planes z-1 and z+1
-                float v0[NF][RY + 2][NCH][4], vm[NF][RY][NCH][4], vp[NF][RY][NCH][4];
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
-#pragma unroll
-                        for (int r = 0; r < RY + 2; ++r) {
-                            const float4 q = *reinterpret_cast<const float4*>(S0 + (f * R::ROWS + r0 + r) * TXT + c * 256 + lane * 4);
-                            v0[f][r][c][0] = q.x; v0[f][r][c][1] = q.y; v0[f][r][c][2] = q.z; v0[f][r][c][3] = q.w;
-                        }
-#pragma unroll
-                        for (int r = 0; r < RY; ++r) {
-                            const float4 qm = *reinterpret_cast<const float4*>(Sm + (f * R::ROWS + r0 + 1 + r) * TXT + c * 256 + lane * 4);
-                            const float4 qp = *reinterpret_cast<const float4*>(Sp + (f * R::ROWS + r0 + 1 + r) * TXT + c * 256 + lane * 4);
-                            vm[f][r][c][0] = qm.x; vm[f][r][c][1] = qm.y; vm[f][r][c][2] = qm.z; vm[f][r][c][3] = qm.w;
-                            vp[f][r][c][0] = qp.x; vp[f][r][c][1] = qp.y; vp[f][r][c][2] = qp.z; vp[f][r][c][3] = qp.w;
-                        }
-                    }
-                // boundary rules that replace loaded values (fixed or held rows,
-                // planes and x faces)
-                const bool near_face = z - 1 <= 0 || z + 1 >= a.nz - 1;
-                if (rows_fix || near_face) {
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        const Src pm = resolve_axis(z - 1, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
-                        const Src p0 = resolve_axis(z, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
-                        const Src pp = resolve_axis(z + 1, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]);
-#pragma unroll
-                        for (int c = 0; c < NCH; ++c) {
-                            const int xl = c * 256 + lane * 4;
-#pragma unroll
-                            for (int r = 0; r < RY + 2; ++r) fix_row<4>(a, f, p0, rs[f][r], xl, v0[f][r][c]);
-#pragma unroll
-                            for (int r = 0; r < RY; ++r) {
-                                fix_row<4>(a, f, pm, rs[f][r + 1], xl, vm[f][r][c]);
-                                fix_row<4>(a, f, pp, rs[f][r + 1], xl, vp[f][r][c]);
-                            }
-                        }
-                    }
+                if (first) {
+                    load_plane(ring, vm, S19);
+                    load_plane(ring + R::SLOT, v0, true);
+                    fix_plane(z - 1, vm, S19);
+                    fix_plane(z, v0, true);
                 }
+                load_plane(ring + sp_slot * R::SLOT, vp, true);
+                sp_slot = sp_slot + 1 == D ? 0 : sp_slot + 1;
+                fix_plane(z + 1, vp, true);
                 const bool held = xy_held || (held_lo && z == 0) || (held_hi && z == a.nz - 1);
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
                     const int y = yb + r0 + r;
-                    Nb n[NF][NCH][4];
+                    NBT n[NF][NCH][4];
+                    // x neighbours of a row across lanes, chunks and the x
+                    // faces; `k` scales the face value (a cross sum of four)
+                    auto xnb = [&](int f, const float (&row)[NCH][4], int c, float k, float& left, float& right)
+                                   __attribute__((always_inline)) {
+                        const float fl = c > 0 ? lane_from_left_wrap(row[c - 1][3])
+                                         : rot_l[f] ? lane_from_left_wrap(row[NCH - 1][3])
+                                         : own_l[f] ? row[0][0] : k * fill_l[f];
+                        const float fr = c < NCH - 1 ? lane_from_right_wrap(row[c + 1][0])
+                                         : rot_r[f] ? lane_from_right_wrap(row[0][0])
+                                         : own_r[f] ? row[NCH - 1][3] : k * fill_r[f];
+                        left = lane_from_left(row[c][3], fl);
+                        right = lane_from_right(row[c][0], fr);
+                    };
 #pragma unroll
                     for (int f = 0; f < NF; ++f) {
+                        // 19 points: the cross sums of this row and their x neighbours
+                        float sc[NCH][4];
+                        if constexpr (S19) {
+#pragma unroll
+                            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                                for (int i = 0; i < 4; ++i)
+                                    sc[c][i] = (v0[f][r][c][i] + v0[f][r + 2][c][i]) + (vm[f][r + 1][c][i] + vp[f][r + 1][c][i]);
+                        }
 #pragma unroll
                         for (int c = 0; c < NCH; ++c) {
                             const float (&v)[4] = v0[f][r + 1][c];
-                            // x neighbours across lanes, chunks and the x faces
-                            float fl, fr;
-                            if (c > 0) {
-                                fl = lane_from_left_wrap(v0[f][r + 1][c - 1][3]);
-                            } else if (xsl[f] == XS_ROT) {
-                                fl = lane_from_left_wrap(v0[f][r + 1][NCH - 1][3]);
-                            } else {
-                                fl = xsl[f] == XS_OWN ? v[0] : a.bcv[f][0];
-                            }
-                            if (c < NCH - 1) {
-                                fr = lane_from_right_wrap(v0[f][r + 1][c + 1][0]);
-                            } else if (xsr[f] == XS_ROT) {
-                                fr = lane_from_right_wrap(v0[f][r + 1][0][0]);
-                            } else {
-                                fr = xsr[f] == XS_OWN ? v[3] : a.bcv[f][1];
-                            }
-                            const float left = lane_from_left(v[3], fl);
-                            const float right = lane_from_right(v[0], fr);
+                            float left, right;
+                            xnb(f, v0[f][r + 1], c, 1.f, left, right);
+                            float sl = 0.f, sr = 0.f;
+                            if constexpr (S19) xnb(f, sc, c, 4.f, sl, sr);
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
-                                Nb& q = n[f][c][i];
+                                NBT& q = n[f][c][i];
                                 q.c = v[i];
                                 q.xm = i > 0 ? v[i - 1] : left;
                                 q.xp = i < 3 ? v[i + 1] : right;
                                 q.ym = v0[f][r][c][i];
                                 q.yp = v0[f][r + 2][c][i];
-                                q.zm = vm[f][r][c][i];
-                                q.zp = vp[f][r][c][i];
+                                q.zm = vm[f][r + 1][c][i];
+                                q.zp = vp[f][r + 1][c][i];
+                                if constexpr (S19) {
+                                    q.s = sc[c][i];
+                                    q.sxm = i > 0 ? sc[c][i - 1] : sl;
+                                    q.sxp = i < 3 ? sc[c][i + 1] : sr;
+                                    q.q = (vm[f][r][c][i] + vm[f][r + 2][c][i]) + (vp[f][r][c][i] + vp[f][r + 2][c][i]);
+                                }
                             }
                         }
                     }
@@ -1385,7 +1467,7 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const float (*ri
                         float o[NO][4];
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            Nb ni[NF];
+                            NBT ni[NF];
 #pragma unroll
                             for (int f = 0; f < NF; ++f) ni[f] = n[f][c][i];
                             Emission<NO> em{};
@@ -1404,10 +1486,17 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const float (*ri
                 }
             }
         }
+    };
+    for (int z = z0; z < z1; z += 3) {
+        plane(z, PA, PB, PC, z == z0);
+        if (z + 1 >= z1) break;
+        plane(z + 1, PB, PC, PA, false);
+        if (z + 2 >= z1) break;
+        plane(z + 2, PC, PA, PB, false);
     }
 }
 
-template <class M, int NCH, int BY, int WC, int D>
+template <class M, int NCH, int BY, int WC, int D, bool S19>
 __global__ __launch_bounds__(64 * (WC + 1)) void lds_kernel(const StepArgs* __restrict__ pa) {
     using R = LdsRing<M::NF, NCH, BY, D>;
     static_assert(R::FITS && BY % WC == 0, "ring shape does not fit");
@@ -1418,8 +1507,9 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds_kernel(const StepArgs* __re
     const int yb = tc.y * BY;
     const int z0 = tc.z * a.cz;
     const int z1 = min(z0 + a.cz, a.nz);
-    if (w == 0) lds_producer<M, NCH, BY, WC, D>(a, ring, yb, z0, z1);
-    else lds_consumer<M, NCH, BY, WC, D>(a, ring, w - 1, yb, z0, z1);
+    RD_LDS float* base = (RD_LDS float*)&ring[0][0];
+    if (w == 0) lds_producer<M, NCH, BY, WC, D>(a, base, yb, z0, z1);
+    else lds_consumer<M, NCH, BY, WC, D, S19>(a, base, w - 1, yb, z0, z1);
 }
 
 // ---- two steps per launch (temporal blocking) on the LDS ring ---------------
@@ -1460,7 +1550,7 @@ __device__ __forceinline__ void lds_done() {
 }
 
 template <class M, int NCH, int BY, int WC, int D>
-__device__ __forceinline__ void lds2_producer(const StepArgs& a, float* iring, int yb, int z0, int z1) {
+__device__ __forceinline__ void lds2_producer(const StepArgs& a, RD_LDS float* iring, int yb, int z0, int z1) {
     using R = Lds2Ring<M::NF, NCH, BY, D>;
     constexpr int NF = M::NF, IROWS = R::IROWS, TXT = R::TXT;
     const int lane = threadIdx.x & 63;
@@ -1470,8 +1560,8 @@ __device__ __forceinline__ void lds2_producer(const StepArgs& a, float* iring, i
 #pragma unroll
         for (int j = 0; j < IROWS; ++j)
             ridx[f][j] = wrap_or_clamp(yb - 2 + j, a.ny, a.bck[f][2] == BC_PERIODIC);
-    auto issue = [&](int slot, int p) {
-        float* base_l = iring + slot * R::ISLOT;
+    auto issue = [&](int slot, int p) __attribute__((always_inline)) {
+        RD_LDS float* base_l = iring + slot * R::ISLOT;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int pz = wrap_or_clamp(p, a.nz, a.bck[f][4] == BC_PERIODIC);
@@ -1482,7 +1572,7 @@ __device__ __forceinline__ void lds2_producer(const StepArgs& a, float* iring, i
                 for (int c = 0; c < NCH; ++c)
                     __builtin_amdgcn_global_load_lds(
                         base + (long long)ridx[f][j] * a.pitch + c * 256,
-                        (__attribute__((address_space(3))) void*)(base_l + (f * IROWS + j) * TXT + c * 256), 16, 0, 0);
+                        (RD_LDS void*)(base_l + (f * IROWS + j) * TXT + c * 256), 16, 0, 0);
         }
     };
     // input planes z0-2 .. z1+1; plane p lives in slot (p - z0 + 2) % D
@@ -1510,8 +1600,8 @@ __device__ __forceinline__ MidSrc mid_src(int q, int n, int base, int klo, int k
 }
 
 template <class M, int NCH, int BY, int WC, int D>
-__device__ __forceinline__ void lds2_consumer(const StepArgs& a, const float* iring, float* mring, int cw, int yb,
-                                              int z0, int z1) {
+__device__ __forceinline__ void lds2_consumer(const StepArgs& a, const RD_LDS float* iring, RD_LDS float* mring, int cw,
+                                              int yb, int z0, int z1) {
     static_assert(!M::SOURCES && M::NO == M::NF, "point sources and extra fields are not blocked");
     using R = Lds2Ring<M::NF, NCH, BY, D>;
     constexpr int NF = M::NF, NO = M::NO, TXT = R::TXT, IROWS = R::IROWS, MROWS = R::MROWS;
@@ -1529,7 +1619,7 @@ __device__ __forceinline__ void lds2_consumer(const StepArgs& a, const float* ir
     in_fix = in_fix || any_held;
 
     // x neighbours of lane values v (chunks of 4 per lane) by the x face rules
-    auto xnb = [&](int f, const float (&v)[NCH][4], int c, float& left, float& right) {
+    auto xnb = [&](int f, const float (&v)[NCH][4], int c, float& left, float& right) __attribute__((always_inline)) {
         float fl, fr;
         if (c > 0) fl = lane_from_left_wrap(v[c - 1][3]);
         else if (xsl[f] == XS_ROT) fl = lane_from_left_wrap(v[NCH - 1][3]);
@@ -1540,10 +1630,7 @@ __device__ __forceinline__ void lds2_consumer(const StepArgs& a, const float* ir
         left = lane_from_left(v[c][3], fl);
         right = lane_from_right(v[c][0], fr);
     };
-    auto ld4 = [&](const float* p, float (&o)[4]) {
-        const float4 t = *reinterpret_cast<const float4*>(p);
-        o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
-    };
+    auto ld4 = [&](const RD_LDS float* p, float (&o)[4]) __attribute__((always_inline)) { lds_ld4(p, o); };
 
     int islot0 = 0;              // input slot of plane q-1 at iteration q (plane z0-2 is slot 0)
     int mslot = 0;               // mid slot of plane q (mid plane z0-1 is slot 0)
@@ -1553,10 +1640,10 @@ __device__ __forceinline__ void lds2_consumer(const StepArgs& a, const float* ir
         // ---- mid plane q on rows yb-1 .. yb+BY (mid row m = grid row yb-1+m)
         if (q <= z1) {
             const int sm = islot0, s0 = islot0 + 1 == D ? 0 : islot0 + 1, sp = s0 + 1 == D ? 0 : s0 + 1;
-            const float* Im = iring + sm * R::ISLOT;
-            const float* I0 = iring + s0 * R::ISLOT;
-            const float* Ip = iring + sp * R::ISLOT;
-            float* Mq = mring + mslot * R::MSLOT;
+            const RD_LDS float* Im = iring + sm * R::ISLOT;
+            const RD_LDS float* I0 = iring + s0 * R::ISLOT;
+            const RD_LDS float* Ip = iring + sp * R::ISLOT;
+            RD_LDS float* Mq = mring + mslot * R::MSLOT;
 #pragma unroll
             for (int k = 0; k < MPW; ++k) {
                 const int m = cw + k * WC;
@@ -1637,8 +1724,7 @@ __device__ __forceinline__ void lds2_consumer(const StepArgs& a, const float* ir
                         }
 #pragma unroll
                         for (int s = 0; s < NO; ++s)
-                            *reinterpret_cast<float4*>(Mq + (s * MROWS + m) * TXT + c * 256 + lane * 4) =
-                                make_float4(o[s][0], o[s][1], o[s][2], o[s][3]);
+                            lds_st4(Mq + (s * MROWS + m) * TXT + c * 256 + lane * 4, o[s][0], o[s][1], o[s][2], o[s][3]);
                     }
                 }
             }
@@ -1666,9 +1752,9 @@ __device__ __forceinline__ void lds2_consumer(const StepArgs& a, const float* ir
                     const MidSrc pzm = mid_src(z - 1, a.nz, z - 1, kk[4], kk[5], vv[4], vv[5]);
                     const MidSrc pzp = mid_src(z + 1, a.nz, z - 1, kk[4], kk[5], vv[4], vv[5]);
                     // pzm.idx / pzp.idx: 0 = plane z-1, 1 = plane z, 2 = plane z+1
-                    const float* Mz = mring + ms_z * R::MSLOT + f * MROWS * TXT;
-                    const float* Mm = mring + (pzm.idx == 1 ? ms_z : ms_m) * R::MSLOT + f * MROWS * TXT;
-                    const float* Mp = mring + (pzp.idx == 1 ? ms_z : ms_p) * R::MSLOT + f * MROWS * TXT;
+                    const RD_LDS float* Mz = mring + ms_z * R::MSLOT + f * MROWS * TXT;
+                    const RD_LDS float* Mm = mring + (pzm.idx == 1 ? ms_z : ms_m) * R::MSLOT + f * MROWS * TXT;
+                    const RD_LDS float* Mp = mring + (pzp.idx == 1 ? ms_z : ms_p) * R::MSLOT + f * MROWS * TXT;
 #pragma unroll
                     for (int c = 0; c < NCH; ++c) {
 #pragma unroll
@@ -1752,8 +1838,10 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds2_kernel(const StepArgs* __r
     const int yb = tc.y * BY;
     const int z0 = tc.z * a.cz;
     const int z1 = min(z0 + a.cz, a.nz);
-    if (w == 0) lds2_producer<M, NCH, BY, WC, D>(a, iring, yb, z0, z1);
-    else lds2_consumer<M, NCH, BY, WC, D>(a, iring, mring, w - 1, yb, z0, z1);
+    RD_LDS float* ib = (RD_LDS float*)&iring[0];
+    RD_LDS float* mb = (RD_LDS float*)&mring[0];
+    if (w == 0) lds2_producer<M, NCH, BY, WC, D>(a, ib, yb, z0, z1);
+    else lds2_consumer<M, NCH, BY, WC, D>(a, ib, mb, w - 1, yb, z0, z1);
 }
 
 // ------------------------------------------------------------ batched kernel

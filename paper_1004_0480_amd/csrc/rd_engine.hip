@@ -256,6 +256,22 @@ long long set_tiling(StepArgs& a, const rd_plan& p) {
 rd_plan heuristic_plan(const rd_grid* g) {
     rd_plan best{};
     best.kernel = RD_KERNEL_DIRECT;
+    if (g->args[0][0].s19) {
+        // 19-point: the first LDS-ring shape this grid and model take, else direct
+        for (int i = 0; i < kNumLdsCfgs; ++i) {
+            const LdsCfg c = kLdsCfgs[i];
+            bool ok = g->nx == 256 * c.nch;
+            for (int k = 0; k < g->npass; ++k) ok = ok && lds_ok(g->storage, g->pass_pm[k], i);
+            if (!ok) continue;
+            best.kernel = RD_KERNEL_LDS;
+            best.vx = 4 * c.nch;
+            best.ry = c.by;
+            best.waves = c.wc;
+            best.prefetch = c.d;
+            break;
+        }
+        return best;
+    }
     double best_score = 1e30;
     unsigned mask = ~0u;
     for (int k = 0; k < g->npass; ++k) mask &= block_mask(g->storage, g->pass_pm[k]);
@@ -286,11 +302,15 @@ rd_plan heuristic_plan(const rd_grid* g) {
 }
 
 std::mutex g_tune_mu;
+// autotuned plans by (nx, ny, nz, species, model and stencil, storage)
 std::map<std::tuple<int64_t, int64_t, int64_t, int, int, int>, rd_plan> g_tune_cache;
+int tune_model_key(const rd_grid* g) { return g->model * 2 + (g->args[0][0].s19 ? 1 : 0); }
 
 int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
     if (p.graph_chunk != 0 && (p.graph_chunk < 2 || (p.graph_chunk & 1)))
         return fail(RD_EINVAL, "graph_chunk must be 0 or an even number >= 2");
+    if (g->args[0][0].s19 && p.kernel != RD_KERNEL_DIRECT && p.kernel != RD_KERNEL_LDS)
+        return fail(RD_EINVAL, "the 19-point Laplacian runs on the direct and LDS-ring plans only");
     if (p.kernel == RD_KERNEL_DIRECT) {
         if (g->nz > 65535 || (g->ny + 3) / 4 > 65535)
             return fail(RD_EINVAL, "grid too large for the direct kernel's launch shape");
@@ -344,7 +364,7 @@ int apply_plan(rd_grid* g) {
     rd_plan p = g->plan;
     if (p.kernel == RD_KERNEL_AUTO) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find({g->nx, g->ny, g->nz, g->ns, g->model, g->storage});
+        auto it = g_tune_cache.find({g->nx, g->ny, g->nz, g->ns, tune_model_key(g), g->storage});
         const int gc = p.graph_chunk;
         p = it != g_tune_cache.end() ? it->second : heuristic_plan(g);
         p.graph_chunk = gc;
@@ -516,19 +536,29 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
     } else if (m->nsrc != 0) {
         return fail(RD_EINVAL, "point sources need the pollutant model");
     }
-    // Explicit stability (monotone bound of the 7-point stencil + upwind).
+    if (m->stencil != 0 && m->stencil != 7 && m->stencil != 19) return fail(RD_EINVAL, "stencil must be 7 or 19");
+    const bool s19 = m->stencil == 19;
+    if (s19)
+        for (int s = 0; s < ns; ++s)
+            if (m->diff[s][1] != m->diff[s][0] || m->diff[s][2] != m->diff[s][0])
+                return fail(RD_EINVAL, "the 19-point Laplacian needs isotropic diffusion coefficients");
+    // Explicit stability: monotone bound (non-negative centre weight) of the
+    // stencil plus upwind; 19-point centre weight 24/(6h^2) = 4/h^2.
     const double h2 = h * h;
     for (int s = 0; s < ns; ++s) {
-        const double k = 2.0 * (m->diff[s][0] + m->diff[s][1] + m->diff[s][2]) / h2 + umax / h;
+        const double k = (s19 ? 4.0 * m->diff[s][0] : 2.0 * (m->diff[s][0] + m->diff[s][1] + m->diff[s][2])) / h2 +
+                         umax / h;
         if (m->dt * k > 1.0 + 1e-12)
-            return fail(RD_EUNSTABLE, "dt exceeds the explicit bound dt*(2*sum(K)/h^2 + umax/h) <= 1");
+            return fail(RD_EUNSTABLE, s19 ? "dt exceeds the explicit bound dt*(4*D/h^2 + umax/h) <= 1"
+                                          : "dt exceeds the explicit bound dt*(2*sum(K)/h^2 + umax/h) <= 1");
     }
     if (m->model == RD_MODEL_FRONT_CH) {
         const double M = m->param[1], kappa = m->param[2], eps = m->param[3];
         if (M < 0.0 || kappa < 0.0) return fail(RD_EINVAL, "M and kappa must be >= 0");
-        const double lam = 12.0 / h2;
+        // largest magnitude of the discrete Laplacian: 7-point 12/h^2, 19-point 32/(6h^2)
+        const double lam = s19 ? 16.0 / (3.0 * h2) : 12.0 / h2;
         if (m->dt * M * (kappa * lam * lam + std::fabs(eps) * lam) > 1.0 + 1e-12)
-            return fail(RD_EUNSTABLE, "dt exceeds the Cahn-Hilliard bound dt*M*(kappa*(12/h^2)^2 + |eps|*12/h^2) <= 1");
+            return fail(RD_EUNSTABLE, "dt exceeds the Cahn-Hilliard bound dt*M*(kappa*L^2 + |eps|*L) <= 1");
     }
     return RD_OK;
 }
@@ -654,10 +684,14 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
     }
 
     const PassGroups groups = pass_groups(m->model, ns);
+    // 19-point form: the kernels take K/(6h^2) as their coefficient
+    const bool s19 = m->stencil == 19;
+    const double lap_scale = s19 ? 1.0 / 6.0 : 1.0;
     for (int par = 0; par < 2; ++par) {
         for (int k = 0; k < 2; ++k) {
             StepArgs& a = g->args[par][k];
             std::memset(&a, 0, sizeof(a));
+            a.s19 = s19 ? 1 : 0;
             a.nx = int(g->nx);
             a.ny = int(g->ny);
             a.nz = int(g->nz);
@@ -675,21 +709,21 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
             StepArgs& a0 = g->args[par][0];
             a0.in[0] = g->buf[par][2];
             a0.out[0] = g->aux;
-            a0.kx[0] = a0.ky[0] = a0.kz[0] = float(ih2);
+            a0.kx[0] = a0.ky[0] = a0.kz[0] = float(ih2 * lap_scale);
             fill_bc(a0, 0, m, 2);
             a0.out_held[0] = 0;
             StepArgs& a1 = g->args[par][1];
             for (int s = 0; s < 3; ++s) {
                 a1.in[s] = g->buf[par][s];
                 a1.out[s] = g->buf[par ^ 1][s];
-                a1.kx[s] = float(m->diff[s][0] * ih2);
-                a1.ky[s] = float(m->diff[s][1] * ih2);
-                a1.kz[s] = float(m->diff[s][2] * ih2);
+                a1.kx[s] = float(m->diff[s][0] * ih2 * lap_scale);
+                a1.ky[s] = float(m->diff[s][1] * ih2 * lap_scale);
+                a1.kz[s] = float(m->diff[s][2] * ih2 * lap_scale);
                 fill_bc(a1, s, m, s);
                 a1.out_held[s] = a1.held[s];
             }
             a1.in[3] = g->aux;
-            a1.kx[3] = a1.ky[3] = a1.kz[3] = float(ih2);
+            a1.kx[3] = a1.ky[3] = a1.kz[3] = float(ih2 * lap_scale);
             fill_mirror(a1, 3);
             for (int k = 0; k < 2; ++k) {
                 StepArgs& a = g->args[par][k];
@@ -708,9 +742,9 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
                     const int s = s0 + f;
                     a.in[f] = g->buf[par][s];
                     a.out[f] = g->buf[par ^ 1][s];
-                    a.kx[f] = float(m->diff[s][0] * ih2);
-                    a.ky[f] = float(m->diff[s][1] * ih2);
-                    a.kz[f] = float(m->diff[s][2] * ih2);
+                    a.kx[f] = float(m->diff[s][0] * ih2 * lap_scale);
+                    a.ky[f] = float(m->diff[s][1] * ih2 * lap_scale);
+                    a.kz[f] = float(m->diff[s][2] * ih2 * lap_scale);
                     fill_bc(a, f, m, s);
                     a.out_held[f] = a.held[f];
                 }
@@ -1058,7 +1092,7 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     if (rc == RD_OK) {
         best_plan.graph_chunk = 0;
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[{g->nx, g->ny, g->nz, g->ns, g->model, g->storage}] = best_plan;
+        g_tune_cache[{g->nx, g->ny, g->nz, g->ns, tune_model_key(g), g->storage}] = best_plan;
     }
     g->plan = user;
     const int rc2 = apply_plan(g);
@@ -1145,6 +1179,7 @@ extern "C" int rd_batch_add(rd_batch* b, rd_grid* g, int64_t steps) {
     if (!g->has_model) return fail(RD_ESTATE, "grid has no model");
     if (!(g->model == RD_MODEL_BRUSSELATOR || (g->model == RD_MODEL_DIFFUSION && g->ns == 1)))
         return fail(RD_EINVAL, "batches take 1-species diffusion or Brusselator grids");
+    if (g->args[0][0].s19) return fail(RD_EINVAL, "batches take 7-point grids");
     if (g->storage != b->storage) return fail(RD_EINVAL, "grid storage differs from the batch's");
     if (g->stream != b->stream) return fail(RD_EINVAL, "grid and batch must use the same stream");
     if (int(b->members.size()) >= b->max_grids) return fail(RD_EINVAL, "batch is full");

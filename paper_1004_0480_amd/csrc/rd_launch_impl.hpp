@@ -29,10 +29,10 @@ template <> struct PmOf<Pollutant<1, false>> { static constexpr int v = PM_POLL1
 template <> struct PmOf<Pollutant<2, true>> { static constexpr int v = PM_POLL2; };
 template <> struct PmOf<Pollutant<2, false>> { static constexpr int v = PM_POLL2U; };
 
-template <class M>
+template <class M, bool S19>
 hipError_t run_direct(const StepArgs& h, const StepArgs* d, hipStream_t s) {
     dim3 grid((h.nx + 63) / 64, (h.ny + 3) / 4, h.nz);
-    hipLaunchKernelGGL((direct_kernel<M, S>), grid, dim3(256), 0, s, d);
+    hipLaunchKernelGGL((direct_kernel<M, S, S19>), grid, dim3(256), 0, s, d);
     return hipGetLastError();
 }
 
@@ -60,12 +60,12 @@ hipError_t run_block(const StepArgs* d, long long blocks, hipStream_t s) {
     }
 }
 
-template <class M, int I>
+template <class M, int I, bool S19>
 hipError_t run_lds(const StepArgs* d, long long blocks, hipStream_t s) {
     if constexpr (lds_ok(kStorage, PmOf<M>::v, I)) {
         constexpr LdsCfg c = kLdsCfgs[I];
-        hipLaunchKernelGGL((lds_kernel<M, c.nch, c.by, c.wc, c.d>), dim3((unsigned)blocks), dim3(64 * (c.wc + 1)),
-                           0, s, d);
+        hipLaunchKernelGGL((lds_kernel<M, c.nch, c.by, c.wc, c.d, S19>), dim3((unsigned)blocks),
+                           dim3(64 * (c.wc + 1)), 0, s, d);
         return hipGetLastError();
     } else {
         return hipErrorNotSupported;
@@ -101,11 +101,11 @@ hipError_t run_block_index(int cfg, const StepArgs* d, long long blocks, hipStre
     return r;
 }
 
-template <class M, int... I>
+template <class M, bool S19, int... I>
 hipError_t run_lds_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
                          std::integer_sequence<int, I...>) {
     hipError_t r = hipErrorInvalidValue;
-    ((void)(cfg == I && ((r = run_lds<M, I>(d, blocks, s)), true)), ...);
+    ((void)(cfg == I && ((r = run_lds<M, I, S19>(d, blocks, s)), true)), ...);
     return r;
 }
 
@@ -120,9 +120,13 @@ hipError_t run_lds2_index(int cfg, const StepArgs* d, long long blocks, hipStrea
 template <class M>
 hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, long long blocks,
                      hipStream_t s) {
+    // the 19-point Laplacian runs on the direct and LDS-ring kernels only
+    if (kernel == 1) return h.s19 ? run_direct<M, true>(h, d, s) : run_direct<M, false>(h, d, s);
+    if (kernel == 4)
+        return h.s19 ? run_lds_index<M, true>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLdsCfgs>{})
+                     : run_lds_index<M, false>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLdsCfgs>{});
+    if (h.s19) return hipErrorNotSupported;
     if (kernel == 5) return run_lds2_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLds2Cfgs>{});
-    if (kernel == 1) return run_direct<M>(h, d, s);
-    if (kernel == 4) return run_lds_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLdsCfgs>{});
     if (kernel == 3) return run_block_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumBlockCfgs>{});
     return run_tiled_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumTileCfgs>{});
 }

@@ -48,6 +48,7 @@ class ModelDesc(C.Structure):
         ("src_cell", C.POINTER(C.c_int64)),
         ("src_species", C.POINTER(C.c_int32)),
         ("src_rate", C.POINTER(C.c_double)),
+        ("stencil", C.c_int32),
     ]
 
 
@@ -139,6 +140,7 @@ def model_desc(spec, shape) -> Tuple[ModelDesc, list]:
     m.model = MODEL[spec.model]
     m.nspecies = spec.ns
     m.dt = float(spec.dt)
+    m.stencil = int(getattr(spec, "stencil", 7))
     for s in range(spec.ns):
         for d in range(3):
             m.diff[s][d] = float(spec.K[s][d])

@@ -31,8 +31,8 @@ def test_library_loads_and_exports_header_functions():
 
 def test_model_desc_layout_matches_header():
     # int32 model, int32 nspecies, double dt, 4x3 double, 4x6 int32, 4x6 double,
-    # 8 double, ptr, int64, int64, ptr, ptr, ptr
-    assert C.sizeof(rd.ModelDesc) == 4 + 4 + 8 + 96 + 96 + 192 + 64 + 8 + 8 + 8 + 8 + 8 + 8
+    # 8 double, ptr, int64, int64, ptr, ptr, ptr, int32 stencil (+4 padding)
+    assert C.sizeof(rd.ModelDesc) == 4 + 4 + 8 + 96 + 96 + 192 + 64 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert C.sizeof(rd.Plan) == 32
 
 
@@ -115,6 +115,24 @@ def test_validate_rejects_bad_models():
     s = W.diffusion_spec()
     s.dt = float("inf")
     assert rd.validate_model(s, shape) == rd.EINVAL
+
+
+def test_validate_stencil19():
+    shape = (8, 8, 8)
+    s = W.diffusion_spec(dt=0.2)
+    s.stencil = 19
+    assert rd.validate_model(s, shape) == rd.OK           # 0.2 * 4 <= 1
+    s.dt = 0.26
+    assert rd.validate_model(s, shape) == rd.EUNSTABLE    # 0.26 * 4 > 1
+    a = W.diffusion_spec(dt=0.05)
+    a.K[0][2] = 0.5
+    a.stencil = 19
+    assert rd.validate_model(a, shape) == rd.EINVAL       # anisotropic
+    a.stencil = 9
+    assert rd.validate_model(a, shape) == rd.EINVAL
+    p = W.pollutant_spec(shape, 1)
+    p.stencil = 19                                        # Kx = Ky = 50, Kz = 1
+    assert rd.validate_model(p, shape) == rd.EINVAL
 
 
 def test_grid_bytes():

@@ -494,6 +494,145 @@ def test_whole_tile_rows_every_plan(case):
             assert np.array_equal(got[s], base[s]), (case, plan, s)
 
 
+# ------------------------------------------------------ 19-point Laplacian
+
+def as19(w, dt=None):
+    """The same workload on the 19-point Laplacian of Eqs. (3)-(4): each
+    species keeps its x coefficient on every axis."""
+    spec = w.spec.copy()
+    spec.stencil = 19
+    spec.K = [[k[0]] * 3 for k in spec.K]
+    if dt is not None:
+        spec.dt = dt
+    return W.Workload(w.name + "_19", w.shape, spec, w.fields, w.steps, w.seed)
+
+
+def case19(case):
+    if case == "faces70":
+        shape = (9, 10, 70)
+        rng = np.random.default_rng(21)
+        faces = [(HELD, 1.0), (GHOST, -0.5), (PERIODIC, 0), (PERIODIC, 0), (GHOST, 2.0), (HELD, -1.0)]
+        return as19(W.Workload("faces70", shape, bc_spec(2, faces, K=(0.5, 0.5, 0.5)),
+                               [rng.uniform(0, 1, shape) for _ in range(2)], 6, 0))
+    if case == "faces256":
+        shape = (10, 12, 256)
+        rng = np.random.default_rng(22)
+        faces = [(GHOST, 0.5), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0), (HELD, 0.25), (GHOST, -1.0)]
+        return as19(W.Workload("faces256", shape, bc_spec(1, faces, K=(1.0, 1.0, 1.0)),
+                               [rng.uniform(0, 1, shape)], 6, 0))
+    if case == "held512":
+        shape = (7, 9, 512)
+        rng = np.random.default_rng(23)
+        faces = [(HELD, 1.0), (GHOST, -0.5), (HELD, 0.25), (MIRROR, 0), (GHOST, 2.0), (HELD, -1.0)]
+        return as19(W.Workload("held512", shape, bc_spec(2, faces, K=(1.0, 1.0, 1.0)),
+                               [rng.uniform(0, 1, shape) for _ in range(2)], 6, 0))
+    if case == "bruss256":
+        return as19(W.make_workload("brusselator256", shape=(8, 10, 256)))
+    if case == "bruss256ragged":
+        return as19(W.make_workload("brusselator256", shape=(5, 19, 256)))
+    if case == "poll256":
+        return as19(W.make_workload("pollutant512", shape=(9, 11, 256)))
+    if case == "front512":
+        w = W.make_workload("front384", shape=(9, 10, 512))
+        spec = w.spec
+        spec.bc[2] = [(HELD, 0.3), (GHOST, 0.1), (GHOST, -0.2), (HELD, 0.4), (HELD, 0.5), (GHOST, 0.0)]
+        spec.bc[1] = [(GHOST, 0.2), (HELD, 0.6), (MIRROR, 0), (GHOST, 0.3), (MIRROR, 0), (HELD, 0.1)]
+        rng = np.random.default_rng(24)
+        fields = [f.astype(np.float32).astype(np.float64) for f in w.fields]
+        fields[2] = rng.uniform(-1.0, 1.0, w.shape).astype(np.float32).astype(np.float64)
+        return as19(W.Workload("front512", w.shape, spec, fields, 6, 0))
+    raise KeyError(case)
+
+
+@pytest.mark.parametrize("case", ["faces70", "faces256", "held512", "bruss256", "bruss256ragged",
+                                  "poll256", "front512"])
+def test_stencil19_every_plan(case):
+    """The 19-point Laplacian with edge ghosts on every face kind: the
+    direct and LDS-ring plans agree bit for bit and with the oracle; the
+    plans that only know the 7-point form are refused."""
+    w = case19(case)
+    steps = 6
+    ref = oracle.run(w.spec, w.fields, steps)
+    plans = compiled_plans(w, czs=(0, 4, 7))
+    assert all(p["kernel"] in ("direct", "lds") for p in plans), case
+    if w.shape[2] in (256, 512) and w.spec.model in ("diffusion", "brusselator", "pollutant"):
+        assert any(p["kernel"] == "lds" for p in plans), case
+    base = None
+    for plan in plans:
+        got, _ = gpu_run(w, steps, plan=plan)
+        if base is None:
+            base = got
+            for s in range(w.spec.ns):
+                e = rel_l2(got[s], ref[s])
+                print("%s species %d rel-L2 %.3e" % (case, s, e))
+                assert e <= TOL, (case, s, e)
+            continue
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], base[s]), (case, plan, s)
+    # the 7-point change over these steps is measurably different, so the
+    # stencil took effect
+    w7 = W.Workload(w.name, w.shape, w.spec.copy(), w.fields, steps, 0)
+    w7.spec.stencil = 7
+    got7, _ = gpu_run(w7, steps, plan=dict(kernel="direct"))
+    assert any(rel_l2(got7[s] - w.fields[s], ref[s] - w.fields[s]) > 1e-3 for s in range(w.spec.ns)), case
+
+
+def test_stencil19_front_chemical_potential():
+    """The Cahn-Hilliard potential with the 19-point Laplacian (first pass)."""
+    w = case19("front512")
+    mu_ref = oracle.chemical_potential(w.spec, w.fields)
+    for plan in compiled_plans(w, czs=(0,)):
+        g = rd.Grid(w.shape, 3, 1.0)
+        g.set_model(w.spec)
+        g.set_plan(**plan)
+        for s in range(3):
+            g.write(s, w.fields[s])
+        mu = g.chemical_potential().astype(np.float64)
+        g.close()
+        assert np.max(np.abs(mu - mu_ref)) <= 1e-5 * max(1.0, np.max(np.abs(mu_ref))), plan
+
+
+def test_stencil19_long_run_and_graphs():
+    """200 steps of 19-point diffusion on 64^3 no-flux, eager and through
+    graph chunks: the oracle's answer, and mass kept to FP32 rounding."""
+    import torch
+    w = as19(W.make_workload("diffusion64"))
+    ref = oracle.run(w.spec, w.fields, 200)
+    eager = None
+    for chunk in (0, 16):
+        g = rd.Grid(w.shape, 1, w.spec.h, "f32", stream=torch.cuda.Stream() if chunk else None)
+        g.set_model(w.spec)
+        g.set_plan(graph_chunk=chunk)
+        g.write(0, w.fields[0])
+        g.step(120)
+        g.step(80)
+        got = g.read_all()
+        g.close()
+        if eager is None:
+            eager = got
+            assert rel_l2(got[0], ref[0]) <= TOL
+            assert abs(got[0].sum() - w.fields[0].sum()) <= 1e-5 * w.fields[0].sum()
+        assert np.array_equal(got[0], eager[0]), chunk
+
+
+@pytest.mark.parametrize("name,steps", [("diffusion512", 2), ("brusselator256", 4)])
+def test_stencil19_full_size_autotuned(name, steps):
+    """Full-size grids on the 19-point form in the autotuned plan."""
+    w = as19(W.make_workload(name))
+    g = rd.Grid.from_workload(w)
+    g.autotune(3)
+    plan = g.plan()
+    assert plan["kernel"] in (rd.KERNEL["direct"], rd.KERNEL["lds"]), plan
+    g.step(steps)
+    got = g.read_all()
+    g.close()
+    ref = oracle.run(w.spec, w.fields, steps)
+    for s in range(w.spec.ns):
+        e = rel_l2(got[s], ref[s])
+        print("%s 19-point species %d rel-L2 %.3e plan %s" % (name, s, e, plan))
+        assert e <= TOL
+
+
 @pytest.mark.parametrize("name,shape", [("brusselator256", (6, 12, 256)), ("diffusion512", (9, 7, 512))])
 def test_two_step_plans_with_graphs_and_odd_counts(name, shape):
     """Two steps per launch: graph chunks of 2, 4 and 6 steps and odd step
