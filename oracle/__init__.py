@@ -7,8 +7,8 @@ with the HIP path: it reads a problem description made of plain numbers
 
 The arithmetic lives in ``rd_oracle.c`` (section 2, Eqs. (2) and (5), the
 7-point Laplacian or the 19-point one of Eqs. (3)-(4), the boundary handling
-of section 4.1 and the four Table 1 model families); see its header for the
-exact definition.
+of section 4.1, the four Table 1 model families and the pollutant model with a
+height-dependent wind); see its header for the exact definition.
 """
 from __future__ import annotations
 
@@ -23,13 +23,17 @@ _LIBPATH = os.path.join(_HERE, "liboracle.so")
 
 MIRROR, PERIODIC, GHOST, HELD = 0, 1, 2, 3
 _KIND = {"mirror": MIRROR, "periodic": PERIODIC, "ghost": GHOST, "held": HELD}
-_MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3}
+_MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3, "turing": 4, "atmos": 5}
 _PARAM_SLOTS = {
     "diffusion": (),
     "brusselator": ("a", "b"),
-    "front_ch": ("k", "M", "kappa", "eps", "gamma"),
+    "front_ch": ("k", "M", "kappa", "eps", "gamma", "k2"),
     "pollutant": ("decay", "kab"),
+    "turing": ("alpha", "beta", "gamma"),
+    "atmos": ("ux", "uy", "uz", "uz_period", "t0"),
 }
+# constants that may be left out of a spec's params (then 0)
+_OPTIONAL = ("k2", "uz_period", "t0")
 
 
 class _Problem(C.Structure):
@@ -68,6 +72,8 @@ def _load():
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.or_reduce.restype = None
         lib.or_threads.restype = C.c_int
+        lib.or_set_threads.argtypes = [C.c_int]
+        lib.or_set_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -93,7 +99,7 @@ def _problem(spec, shape):
             P.bc_kind[s][f] = _KIND[kind]
             P.bc_value[s][f] = float(val)
     for slot, name in enumerate(_PARAM_SLOTS[spec.model]):
-        P.p[slot] = float(spec.params[name])
+        P.p[slot] = float(spec.params.get(name, 0.0) if name in _OPTIONAL else spec.params[name])
     keep = []
     if spec.model == "pollutant":
         wind = np.ascontiguousarray(spec.wind, dtype=np.float64)
@@ -101,6 +107,7 @@ def _problem(spec, shape):
             raise ValueError("wind must have nz entries")
         keep.append(wind)
         P.wind = _dptr(wind)
+    if spec.model in ("pollutant", "atmos"):
         if spec.sources is not None and len(spec.sources[0]):
             cell = np.ascontiguousarray(spec.sources[0], dtype=np.int64)
             sp = np.ascontiguousarray(spec.sources[1], dtype=np.int32)
@@ -154,3 +161,8 @@ def reduce(field: np.ndarray, h: float = 1.0):
 
 def threads() -> int:
     return int(_load().or_threads())
+
+
+def set_threads(n: int) -> int:
+    """Run on n threads from now on; returns the number in use."""
+    return int(_load().or_set_threads(int(n)))

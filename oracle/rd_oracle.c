@@ -156,7 +156,8 @@ static int valid(const or_problem *P)
     if (P->ns < 1 || P->ns > OR_MAX_SPECIES) return 0;
     if (P->model == OR_BRUSSELATOR && P->ns != 2) return 0;
     if (P->model == OR_FRONT_CH && P->ns != 3) return 0;
-    if (P->model < OR_DIFFUSION || P->model > OR_POLLUTANT) return 0;
+    if (P->model == OR_TURING && P->ns != 2) return 0;
+    if (P->model < OR_DIFFUSION || P->model > OR_ATMOS) return 0;
     if (P->model == OR_POLLUTANT && !P->wind) return 0;
     if (P->stencil != 7 && P->stencil != 19) return 0;
     if (P->stencil == 19)
@@ -193,14 +194,32 @@ static void chemical_potential(const or_problem *P, const double *C, double *mu)
             }
 }
 
-/* One forward Euler step (Eq. (5)) from `in` to `out` (Table 3 lines 4-9). */
+/* First-order upwind approximation of -u d(c)/d(axis) at (i, j, k): the
+ * one-sided difference on the side the wind comes from (section 4.1). */
+static double upwind(const or_problem *P, const double *f, const int32_t kind[6],
+                     const double val[6], double u, int axis, int64_t i, int64_t j, int64_t k)
+{
+    const int64_t di = axis == 0, dj = axis == 1, dk = axis == 2;
+    const double c = sample(f, P->nx, P->ny, P->nz, kind, val, i, j, k);
+    if (u > 0.0)
+        return -u * (c - sample(f, P->nx, P->ny, P->nz, kind, val, i - di, j - dj, k - dk)) / P->h;
+    if (u < 0.0)
+        return -u * (sample(f, P->nx, P->ny, P->nz, kind, val, i + di, j + dj, k + dk) - c) / P->h;
+    return 0.0;
+}
+
+/* One forward Euler step (Eq. (5)) from `in` to `out` (Table 3 lines 4-9);
+ * `t` is the time of the old level. */
 static void step(const or_problem *P, const double *in, double *out, double *mu,
-                 const source_t *src, int64_t nsrc)
+                 const source_t *src, int64_t nsrc, double t)
 {
     const int64_t nx = P->nx, ny = P->ny, nz = P->nz, N = nx * ny * nz;
     const int ns = P->ns;
     const double dt = P->dt, h = P->h;
     const double unit[3] = { 1.0, 1.0, 1.0 };
+    /* atmospheric wind at time t (Table 1, last row) */
+    const double wind[3] = { P->p[0], P->p[1],
+                             P->p[3] != 0.0 ? P->p[2] * sin(t / P->p[3]) : P->p[2] };
 
     if (P->model == OR_FRONT_CH)
         chemical_potential(P, in + 2 * N, mu);
@@ -224,12 +243,26 @@ static void step(const or_problem *P, const double *in, double *out, double *mu,
                 }
                 case OR_FRONT_CH: {
                     const double r = P->p[0] * c[0] * c[1];
+                    const double q = P->p[5] * c[0] * c[2];    /* redissolution A + C */
                     const double lap_mu = lap_of(P, mu, MU_KIND, MU_VAL, unit, i, j, k);
-                    rate[0] += -r;
+                    rate[0] += -r - q;
                     rate[1] += -r;
-                    rate[2] += r + P->p[1] * lap_mu;
+                    rate[2] += r - q + P->p[1] * lap_mu;
                     break;
                 }
+                case OR_TURING: {
+                    const double u = c[0], v = c[1];
+                    rate[0] += u - u * u * u - v;
+                    rate[1] += P->p[2] * (u - P->p[0] * v - P->p[1]);
+                    break;
+                }
+                case OR_ATMOS:
+                    for (int s = 0; s < ns; ++s) {
+                        for (int d = 0; d < 3; ++d)
+                            rate[s] += upwind(P, in + s * N, P->bc_kind[s], P->bc_value[s], wind[d], d, i, j, k);
+                        rate[s] += emission(src, nsrc, idx, s);
+                    }
+                    break;
                 case OR_POLLUTANT: {
                     const double u = P->wind[k];
                     for (int s = 0; s < ns; ++s) {
@@ -268,7 +301,7 @@ int or_run(const or_problem *P, double *state, int64_t nsteps)
     source_t *src = NULL;
     int64_t nsrc = 0;
     if (!work || (P->model == OR_FRONT_CH && !mu)) { free(work); free(mu); return -1; }
-    if (P->model == OR_POLLUTANT && P->nsrc > 0) {
+    if ((P->model == OR_POLLUTANT || P->model == OR_ATMOS) && P->nsrc > 0) {
         src = (source_t *)malloc((size_t)P->nsrc * sizeof(source_t));
         if (!src) { free(work); free(mu); return -1; }
         for (int64_t q = 0; q < P->nsrc; ++q) {
@@ -281,7 +314,7 @@ int or_run(const or_problem *P, double *state, int64_t nsteps)
     }
     double *a = state, *b = work;
     for (int64_t n = 0; n < nsteps; ++n) {
-        step(P, a, b, mu, src, nsrc);
+        step(P, a, b, mu, src, nsrc, P->p[4] + (double)n * P->dt);
         double *t = a; a = b; b = t;            /* swap first and second arrays */
     }
     if (a != state) memcpy(state, a, bytes);
@@ -309,6 +342,16 @@ void or_reduce(int64_t nx, int64_t ny, int64_t nz, double h, const double *f, do
     }
     out[0] = m * h * h * h;
     out[1] = e * h * h * h;
+}
+
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return or_threads();
 }
 
 int or_threads(void)

@@ -45,22 +45,31 @@ extern "C" {
 #define OR_MAX_SPECIES 4
 
 enum { OR_MIRROR = 0, OR_PERIODIC = 1, OR_GHOST = 2, OR_HELD = 3 };
-enum { OR_DIFFUSION = 0, OR_BRUSSELATOR = 1, OR_FRONT_CH = 2, OR_POLLUTANT = 3 };
+enum { OR_DIFFUSION = 0, OR_BRUSSELATOR = 1, OR_FRONT_CH = 2, OR_POLLUTANT = 3,
+       OR_TURING = 4, OR_ATMOS = 5 };
 
 /* Model constants in p[]:
  *   OR_BRUSSELATOR  p[0]=a  p[1]=b
  *       R_u = a - (b+1) u + u^2 v ,  R_v = b u - u^2 v
- *   OR_FRONT_CH     p[0]=k  p[1]=M  p[2]=kappa  p[3]=eps  p[4]=gamma
- *       species A, B, C;  r = k A B
- *       R_A = -r ,  R_B = -r ,  R_C = r + M Lap(mu),
+ *   OR_FRONT_CH     p[0]=k  p[1]=M  p[2]=kappa  p[3]=eps  p[4]=gamma  p[5]=k2
+ *       species A, B, C;  r = k A B ,  q = k2 A C  (redissolution)
+ *       R_A = -r - q ,  R_B = -r ,  R_C = r - q + M Lap(mu),
  *       mu = gamma C^3 - eps C - kappa Lap(C)
- *     (Table 1, third row, -lambda Lap(eps c - gamma c^3 + sigma Lap c) with
+ *     (Table 1, third row: k = k_1, k2 = k_2, -lambda Lap(eps c - gamma c^3 + sigma Lap c) with
  *      lambda = M and sigma = kappa; the biharmonic part is the Laplacian
  *      taken twice with boundary values re-applied in between, section 4.1.
  *      mu's ghosts are mirror on every face.)
  *   OR_POLLUTANT    p[0]=decay lambda  p[1]=k_AB (species 0 -> species 1)
  *       A_s = -u(z) (c_s(i) - c_s(i-1)) / h     (upwind, u >= 0 along +x)
  *       R_s = -lambda c_s ;  R_0 -= k_AB c_0 ;  R_1 += k_AB c_0
+ *   OR_TURING       p[0]=alpha  p[1]=beta  p[2]=gamma   (Table 1, second row)
+ *       R_1 = c_1 - c_1^3 - c_2 ,  R_2 = gamma (c_1 - alpha c_2 - beta)
+ *   OR_ATMOS        p[0]=u_x  p[1]=u_y  p[2]=u_z amplitude  p[3]=T  p[4]=t_0
+ *       (Table 1, last row) a wind uniform in space, u = (u_x, u_y, u_z(t)),
+ *       u_z(t) = p[2] sin(t / T) (p[2] itself when T = 0), t = t_0 + n dt at
+ *       step n; A_s = sum over axes of the first-order upwind form of
+ *       -u_d dc/dx_d (the difference on the side the wind comes from);
+ *       E_s = point emissions (src_*); every species carried independently.
  */
 typedef struct or_problem {
     int64_t nx, ny, nz;
@@ -73,7 +82,7 @@ typedef struct or_problem {
     double bc_value[OR_MAX_SPECIES][6];
     double p[8];
     const double *wind;                   /* nz values (pollutant), else NULL */
-    int64_t nsrc;                         /* point sources (pollutant)        */
+    int64_t nsrc;                         /* point sources (pollutant, atmos) */
     const int64_t *src_cell;              /* linear index (k*ny + j)*nx + i   */
     const int32_t *src_species;
     const double *src_rate;
@@ -94,6 +103,10 @@ void or_reduce(int64_t nx, int64_t ny, int64_t nz, double h, const double *f,
 
 /* Number of threads or_run uses. */
 int or_threads(void);
+
+/* Use n threads from now on (n >= 1; the paper's CPU baseline is one
+ * thread); returns the number now in use. */
+int or_set_threads(int n);
 
 #ifdef __cplusplus
 }

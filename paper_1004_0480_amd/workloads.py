@@ -22,6 +22,15 @@ four single-grid workloads used throughout this package:
                           upwind log-profile wind in +x, decay, A->B, sources
 * ``diffusion512``     -- 512^3 single-species diffusion (bandwidth probe)
 
+the paper's own Table 1 problem set at its 192^3 grid, 19-point Laplacian:
+
+* ``t1_diffusion192``  -- D=1, h=1, dt=0.02, 1 inside a sphere of radius 20
+* ``t1_turing192``     -- activator/inhibitor, D1=5e-5, D2=5e-3, h=6.2e-3
+* ``t1_front192``      -- A+B->C with redissolution A+C, Cahn-Hilliard on C,
+                          A held at 10 on the x=0 plane
+* ``t1_atmos192``      -- one species, wind (5, 1, 5 sin(t/500)), D=100,
+                          h=100, dt=5, one point source of rate 10
+
 and the served-batch trace (``make_trace``).
 """
 from __future__ import annotations
@@ -41,7 +50,7 @@ HELD = "held"            # the boundary layer itself is held at a fixed value
 BC_KINDS = (MIRROR, PERIODIC, GHOST, HELD)
 FACES = ("x-", "x+", "y-", "y+", "z-", "z+")
 
-MODELS = ("diffusion", "brusselator", "front_ch", "pollutant")
+MODELS = ("diffusion", "brusselator", "front_ch", "pollutant", "turing", "atmos")
 
 
 @dataclass
@@ -170,6 +179,47 @@ def pollutant_spec(shape, seed: int, ns: int = 4, Kxy=50.0, Kz=1.0, umax=5.0,
                          shape, seed + 1000, n=nsrc, ns=ns, rate=rate))
 
 
+# ----------------------------------------------- the paper's Table 1 at 192^3
+
+def sphere(shape, radius: float):
+    """1 on cells whose centre lies within `radius` of the grid centre
+    ((n-1)/2 per axis), 0 elsewhere."""
+    nz, ny, nx = shape
+    z = np.arange(nz, dtype=np.float64) - (nz - 1) / 2.0
+    y = np.arange(ny, dtype=np.float64) - (ny - 1) / 2.0
+    x = np.arange(nx, dtype=np.float64) - (nx - 1) / 2.0
+    r2 = z[:, None, None] ** 2 + y[None, :, None] ** 2 + x[None, None, :] ** 2
+    return (r2 <= radius * radius).astype(np.float64)
+
+
+def turing_spec(D1=5e-5, D2=5e-3, h=6.2e-3, dt=5e-4, alpha=0.5, beta=0.09, gamma=26.0,
+                stencil: int = 19) -> ModelSpec:
+    return ModelSpec("turing", 2, dt, h, [[D1] * 3, [D2] * 3], uniform_bc(2, MIRROR),
+                     {"alpha": alpha, "beta": beta, "gamma": gamma}, stencil=stencil)
+
+
+def paper_front_spec(k1=0.2, k2=0.005, lam=1.0, eps=1.0, gamma=1.0, sigma=1.0, D1=1.0, D2=1.0,
+                     dt=0.02, h=1.0, held_value=10.0, stencil: int = 19) -> ModelSpec:
+    """Table 1, third row: C has no Fickian term; A is held on the x = 0 plane."""
+    bc = uniform_bc(3, MIRROR)
+    bc[0][0] = (HELD, float(held_value))
+    return ModelSpec("front_ch", 3, dt, h, [[D1] * 3, [D2] * 3, [0.0] * 3], bc,
+                     {"k": k1, "k2": k2, "M": lam, "kappa": sigma, "eps": eps, "gamma": gamma},
+                     stencil=stencil)
+
+
+def atmos_spec(shape, D=100.0, h=100.0, dt=5.0, ux=5.0, uy=1.0, uz=5.0, period=500.0, rate=10.0,
+               source=None, stencil: int = 19) -> ModelSpec:
+    """Table 1, last row.  The source cell is not given in the paper: here it
+    sits a quarter of the way along x (upwind), centred in y and z."""
+    nz, ny, nx = shape
+    sx, sy, sz = source if source is not None else (nx // 4, ny // 2, nz // 2)
+    cells = np.array([(sz * ny + sy) * nx + sx], np.int64)
+    return ModelSpec("atmos", 1, dt, h, [[D] * 3], uniform_bc(1, MIRROR),
+                     {"ux": ux, "uy": uy, "uz": uz, "uz_period": period, "t0": 0.0},
+                     sources=(cells, np.zeros(1, np.int32), np.array([rate])), stencil=stencil)
+
+
 # ------------------------------------------------------------------ catalogue
 
 DEFAULT_SHAPES = {
@@ -178,11 +228,17 @@ DEFAULT_SHAPES = {
     "front384": (512, 384, 384),
     "pollutant512": (128, 512, 512),
     "diffusion512": (512, 512, 512),
+    "t1_diffusion192": (192, 192, 192),
+    "t1_turing192": (192, 192, 192),
+    "t1_front192": (192, 192, 192),
+    "t1_atmos192": (192, 192, 192),
 }
 DEFAULT_STEPS = {"diffusion64": 100, "brusselator256": 2000, "front384": 5000,
-                 "pollutant512": 3000, "diffusion512": 100}
+                 "pollutant512": 3000, "diffusion512": 100, "t1_diffusion192": 1000,
+                 "t1_turing192": 1000, "t1_front192": 1000, "t1_atmos192": 1000}
 DEFAULT_SEEDS = {"diffusion64": 0, "brusselator256": 1, "front384": 2,
-                 "pollutant512": 3, "diffusion512": 5}
+                 "pollutant512": 3, "diffusion512": 5, "t1_diffusion192": 6,
+                 "t1_turing192": 7, "t1_front192": 8, "t1_atmos192": 9}
 
 
 def make_workload(name: str, shape: Optional[Tuple[int, int, int]] = None,
@@ -214,6 +270,21 @@ def make_workload(name: str, shape: Optional[Tuple[int, int, int]] = None,
     elif name == "pollutant512":
         spec = pollutant_spec(shape, seed)
         fields = [np.zeros(shape) for _ in range(spec.ns)]
+    elif name == "t1_diffusion192":
+        spec = ModelSpec("diffusion", 1, 0.02, 1.0, [[1.0] * 3], uniform_bc(1, MIRROR), stencil=19)
+        fields = [sphere(shape, 20.0)]
+    elif name == "t1_turing192":
+        spec = turing_spec()
+        rng = np.random.default_rng(seed)
+        fields = [1.0 + rng.uniform(-5e-4, 5e-4, size=shape) for _ in range(2)]
+    elif name == "t1_front192":
+        spec = paper_front_spec()
+        A = np.zeros(shape)
+        A[:, :, 0] = spec.bc[0][0][1]
+        fields = [A, np.ones(shape), np.full(shape, -1.0)]
+    elif name == "t1_atmos192":
+        spec = atmos_spec(shape)
+        fields = [np.zeros(shape)]
     else:
         raise KeyError(name)
     return Workload(name, shape, spec, fields, steps, seed)

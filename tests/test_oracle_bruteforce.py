@@ -7,6 +7,7 @@ are dyadic rationals and the parameters are the exact binary values of the
 doubles handed to the oracle, so the only difference left is the oracle's own
 FP64 rounding.
 """
+import math
 from fractions import Fraction as F
 
 import numpy as np
@@ -91,7 +92,16 @@ def lap19(get, p, K, h):
     return K[0] * total / (6 * h * h)
 
 
-def exact_step(spec, state):
+def wind_at(spec, n):
+    """The atmospheric wind of step n, as the exact values of the doubles the
+    oracle forms: u_z(t) = u_z sin(t / T), t = t_0 + n dt (Table 1, last row)."""
+    prm = spec.params
+    T, t0 = prm.get("uz_period", 0.0), prm.get("t0", 0.0)
+    uz = prm["uz"] * math.sin((t0 + float(n) * spec.dt) / T) if T != 0.0 else prm["uz"]
+    return [fr(prm["ux"]), fr(prm["uy"]), fr(uz)]
+
+
+def exact_step(spec, state, n=0):
     ns, h, dt = spec.ns, fr(spec.h), fr(spec.dt)
     K = [[fr(v) for v in row] for row in spec.K]
     lap = lap19 if getattr(spec, "stencil", 7) == 19 else lap7
@@ -104,7 +114,7 @@ def exact_step(spec, state):
               - P["kappa"] * lap(gets[2], p, [F(1)] * 3, h) for p in cells}
         mu_get = Exact(mu, [(MIRROR, 0.0)] * 6)
     src = {}
-    if spec.model == "pollutant" and spec.sources is not None:
+    if spec.model in ("pollutant", "atmos") and spec.sources is not None:
         for cell, sp, r in zip(*spec.sources):
             x, y, z = int(cell) % N, (int(cell) // N) % N, int(cell) // (N * N)
             src[(x, y, z, int(sp))] = src.get((x, y, z, int(sp)), F(0)) + fr(r)
@@ -118,9 +128,26 @@ def exact_step(spec, state):
             rate[1] += b * c[0] - c[0] ** 2 * c[1]
         elif spec.model == "front_ch":
             r = P["k"] * c[0] * c[1]
-            rate[0] -= r
+            q = P.get("k2", F(0)) * c[0] * c[2]
+            rate[0] -= r + q
             rate[1] -= r
-            rate[2] += r + P["M"] * lap(mu_get, p, [F(1)] * 3, h)
+            rate[2] += r - q + P["M"] * lap(mu_get, p, [F(1)] * 3, h)
+        elif spec.model == "turing":
+            rate[0] += c[0] - c[0] ** 3 - c[1]
+            rate[1] += P["gamma"] * (c[0] - P["alpha"] * c[1] - P["beta"])
+        elif spec.model == "atmos":
+            u = wind_at(spec, n)
+            for s in range(ns):
+                for axis in range(3):
+                    e = [0, 0, 0]
+                    e[axis] = 1
+                    up = gets[s]((p[0] + e[0], p[1] + e[1], p[2] + e[2]))
+                    down = gets[s]((p[0] - e[0], p[1] - e[1], p[2] - e[2]))
+                    if u[axis] > 0:
+                        rate[s] += -u[axis] * (c[s] - down) / h
+                    elif u[axis] < 0:
+                        rate[s] += -u[axis] * (up - c[s]) / h
+                rate[s] += src.get(p + (s,), F(0))
         elif spec.model == "pollutant":
             u = fr(spec.wind[p[2]])
             for s in range(ns):
@@ -203,6 +230,30 @@ CASES = {
         wind=np.array([0.0, 0.5, 0.75, 1.0]),
         sources=(np.array([5, 37], np.int64), np.array([1, 0], np.int32), np.array([10.0, 2.0])),
         stencil=19),
+    # the rest of Table 1: the Turing model, redissolution in the front
+    # model, and the atmospheric wind blowing along every axis in turn
+    "turing_mirror": lambda: ModelSpec(
+        "turing", 2, 1 / 64, 1.0, [[0.25] * 3, [1.0] * 3], [[(MIRROR, 0.0)] * 6] * 2,
+        {"alpha": 0.5, "beta": 0.09, "gamma": 26.0}),
+    "turing19_mixed": lambda: ModelSpec(
+        "turing", 2, 1 / 128, 0.5, [[0.125] * 3, [0.25] * 3],
+        [[(MIRROR, 0), (GHOST, 1.0), (PERIODIC, 0), (PERIODIC, 0), (HELD, 0.5), (MIRROR, 0)]] * 2,
+        {"alpha": 0.5, "beta": 0.09, "gamma": 26.0}, stencil=19),
+    "front19_redissolution": lambda: ModelSpec(
+        "front_ch", 3, 1 / 64, 1.0, [[1.0] * 3, [1.0] * 3, [0.0] * 3],
+        [[(HELD, 10.0)] + [(MIRROR, 0)] * 5, [(MIRROR, 0)] * 6, [(MIRROR, 0)] * 6],
+        {"k": 0.2, "k2": 0.125, "M": 1.0, "kappa": 1.0, "eps": 1.0, "gamma": 1.0}, stencil=19),
+    "atmos_wind_every_axis": lambda: ModelSpec(
+        "atmos", 1, 1 / 16, 1.0, [[0.25] * 3],
+        [[(MIRROR, 0), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0), (GHOST, 0.5), (MIRROR, 0)]],
+        {"ux": 0.5, "uy": -0.25, "uz": 0.75, "uz_period": 0.125, "t0": 0.0625},
+        sources=(np.array([5, 42], np.int64), np.array([0, 0], np.int32), np.array([10.0, 3.0]))),
+    "atmos19_two_species": lambda: ModelSpec(
+        "atmos", 2, 1 / 32, 2.0, [[1.0] * 3, [0.5] * 3],
+        [[(HELD, 1.0), (MIRROR, 0), (MIRROR, 0), (GHOST, -0.5), (MIRROR, 0), (MIRROR, 0)]] * 2,
+        {"ux": -0.5, "uy": 0.0, "uz": 1.0, "uz_period": 0.0625, "t0": 0.0},
+        sources=(np.array([21, 21], np.int64), np.array([0, 1], np.int32), np.array([10.0, 10.0])),
+        stencil=19),
 }
 
 
@@ -216,8 +267,8 @@ def test_oracle_matches_exact_expansion(oracle, case, steps):
     else:
         fields = [dyadic_field(rng) for _ in range(spec.ns)]
     state = [to_exact(f) for f in fields]
-    for _ in range(steps):
-        state = exact_step(spec, state)
+    for n in range(steps):
+        state = exact_step(spec, state, n)
     got = oracle.run(spec, fields, steps)
     for s in range(spec.ns):
         exact = to_array(state[s])

@@ -479,3 +479,134 @@ def test_reduce_mass_energy(oracle):
     m, e = oracle.reduce(f, h=0.5)
     assert abs(m - math.fsum(f.ravel()) * 0.125) < 1e-13
     assert abs(e - math.fsum((f * f).ravel()) * 0.125) < 1e-13
+
+
+# ------------------------------------------------------------------ P12
+# The rest of Table 1: the Turing model, redissolution in the front model
+# and the atmospheric wind.
+
+def turing_spec(stencil=7, dt=5e-4, h=6.2e-3, D=(5e-5, 5e-3)):
+    return ModelSpec("turing", 2, dt, h, [[D[0]] * 3, [D[1]] * 3], uniform_bc(2, MIRROR),
+                     {"alpha": 0.5, "beta": 0.09, "gamma": 26.0}, stencil=stencil)
+
+
+def turing_fixed_point(alpha=0.5, beta=0.09):
+    """Homogeneous steady state: c1 - c1^3 - c2 = 0 and c1 - alpha c2 - beta = 0
+    give alpha c1^3 + (1 - alpha) c1 - beta = 0 (one real root)."""
+    r = np.roots([alpha, 0.0, 1.0 - alpha, -beta])
+    c1 = float(np.real(r[np.abs(np.imag(r)) < 1e-12][0]))
+    return c1, c1 - c1**3
+
+
+@pytest.mark.parametrize("stencil", [7, 19])
+def test_turing_fixed_point_is_steady(oracle, stencil):
+    c1, c2 = turing_fixed_point()
+    shape = (4, 5, 6)
+    out = oracle.run(turing_spec(stencil), [np.full(shape, c1), np.full(shape, c2)], 40)
+    assert np.max(np.abs(out[0] - c1)) < 1e-14 and np.max(np.abs(out[1] - c2)) < 1e-14
+
+
+def laplacian_symbol(lams, h, stencil):
+    """Eigenvalue of the 7- or 19-point Laplacian (per unit coefficient) on a
+    separable mode whose 1D eigenvalues are lams; the 19-point one follows
+    from v(i-1) + v(i+1) = s v(i), s = 2 + h^2 lambda, and Eq. (4)'s weights."""
+    if stencil == 7:
+        return sum(lams)
+    s = [2.0 + h * h * l for l in lams]
+    return (-24.0 + 2.0 * sum(s) + s[0] * s[1] + s[0] * s[2] + s[1] * s[2]) / (6.0 * h * h)
+
+
+@pytest.mark.parametrize("stencil", [7, 19])
+def test_turing_linearised_mode(oracle, stencil):
+    """A small no-flux cosine mode about the steady state evolves by
+    I + dt (J + Lam diag(D1, D2)) per step: J the Jacobian of Table 1's
+    kinetics there, Lam the Laplacian's eigenvalue on the mode."""
+    spec = turing_spec(stencil)
+    c1, c2 = turing_fixed_point()
+    al, ga, dt, h = 0.5, 26.0, spec.dt, spec.h
+    shape = (6, 7, 8)
+    nz, ny, nx = shape
+    vx, lx = mode_1d(MIRROR, nx, 3, h)
+    vy, ly = mode_1d(MIRROR, ny, 2, h)
+    vz, lz = mode_1d(MIRROR, nz, 1, h)
+    mode = vz[:, None, None] * vy[None, :, None] * vx[None, None, :]
+    Lam = laplacian_symbol([lx, ly, lz], h, stencil)
+    J = np.array([[1.0 - 3.0 * c1 * c1, -1.0], [ga, -ga * al]])
+    G = np.eye(2) + dt * (J + Lam * np.diag([spec.K[0][0], spec.K[1][0]]))
+    eps, n = 1e-7, 30
+    out = oracle.run(spec, [c1 + eps * mode, c2 + 0.5 * eps * mode], n)
+    pred = np.linalg.matrix_power(G, n) @ np.array([1.0, 0.5])
+    proj = [np.sum((out[0] - c1) * mode) / np.sum(mode * mode) / eps,
+            np.sum((out[1] - c2) * mode) / np.sum(mode * mode) / eps]
+    assert np.allclose(proj, pred, rtol=2e-6, atol=0)
+    # diffusion matters here: the same map without it predicts otherwise
+    G0 = np.eye(2) + dt * J
+    assert not np.allclose(proj, np.linalg.matrix_power(G0, n) @ np.array([1.0, 0.5]), rtol=1e-3)
+
+
+@pytest.mark.parametrize("stencil", [7, 19])
+def test_front_redissolution_budget(oracle, stencil):
+    """With no-flux faces every Laplacian sums to zero, so one step changes
+    sum(B + C) by exactly -dt k2 sum(A C) (redissolution removes C, the
+    precipitation reaction moves B into C) and keeps sum(A - 2B - C)."""
+    shape = (5, 6, 7)
+    rng = np.random.default_rng(12)
+    A, B, Cc = (rng.uniform(0.1, 1.0, shape) for _ in range(3))
+    k1, k2, dt = 0.2, 0.3, 0.01
+    spec = ModelSpec("front_ch", 3, dt, 1.0, [[1.0] * 3, [0.5] * 3, [0.0] * 3], uniform_bc(3, MIRROR),
+                     {"k": k1, "k2": k2, "M": 1.0, "kappa": 1.0, "eps": 1.0, "gamma": 1.0},
+                     stencil=stencil)
+    out = oracle.run(spec, [A, B, Cc], 1)
+    d_bc = (out[1] + out[2]).sum() - (B + Cc).sum()
+    assert abs(d_bc - (-dt * k2 * np.sum(A * Cc))) < 1e-12 * abs(d_bc)
+    inv0 = (A - 2 * B - Cc).sum()
+    out = oracle.run(spec, [A, B, Cc], 6)
+    assert abs((out[0] - 2 * out[1] - out[2]).sum() - inv0) < 1e-12 * np.sum(np.abs(A) + 2 * B + Cc)
+
+
+def atmos_spec(shape, ux=0.0, uy=0.0, uz=0.0, T=0.0, t0=0.0, K=0.0, dt=0.5, h=1.0, bc=None,
+               sources=None, stencil=7):
+    return ModelSpec("atmos", 1, dt, h, [[K] * 3], bc if bc is not None else uniform_bc(1, MIRROR),
+                     {"ux": ux, "uy": uy, "uz": uz, "uz_period": T, "t0": t0},
+                     sources=sources, stencil=stencil)
+
+
+def test_atmos_unit_cfl_is_exact_shift_on_every_axis(oracle):
+    """|u| dt / h = 1 on one axis moves every value exactly one cell
+    downwind per step, whichever way the wind blows; the vertical wind of
+    Table 1, u_z sin(t / T), blows down at t = -pi T / 2 and up at +pi T / 2."""
+    shape = (5, 6, 7)
+    rng = np.random.default_rng(8)
+    c0 = rng.integers(-50, 50, shape).astype(float)
+    per = [(PERIODIC, 0.0)] * 6
+    out = oracle.run(atmos_spec(shape, ux=2.0, bc=[per]), [c0], 3)[0]
+    assert np.array_equal(out, np.roll(c0, 3, axis=2))
+    out = oracle.run(atmos_spec(shape, uy=-2.0, bc=[per]), [c0], 3)[0]
+    assert np.array_equal(out, np.roll(c0, -3, axis=1))
+    down = oracle.run(atmos_spec(shape, uz=2.0, T=1.0, t0=-math.pi / 2, bc=[per]), [c0], 1)[0]
+    assert np.array_equal(down, np.roll(c0, -1, axis=0))
+    up = oracle.run(atmos_spec(shape, uz=2.0, T=1.0, t0=math.pi / 2, bc=[per]), [c0], 1)[0]
+    assert np.array_equal(up, np.roll(c0, 1, axis=0))
+
+
+@pytest.mark.parametrize("stencil", [7, 19])
+def test_atmos_mass_budget(oracle, stencil):
+    """No-flux (mirror) faces: diffusion sums to zero and the upwind sums
+    telescope, so one step changes the total by exactly
+    dt (sum E - sum_d (u_d / h) sum over lines along d of (c_last - c_first)),
+    for either sign of each wind component."""
+    shape = (6, 7, 8)
+    rng = np.random.default_rng(31)
+    c0 = rng.uniform(0.0, 2.0, shape)
+    nz, ny, nx = shape
+    cells = np.array([(2 * ny + 3) * nx + 4, (4 * ny + 1) * nx + 6], np.int64)
+    rates = np.array([10.0, 2.5])
+    ux, uy, uz, T, t0, dt, h = 0.3, -0.2, 0.4, 3.0, 1.0, 0.05, 1.5
+    spec = atmos_spec(shape, ux, uy, uz, T, t0, K=0.7, dt=dt, h=h, stencil=stencil,
+                      sources=(cells, np.zeros(2, np.int32), rates))
+    out = oracle.run(spec, [c0], 1)[0]
+    u = [ux, uy, uz * math.sin(t0 / T)]
+    flux = sum(u[d] / h * np.sum(np.take(c0, -1, axis=2 - d) - np.take(c0, 0, axis=2 - d))
+               for d in range(3))
+    expect = dt * (rates.sum() - flux)
+    assert abs((out.sum() - c0.sum()) - expect) < 1e-12 * c0.sum()
