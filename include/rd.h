@@ -61,7 +61,9 @@ enum {
     RD_MODEL_DIFFUSION = 0,    /* R = 0; 1..4 independent species             */
     RD_MODEL_BRUSSELATOR = 1,  /* 2 species u, v: activator-inhibitor Turing   */
     RD_MODEL_FRONT_CH = 2,     /* 3 species A, B, C: front + Cahn-Hilliard     */
-    RD_MODEL_POLLUTANT = 3     /* 1..4 species: advection-diffusion + sources  */
+    RD_MODEL_POLLUTANT = 3,    /* 1..4 species: advection-diffusion + sources  */
+    RD_MODEL_TURING = 4,       /* 2 species: Table 1's activator-inhibitor     */
+    RD_MODEL_ATMOS = 5         /* 1..4 species: Table 1's atmospheric wind     */
 };
 
 /* boundary rule of one face of one species (section 4.1, Table 1) */
@@ -85,8 +87,9 @@ enum { RD_FACE_XLO = 0, RD_FACE_XHI, RD_FACE_YLO, RD_FACE_YHI, RD_FACE_ZLO, RD_F
  * param[]      model constants:
  *   DIFFUSION    none
  *   BRUSSELATOR  [0]=a [1]=b      R_u = a-(b+1)u+u^2 v,  R_v = b u - u^2 v
- *   FRONT_CH     [0]=k [1]=M [2]=kappa [3]=eps [4]=gamma
- *                r = k A B;  R_A = R_B = -r;  R_C = r + M Lap(mu),
+ *   FRONT_CH     [0]=k [1]=M [2]=kappa [3]=eps [4]=gamma [5]=k2 (>= 0)
+ *                r = k A B, q = k2 A C (redissolution);  R_A = -r - q,
+ *                R_B = -r;  R_C = r - q + M Lap(mu),
  *                mu = gamma C^3 - eps C - kappa Lap(C)  (Table 1, third row,
  *                with lambda = M, sigma = kappa).  mu uses mirror ghosts on
  *                every face.  diff[2] may be 0 (C moves by the CH term only).
@@ -94,8 +97,20 @@ enum { RD_FACE_XLO = 0, RD_FACE_XHI, RD_FACE_YLO, RD_FACE_YHI, RD_FACE_ZLO, RD_F
  *                [1]=k_AB   (linear transfer species 0 -> species 1)
  *                A_s = -u(z) (c_s(i) - c_s(i-1)) / h, first-order upwind
  *                along +x with u(z) >= 0 (section 4.1, Table 1 fourth row)
+ *   TURING       [0]=alpha [1]=beta [2]=gamma   (Table 1, second row)
+ *                R_1 = c_1 - c_1^3 - c_2,  R_2 = gamma (c_1 - alpha c_2 - beta)
+ *   ATMOS        [0]=u_x [1]=u_y [2]=u_z amplitude [3]=T (>= 0) [4]=t_0
+ *                (Table 1, last row) a wind uniform in space, u_z(t) =
+ *                u_z sin(t / T) (u_z itself when T = 0), t = t_0 + n dt at
+ *                the n-th step since rd_set_model; every axis is upwinded
+ *                by the sign of its component, A_s = sum_d of u_d (c[-e_d]
+ *                - c) / h (u_d > 0) or u_d (c - c[+e_d]) / h (u_d < 0);
+ *                species are independent; point sources as below.  The
+ *                step index lives on the device, so graph replays see the
+ *                time advance.  Not blocked in time (RD_KERNEL_LDS2) and not
+ *                batched.
  * wind         POLLUTANT: nz host doubles u(z) >= 0, read during the call.
- * src_*        POLLUTANT: nsrc point sources, host arrays read during the
+ * src_*        POLLUTANT, ATMOS: nsrc point sources, host arrays read during the
  *              call: linear cell index (k*ny + j)*nx + i, species, rate
  *              (added to dc/dt; duplicates add up).
  * stencil      7 (or 0): the 7-point Laplacian with per-axis coefficients;
@@ -107,7 +122,8 @@ enum { RD_FACE_XLO = 0, RD_FACE_XHI, RD_FACE_YLO, RD_FACE_YHI, RD_FACE_ZLO, RD_F
  *              not batched.
  * dt           time step; rd_set_model rejects a dt outside the stable range
  *              (RD_EUNSTABLE): per species dt*(2*sum_d K_d/h^2 + max u/h) <= 1
- *              (19-point: dt*(4 D/h^2 + max u/h) <= 1), and for FRONT_CH also
+ *              (19-point: dt*(4 D/h^2 + max u/h) <= 1; for ATMOS, max u is
+ *              |u_x| + |u_y| + |u_z|), and for FRONT_CH also
  *              dt*M*(kappa*L^2 + |eps|*L) <= 1 with L = 12/h^2 (19-point:
  *              16/(3h^2)), the largest magnitude of the discrete Laplacian.
  */

@@ -28,6 +28,15 @@ constexpr int SLACK = 1024;      // elements after each buffer: overshoot of the
 #define RD_NT_STORE 0
 #endif
 
+// Step clock of a model with a time-dependent wind: the step index n of the
+// state it belongs to and u_z(t_n)/h.  A grid keeps two, one per buffer
+// parity; the step reading one writes the other.
+struct StepClock {
+    long long n;
+    float uzh;
+    int pad;
+};
+
 struct StepArgs {
     int nx, ny, nz;
     int pitch;                    // elements per padded row (multiple of 64)
@@ -50,7 +59,16 @@ struct StepArgs {
     int s19;                      // 19-point Laplacian: kx = ky = kz = K/(6h^2)
     int tiles_x, tiles_y, chunks_z, cz;   // tiled decomposition
     int zfast;                    // slab enumeration: z chunk fastest
+    // time-dependent wind (atmospheric model): u_z(t) = wamp sin(t / wper)
+    // (wamp when wper = 0), t = t0 + n dt64
+    const StepClock* clk_in;      // clock of this step's input state
+    StepClock* clk_out;           // clock of its output state
+    int clk_pass;                 // this pass advances the clock
+    double t0, dt64, wamp, wper, inv_h;
 };
+
+// How a model's cell function gets its per-plane wind argument.
+enum { WIND_NONE = 0, WIND_PLANE = 1, WIND_CLOCK = 2 };
 
 // Tile coordinates of logical tile t: x, then y, then z chunk, or (zfast) z
 // chunk, then x, then y.
@@ -218,10 +236,18 @@ __device__ __forceinline__ float lap19(const Nb19& n, float k6) {
 __device__ __forceinline__ float lap(const Nb& n, float kx, float ky, float kz) { return lap7(n, kx, ky, kz); }
 __device__ __forceinline__ float lap(const Nb19& n, float kx, float, float) { return lap19(n, kx); }
 
+// First-order upwind form of -u dc/dx along one axis, uh = u/h: the
+// difference on the side the wind comes from, u (c[-1] - c) / h for u > 0
+// and u (c - c[+1]) / h for u < 0.
+__device__ __forceinline__ float upwind(float uh, float cm, float cp, float c, float rate) {
+    return __fmaf_rn(uh, uh > 0.f ? cm - c : c - cp, rate);
+}
+
 // Pure diffusion of NS independent species (Table 1, first row).
 template <int NS> struct Diffusion {
     static constexpr int NF = NS, NO = NS;
     static constexpr bool SOURCES = false;
+    static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
     template <class NB>
@@ -237,6 +263,7 @@ template <int NS> struct Diffusion {
 struct Brusselator {
     static constexpr int NF = 2, NO = 2;
     static constexpr bool SOURCES = false;
+    static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
     template <class NB>
@@ -259,6 +286,7 @@ struct Brusselator {
 struct ChemPotential {
     static constexpr int NF = 1, NO = 1;
     static constexpr bool SOURCES = false;
+    static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return true; }
     template <class NB>
@@ -270,12 +298,14 @@ struct ChemPotential {
     }
 };
 
-// Front with precipitation: A + B -> C at rate k, C moves by M Lap(mu).
+// Front with precipitation: A + B -> C at rate k, redissolution A + C at
+// rate k2 (removes A and C), C moves by M Lap(mu).
 // Fields 0..2 = A, B, C (storage type), field 3 = mu (FP32, mirror faces).
-// p[0]=k p[1]=M; kx[3]=ky[3]=kz[3]=1/h^2.
+// p[0]=k p[1]=M p[5]=k2; kx[3]=ky[3]=kz[3]=1/h^2.
 struct FrontCH {
     static constexpr int NF = 4, NO = 3;
     static constexpr bool SOURCES = false;
+    static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int f) { return f == 3; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
     template <class NB>
@@ -283,13 +313,14 @@ struct FrontCH {
                                                 bool, const float (&)[3], float (&o)[3]) {
         const float A = n[0].c, B = n[1].c, C = n[2].c;
         const float r = (a.p[0] * A) * B;
+        const float q = (a.p[5] * A) * C;
         const float la = lap(n[0], a.kx[0], a.ky[0], a.kz[0]);
         const float lb = lap(n[1], a.kx[1], a.ky[1], a.kz[1]);
         const float lc = lap(n[2], a.kx[2], a.ky[2], a.kz[2]);
         const float lmu = lap(n[3], a.kx[3], a.ky[3], a.kz[3]);
-        o[0] = __fmaf_rn(a.dt, la - r, A);
+        o[0] = __fmaf_rn(a.dt, (la - r) - q, A);
         o[1] = __fmaf_rn(a.dt, lb - r, B);
-        o[2] = __fmaf_rn(a.dt, __fmaf_rn(a.p[1], lmu, lc + r), C);
+        o[2] = __fmaf_rn(a.dt, __fmaf_rn(a.p[1], lmu, lc + r) - q, C);
     }
 };
 
@@ -300,6 +331,7 @@ struct FrontCH {
 template <int NS, bool COUPLED> struct Pollutant {
     static constexpr int NF = NS, NO = NS;
     static constexpr bool SOURCES = true;
+    static constexpr int WIND = WIND_PLANE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
     template <class NB>
@@ -319,6 +351,78 @@ template <int NS, bool COUPLED> struct Pollutant {
         }
     }
 };
+
+// Activator-inhibitor kinetics of Table 1 (second row):
+// R_1 = c_1 - c_1^3 - c_2,  R_2 = gamma (c_1 - alpha c_2 - beta).
+// p[0]=alpha p[1]=beta p[2]=gamma.
+struct Turing {
+    static constexpr int NF = 2, NO = 2;
+    static constexpr bool SOURCES = false;
+    static constexpr int WIND = WIND_NONE;
+    static __host__ __device__ constexpr bool f32_field(int) { return false; }
+    static __host__ __device__ constexpr bool f32_out(int) { return false; }
+    template <class NB>
+    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[2], float,
+                                                bool, const float (&)[2], float (&o)[2]) {
+        const float u = n[0].c, v = n[1].c;
+        const float r1 = (u - (u * u) * u) - v;
+        const float r2 = a.p[2] * (__fmaf_rn(-a.p[0], v, u) - a.p[1]);
+        const float l1 = lap(n[0], a.kx[0], a.ky[0], a.kz[0]);
+        const float l2 = lap(n[1], a.kx[1], a.ky[1], a.kz[1]);
+        o[0] = __fmaf_rn(a.dt, l1 + r1, u);
+        o[1] = __fmaf_rn(a.dt, l2 + r2, v);
+    }
+};
+
+// Atmospheric advection-diffusion of NS independent species (Table 1, last
+// row): a wind uniform in space, u_x and u_y fixed (p[0] = u_x/h, p[1] =
+// u_y/h), u_z(t)/h from the step clock (the cell's wind argument), each
+// axis upwinded by the sign of its component, plus point emissions.
+template <int NS> struct Atmos {
+    static constexpr int NF = NS, NO = NS;
+    static constexpr bool SOURCES = true;
+    static constexpr int WIND = WIND_CLOCK;
+    static __host__ __device__ constexpr bool f32_field(int) { return false; }
+    static __host__ __device__ constexpr bool f32_out(int) { return false; }
+    template <class NB>
+    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[NF], float uzh,
+                                                bool has_e, const float (&e)[NO], float (&o)[NO]) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const float c = n[s].c;
+            float rate = lap(n[s], a.kx[s], a.ky[s], a.kz[s]);
+            rate = upwind(a.p[0], n[s].xm, n[s].xp, c, rate);
+            rate = upwind(a.p[1], n[s].ym, n[s].yp, c, rate);
+            rate = upwind(uzh, n[s].zm, n[s].zp, c, rate);
+            if (has_e) rate = rate + e[s];
+            o[s] = __fmaf_rn(a.dt, rate, c);
+        }
+    }
+};
+
+// The wind argument of a model's cell function on plane z.
+template <class M>
+__device__ __forceinline__ float plane_wind(const StepArgs& a, int z) {
+    if constexpr (M::WIND == WIND_PLANE) return gload_ptr<float>(a.wind_h)[z];
+    else if constexpr (M::WIND == WIND_CLOCK) return gload_ptr<StepClock>(a.clk_in)->uzh;
+    else return 0.f;
+}
+
+// One thread of the clock pass writes the clock of the step's output state:
+// n + 1 and u_z(t_{n+1})/h, in FP64 as the time is formed.
+template <class M>
+__device__ __forceinline__ void tick_clock(const StepArgs& a, bool first_thread) {
+    if constexpr (M::WIND == WIND_CLOCK) {
+        if (first_thread && a.clk_pass) {
+            const long long n = gload_ptr<StepClock>(a.clk_in)->n + 1;
+            const double t = a.t0 + double(n) * a.dt64;
+            const double u = a.wper != 0.0 ? a.wamp * sin(t / a.wper) : a.wamp;
+            StepClock* out = gstore_ptr<StepClock>(a.clk_out);
+            out->n = n;
+            out->uzh = float(u * a.inv_h);
+        }
+    }
+}
 
 // ------------------------------------------------------------ ghost logic
 
@@ -447,6 +551,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     const int z = blockIdx.z;
+    tick_clock<M>(a, (blockIdx.x | blockIdx.y | blockIdx.z | threadIdx.x) == 0);
     if (x >= a.nx || y >= a.ny) return;
     std::conditional_t<S19, Nb19, Nb> n[M::NF];
 #pragma unroll
@@ -457,7 +562,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
         const int r = z * a.ny + y;
         em = cell_sources<M::NO>(a, x, gload_ptr<int>(a.src_row)[r], gload_ptr<int>(a.src_row)[r + 1]);
     }
-    const float uh = M::SOURCES ? gload_ptr<float>(a.wind_h)[z] : 0.f;
+    const float uh = plane_wind<M>(a, z);
     float o[M::NO];
     M::cell(a, n, uh, em.any, em.e, o);
     const long long idx = (long long)z * a.plane + (long long)y * a.pitch + x;
@@ -646,7 +751,7 @@ __device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64
                 dn[f][i] = h[f][NH - 1][i];
             }
     }
-    const float uh = M::SOURCES ? gload_ptr<float>(a.wind_h)[z] : 0.f;
+    const float uh = plane_wind<M>(a, z);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
         const int y = y0 + r;
@@ -872,7 +977,7 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
                         dn[f][i] = H[f][k - 1][NH - 1][i];
                     }
             }
-            const float uh = M::SOURCES ? a.wind_h[z] : 0.f;
+            const float uh = plane_wind<M>(a, z);
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const int y = y0 + r;
@@ -1029,6 +1134,7 @@ __device__ __forceinline__ void block_step(const StepArgs& a, int t, BlockLds<M,
 template <class M, class S, int VX, int RY, int W, int CZ>
 __global__ __launch_bounds__(64 * W) void block_kernel(const StepArgs* __restrict__ pa) {
     __shared__ BlockLds<M, W, 64 * VX> sm;
+    tick_clock<M>(*pa, (blockIdx.x | threadIdx.x) == 0);
     block_step<M, S, VX, RY, W, CZ>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
@@ -1205,6 +1311,7 @@ __device__ __forceinline__ void tile_step(const StepArgs& a, int t, BlockLds<M, 
 template <class M, class S, int VX, int RY, int W, int PF>
 __global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restrict__ pa) {
     __shared__ BlockLds<M, W, 64 * VX> sm;
+    tick_clock<M>(*pa, (blockIdx.x | threadIdx.x) == 0);
     tile_step<M, S, VX, RY, W, PF>(*pa, xcd_tile(blockIdx.x, gridDim.x), sm);
 }
 
@@ -1384,7 +1491,7 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
             {
                 // scalar loads of this plane's wind and source range go out
                 // before the barrier so their latency hides behind it
-                const float uh = M::SOURCES ? gload_ptr<float>(a.wind_h)[z] : 0.f;
+                const float uh = plane_wind<M>(a, z);
                 bool plane_src = false;
                 if (M::SOURCES) {
                     const int pa0 = gload_ptr<int>(a.src_row)[z * a.ny];
@@ -1502,6 +1609,7 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds_kernel(const StepArgs* __re
     static_assert(R::FITS && BY % WC == 0, "ring shape does not fit");
     __shared__ __attribute__((aligned(16))) float ring[D][R::SLOT];
     const StepArgs& a = *pa;
+    tick_clock<M>(a, (blockIdx.x | threadIdx.x) == 0);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const TileXYZ tc = tile_coords(a, xcd_tile(blockIdx.x, gridDim.x));
     const int yb = tc.y * BY;
@@ -1830,6 +1938,7 @@ template <class M, int NCH, int BY, int WC, int D>
 __global__ __launch_bounds__(64 * (WC + 1)) void lds2_kernel(const StepArgs* __restrict__ pa) {
     using R = Lds2Ring<M::NF, NCH, BY, D>;
     static_assert(R::FITS, "ring shape does not fit");
+    static_assert(M::WIND != WIND_CLOCK, "a clocked wind is not blocked in time");
     __shared__ __attribute__((aligned(16))) float iring[D * R::ISLOT];
     __shared__ __attribute__((aligned(16))) float mring[4 * R::MSLOT];
     const StepArgs& a = *pa;

@@ -68,6 +68,11 @@ PassGroups pass_groups(int model, int ns) {
         add(0, ns >= 2 ? 2 : 1, ns >= 2 ? PM_POLL2 : PM_POLL1);
         if (ns >= 3) add(2, ns - 2, ns == 3 ? PM_POLL1 : PM_POLL2U);
         break;
+    case RD_MODEL_TURING: add(0, 2, PM_TURING); break;
+    case RD_MODEL_ATMOS:   // independent species, at most two per pass
+        add(0, ns >= 2 ? 2 : 1, ns >= 2 ? PM_ATMOS2 : PM_ATMOS1);
+        if (ns >= 3) add(2, ns - 2, ns == 3 ? PM_ATMOS1 : PM_ATMOS2);
+        break;
     default: break;
     }
     return p;
@@ -120,7 +125,7 @@ int lds2_cfg_index(int nch, int by, int wc, int d) {
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h, const StepArgs* d,
                        long long blocks, hipStream_t s) {
     const bool diff = pm <= PM_DIFF4;
-    const bool react = pm == PM_BRUSS || pm == PM_CHMU || pm == PM_FRONT;
+    const bool react = pm == PM_BRUSS || pm == PM_CHMU || pm == PM_FRONT || pm == PM_TURING;
     switch (storage) {
     case ST_F32:
         return diff ? launch_pass_f32_diff(pm, kernel, cfg, h, d, blocks, s)
@@ -179,6 +184,7 @@ struct rd_grid {
     int* d_src_x = nullptr;
     int* d_src_sp = nullptr;
     float* d_src_rate = nullptr;
+    StepClock* d_clock = nullptr;      // [parity]: step index and wind of that state
     int npass = 0;
     int pass_pm[2] = {-1, -1};
     StepArgs args[2][2];               // [input parity][pass], host copy
@@ -497,6 +503,12 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
     case RD_MODEL_FRONT_CH:
         if (ns != 3) return fail(RD_EINVAL, "the front model has 3 species");
         break;
+    case RD_MODEL_TURING:
+        if (ns != 2) return fail(RD_EINVAL, "the Turing model has 2 species");
+        break;
+    case RD_MODEL_ATMOS:
+        if (ns < 1 || ns > RD_MAX_SPECIES) return fail(RD_EINVAL, "nspecies must be 1..4");
+        break;
     default: return fail(RD_EINVAL, "unknown model");
     }
     if (!(m->dt > 0.0) || !is_finite(m->dt)) return fail(RD_EINVAL, "dt must be a positive finite number");
@@ -515,7 +527,11 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
             if ((m->bc_kind[s][2 * a] == RD_BC_PERIODIC) != (m->bc_kind[s][2 * a + 1] == RD_BC_PERIODIC))
                 return fail(RD_EINVAL, "a periodic axis needs periodic on both faces");
     }
-    double umax = 0.0;
+    double umax = 0.0;   // largest sum over axes of |u_d|
+    if (m->model == RD_MODEL_ATMOS) {
+        if (m->param[3] < 0.0) return fail(RD_EINVAL, "the period of the vertical wind must be >= 0");
+        umax = std::fabs(m->param[0]) + std::fabs(m->param[1]) + std::fabs(m->param[2]);
+    }
     if (m->model == RD_MODEL_POLLUTANT) {
         if (!m->wind || m->nwind != nz) return fail(RD_EINVAL, "pollutant model needs nz wind values");
         for (int64_t k = 0; k < nz; ++k) {
@@ -523,6 +539,9 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
                 return fail(RD_EINVAL, "wind speeds must be finite and >= 0 (upwind along +x)");
             umax = std::max(umax, m->wind[k]);
         }
+        if (m->param[0] < 0.0 || m->param[1] < 0.0) return fail(RD_EINVAL, "decay and k_AB must be >= 0");
+    }
+    if (m->model == RD_MODEL_POLLUTANT || m->model == RD_MODEL_ATMOS) {
         if (m->nsrc < 0 || (m->nsrc > 0 && (!m->src_cell || !m->src_species || !m->src_rate)))
             return fail(RD_EINVAL, "bad source arrays");
         const int64_t N = nx * ny * nz;
@@ -532,9 +551,8 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
                 return fail(RD_EINVAL, "source species out of range");
             if (!is_finite(m->src_rate[q])) return fail(RD_EINVAL, "source rates must be finite");
         }
-        if (m->param[0] < 0.0 || m->param[1] < 0.0) return fail(RD_EINVAL, "decay and k_AB must be >= 0");
     } else if (m->nsrc != 0) {
-        return fail(RD_EINVAL, "point sources need the pollutant model");
+        return fail(RD_EINVAL, "point sources need the pollutant or atmospheric model");
     }
     if (m->stencil != 0 && m->stencil != 7 && m->stencil != 19) return fail(RD_EINVAL, "stencil must be 7 or 19");
     const bool s19 = m->stencil == 19;
@@ -555,6 +573,7 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
     if (m->model == RD_MODEL_FRONT_CH) {
         const double M = m->param[1], kappa = m->param[2], eps = m->param[3];
         if (M < 0.0 || kappa < 0.0) return fail(RD_EINVAL, "M and kappa must be >= 0");
+        if (m->param[5] < 0.0) return fail(RD_EINVAL, "k2 must be >= 0");
         // largest magnitude of the discrete Laplacian: 7-point 12/h^2, 19-point 32/(6h^2)
         const double lam = s19 ? 16.0 / (3.0 * h2) : 12.0 / h2;
         if (m->dt * M * (kappa * lam * lam + std::fabs(eps) * lam) > 1.0 + 1e-12)
@@ -607,6 +626,7 @@ extern "C" int rd_create_grid(int64_t nx, int64_t ny, int64_t nz, int32_t nspeci
                 return cleanup(RD_EDEVICE, "hipMemsetAsync failed");
         }
     if (hipMalloc(&g->d_args, sizeof(g->args)) != hipSuccess ||
+        hipMalloc(&g->d_clock, 2 * sizeof(StepClock)) != hipSuccess ||
         hipMalloc(&g->d_part, 2 * kRedBlocks * sizeof(double)) != hipSuccess ||
         hipMalloc(&g->d_red, 2 * sizeof(double)) != hipSuccess)
         return cleanup(RD_ENOMEM, "hipMalloc of grid work buffers failed");
@@ -625,6 +645,7 @@ extern "C" int rd_destroy_grid(rd_grid* g) {
         for (auto& b : row) (void)hipFree(b);
     (void)hipFree(g->aux);
     (void)hipFree(g->d_args);
+    (void)hipFree(g->d_clock);
     (void)hipFree(g->d_part);
     (void)hipFree(g->d_red);
     free_model_arrays(g);
@@ -644,10 +665,12 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
     const double ih2 = 1.0 / (g->h * g->h);
     const int ns = g->ns;
 
-    // Pollutant wind and sources (sorted by row, duplicates merged in FP64).
-    if (m->model == RD_MODEL_POLLUTANT) {
-        std::vector<float> wh(g->nz);
-        for (int64_t k = 0; k < g->nz; ++k) wh[k] = float(m->wind[k] / g->h);
+    // Pollutant wind and the sources of both source models (sorted by row,
+    // duplicates merged in FP64).
+    if (m->model == RD_MODEL_POLLUTANT || m->model == RD_MODEL_ATMOS) {
+        std::vector<float> wh(g->nz, 0.f);
+        if (m->model == RD_MODEL_POLLUTANT)
+            for (int64_t k = 0; k < g->nz; ++k) wh[k] = float(m->wind[k] / g->h);
         std::map<std::tuple<int64_t, int64_t, int>, double> merged;   // (row, x, species)
         for (int64_t q = 0; q < m->nsrc; ++q) {
             const int64_t c = m->src_cell[q];
@@ -682,6 +705,17 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
         RD_HIP(hipMalloc(&g->aux, g->elems * sizeof(float)));
         RD_HIP(hipMemset(g->aux, 0, g->elems * sizeof(float)));
     }
+    // The clock starts at step 0 in both parities (the state now held is
+    // step 0 whichever buffer holds it).
+    {
+        StepClock c0[2] = {};
+        if (m->model == RD_MODEL_ATMOS) {
+            const double t0 = m->param[4];
+            const double u = m->param[3] != 0.0 ? m->param[2] * std::sin(t0 / m->param[3]) : m->param[2];
+            c0[0].uzh = c0[1].uzh = float(u * (1.0 / g->h));
+        }
+        RD_HIP(hipMemcpy(g->d_clock, c0, sizeof(c0), hipMemcpyHostToDevice));
+    }
 
     const PassGroups groups = pass_groups(m->model, ns);
     // 19-point form: the kernels take K/(6h^2) as their coefficient
@@ -703,6 +737,16 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
             a.src_x = g->d_src_x;
             a.src_sp = g->d_src_sp;
             a.src_rate = g->d_src_rate;
+            a.clk_in = g->d_clock + par;
+            a.clk_out = g->d_clock + (par ^ 1);
+            a.clk_pass = k == 0 ? 1 : 0;
+            if (m->model == RD_MODEL_ATMOS) {
+                a.t0 = m->param[4];
+                a.dt64 = m->dt;
+                a.wamp = m->param[2];
+                a.wper = m->param[3];
+                a.inv_h = 1.0 / g->h;
+            }
         }
         if (m->model == RD_MODEL_FRONT_CH) {
             // pass 0: mu of C with C's faces; pass 1: update A, B, C.
@@ -732,6 +776,7 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
                 a.p[2] = float(m->param[2]);   // kappa
                 a.p[3] = float(m->param[3]);   // eps
                 a.p[4] = float(m->param[4]);   // gamma
+                a.p[5] = float(m->param[5]);   // k2
             }
         } else {
             // one pass per group of species that share a term (see pass_groups)
@@ -756,6 +801,13 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
                 } else if (m->model == RD_MODEL_POLLUTANT) {
                     a.p[0] = float(m->param[0]);
                     a.p[1] = float(m->param[1]);
+                } else if (m->model == RD_MODEL_TURING) {
+                    a.p[0] = float(m->param[0]);   // alpha
+                    a.p[1] = float(m->param[1]);   // beta
+                    a.p[2] = float(m->param[2]);   // gamma
+                } else if (m->model == RD_MODEL_ATMOS) {
+                    a.p[0] = float(m->param[0] / g->h);   // u_x / h
+                    a.p[1] = float(m->param[1] / g->h);   // u_y / h
                 }
             }
         }
@@ -981,6 +1033,11 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     }
     const int cur0 = g->cur;
     const rd_plan user = g->plan;
+    StepClock clk0[2];
+    if (hipMemcpy(clk0, g->d_clock, sizeof(clk0), hipMemcpyDeviceToHost) != hipSuccess) {
+        release();
+        return fail(RD_EDEVICE, "clock copy failed");
+    }
 
     std::vector<rd_plan> cands;
     rd_plan d{};
@@ -1079,6 +1136,8 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
                 rc = fail(RD_EDEVICE, "restore failed");
                 break;
             }
+        if (rc == RD_OK && hipMemcpy(g->d_clock, clk0, sizeof(clk0), hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(RD_EDEVICE, "clock restore failed");
         g->cur = cur0;
         if (rc) break;
     }
@@ -1087,6 +1146,8 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     for (int s = 0; s < g->ns && rc == RD_OK; ++s)
         if (hipMemcpy(g->buf[cur0][s], snap[s], bytes, hipMemcpyDeviceToDevice) != hipSuccess)
             rc = fail(RD_EDEVICE, "restore failed");
+    if (rc == RD_OK && hipMemcpy(g->d_clock, clk0, sizeof(clk0), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(RD_EDEVICE, "clock restore failed");
     g->cur = cur0;
     release();
     if (rc == RD_OK) {

@@ -18,6 +18,9 @@ enum PassModel {
     PM_POLL1,       // one pollutant
     PM_POLL2,       // the coupled pair (transfer from the first to the second)
     PM_POLL2U,      // two uncoupled pollutants
+    PM_TURING,      // activator-inhibitor (Table 1, second row)
+    PM_ATMOS1,      // one species under the atmospheric wind
+    PM_ATMOS2,      // two species under the atmospheric wind
     PM_COUNT
 };
 
@@ -67,34 +70,38 @@ constexpr unsigned bits(std::initializer_list<int> l) {
 // footprints.  The chemical-potential pass covers every shape of the front
 // update so both passes of a step share one plan.
 constexpr unsigned cfg_mask(int storage, int pm) {
-    const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
-    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2 || pm == PM_POLL2U;
+    const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS || pm == PM_TURING;
+    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2 || pm == PM_POLL2U ||
+                        pm == PM_ATMOS1 || pm == PM_ATMOS2;
     if (storage == ST_F32)
         return light ? bits({0, 1, 2, 3, 4, 5, 6}) : medium ? bits({0, 1, 2, 3, 5, 6}) : bits({3, 6});
     if (storage == ST_BF16) return light ? bits({0, 1, 2, 3, 6}) : bits({3, 6});
     return light ? bits({1, 2, 3, 6}) : bits({3, 6});
 }
 constexpr unsigned block_mask(int storage, int pm) {
-    const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS;
-    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2 || pm == PM_POLL2U;
+    const bool light = pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_BRUSS || pm == PM_TURING;
+    const bool medium = pm == PM_DIFF2 || pm == PM_POLL1 || pm == PM_POLL2 || pm == PM_POLL2U ||
+                        pm == PM_ATMOS1 || pm == PM_ATMOS2;
     if (storage == ST_F32) {
         if (light) return bits({0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12});
         if (medium) return bits({0, 1, 2, 5, 6, 7, 8, 11});
         return bits({0, 2, 5, 6, 7, 8, 11});
     }
     if (storage == ST_BF16) {
-        if (pm == PM_DIFF1 || pm == PM_BRUSS) return bits({0, 1, 2, 3, 5});
+        if (pm == PM_DIFF1 || pm == PM_BRUSS || pm == PM_TURING) return bits({0, 1, 2, 3, 5});
         if (pm == PM_CHMU || pm == PM_FRONT) return bits({0, 2, 5, 6});
         return bits({0, 5});
     }
-    if (pm == PM_DIFF1 || pm == PM_BRUSS) return bits({0, 1, 5});
+    if (pm == PM_DIFF1 || pm == PM_BRUSS || pm == PM_TURING) return bits({0, 1, 5});
     return bits({0, 5});
 }
 
 // Stencil fields a pass model reads.
 constexpr int pm_fields(int pm) {
-    return pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_POLL1 ? 1
-         : pm == PM_DIFF2 || pm == PM_BRUSS || pm == PM_POLL2 || pm == PM_POLL2U ? 2
+    return pm == PM_DIFF1 || pm == PM_CHMU || pm == PM_POLL1 || pm == PM_ATMOS1 ? 1
+         : pm == PM_DIFF2 || pm == PM_BRUSS || pm == PM_POLL2 || pm == PM_POLL2U || pm == PM_TURING ||
+                   pm == PM_ATMOS2
+             ? 2
          : pm == PM_DIFF3 ? 3 : 4;
 }
 

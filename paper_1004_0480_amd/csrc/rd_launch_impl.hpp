@@ -28,6 +28,9 @@ template <> struct PmOf<FrontCH> { static constexpr int v = PM_FRONT; };
 template <> struct PmOf<Pollutant<1, false>> { static constexpr int v = PM_POLL1; };
 template <> struct PmOf<Pollutant<2, true>> { static constexpr int v = PM_POLL2; };
 template <> struct PmOf<Pollutant<2, false>> { static constexpr int v = PM_POLL2U; };
+template <> struct PmOf<Turing> { static constexpr int v = PM_TURING; };
+template <> struct PmOf<Atmos<1>> { static constexpr int v = PM_ATMOS1; };
+template <> struct PmOf<Atmos<2>> { static constexpr int v = PM_ATMOS2; };
 
 template <class M, bool S19>
 hipError_t run_direct(const StepArgs& h, const StepArgs* d, hipStream_t s) {
@@ -146,11 +149,14 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
     case PM_BRUSS: return run_model<Brusselator>(kernel, cfg, h, d, blocks, s);
     case PM_CHMU: return run_model<ChemPotential>(kernel, cfg, h, d, blocks, s);
     case PM_FRONT: return run_model<FrontCH>(kernel, cfg, h, d, blocks, s);
+    case PM_TURING: return run_model<Turing>(kernel, cfg, h, d, blocks, s);
 #endif
 #ifdef RD_GROUP_POLL
     case PM_POLL1: return run_model<Pollutant<1, false>>(kernel, cfg, h, d, blocks, s);
     case PM_POLL2: return run_model<Pollutant<2, true>>(kernel, cfg, h, d, blocks, s);
     case PM_POLL2U: return run_model<Pollutant<2, false>>(kernel, cfg, h, d, blocks, s);
+    case PM_ATMOS1: return run_model<Atmos<1>>(kernel, cfg, h, d, blocks, s);
+    case PM_ATMOS2: return run_model<Atmos<2>>(kernel, cfg, h, d, blocks, s);
 #endif
     default: return hipErrorNotSupported;
     }

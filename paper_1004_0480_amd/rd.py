@@ -19,15 +19,18 @@ MAX_SPECIES = 4
 OK, EINVAL, ENOMEM, EUNSTABLE, ESTATE, EDEVICE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 F32, BF16, F16, F64 = 0, 1, 2, 3
 STORAGE = {"f32": F32, "bf16": BF16, "f16": F16}
-MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3}
+MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3, "turing": 4, "atmos": 5}
 BC = {"mirror": 0, "periodic": 1, "ghost": 2, "held": 3}
 KERNEL = {"auto": 0, "direct": 1, "tiled": 2, "block": 3, "lds": 4, "lds2": 5}
 PARAMS = {
     "diffusion": (),
     "brusselator": ("a", "b"),
-    "front_ch": ("k", "M", "kappa", "eps", "gamma"),
+    "front_ch": ("k", "M", "kappa", "eps", "gamma", "k2"),
     "pollutant": ("decay", "kab"),
+    "turing": ("alpha", "beta", "gamma"),
+    "atmos": ("ux", "uy", "uz", "uz_period", "t0"),
 }
+OPTIONAL_PARAMS = ("k2", "uz_period", "t0")   # 0 when a spec leaves them out
 
 
 class RDError(RuntimeError):
@@ -149,7 +152,7 @@ def model_desc(spec, shape) -> Tuple[ModelDesc, list]:
             m.bc_kind[s][f] = BC[kind]
             m.bc_value[s][f] = float(val)
     for slot, name in enumerate(PARAMS[spec.model]):
-        m.param[slot] = float(spec.params[name])
+        m.param[slot] = float(spec.params.get(name, 0.0) if name in OPTIONAL_PARAMS else spec.params[name])
     keep = []
     if spec.wind is not None:
         wind = np.ascontiguousarray(spec.wind, dtype=np.float64)

@@ -143,3 +143,37 @@ def test_grid_bytes():
     # rows are padded to 64 elements
     assert rd.grid_bytes((8, 8, 33), 1, "f32") == rd.grid_bytes((8, 8, 64), 1, "f32")
     assert rd.grid_bytes((0, 8, 8), 1, "f32") == 0
+
+
+def test_validate_table1_workloads():
+    """The paper's Table 1 problems at 192^3 (19-point) pass the checks; each
+    is rejected past its own stability bound or with a bad parameter."""
+    for name in ("t1_diffusion192", "t1_turing192", "t1_front192", "t1_atmos192"):
+        spec = W.make_workload(name, shape=(4, 4, 4)).spec
+        assert spec.stencil == 19
+        assert rd.validate_model(W.make_workload(name, shape=(8, 9, 10)).spec, (8, 9, 10)) == rd.OK, name
+        if name != "t1_atmos192":
+            assert rd.validate_model(spec, W.DEFAULT_SHAPES[name]) == rd.OK, (name, rd.last_error())
+    shape = W.DEFAULT_SHAPES["t1_atmos192"]
+    a = W.atmos_spec(shape)
+    assert rd.validate_model(a, shape) == rd.OK
+    # 5 * (4 * 100 / 100^2 + (5 + 1 + 5) / 100) = 0.75; at dt = 7: 1.05
+    a.dt = 7.0
+    assert rd.validate_model(a, shape) == rd.EUNSTABLE
+    a = W.atmos_spec(shape)
+    a.params["uz_period"] = -1.0
+    assert rd.validate_model(a, shape) == rd.EINVAL
+    t = W.turing_spec()
+    t.dt = 2e-3                                           # 4 D2 dt / h^2 = 1.04
+    assert rd.validate_model(t, (8, 8, 8)) == rd.EUNSTABLE
+    f = W.paper_front_spec()
+    f.params["k2"] = -0.1
+    assert rd.validate_model(f, (8, 8, 8)) == rd.EINVAL
+    t = W.turing_spec()
+    t.ns = 3
+    t.K.append([1e-5] * 3)
+    t.bc.append(t.bc[0])
+    assert rd.validate_model(t, (8, 8, 8)) == rd.EINVAL
+    d = W.make_workload("t1_diffusion192", shape=(8, 8, 8)).spec
+    d.sources = (np.array([3], np.int64), np.array([0], np.int32), np.array([1.0]))
+    assert rd.validate_model(d, (8, 8, 8)) == rd.EINVAL   # sources need a source model

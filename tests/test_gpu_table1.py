@@ -1,0 +1,134 @@
+"""GPU parity for the rest of the paper's Table 1: the Turing kinetics, the
+front model with redissolution, and the atmospheric wind with its
+time-dependent vertical component (the step clock on the device), on every
+plan the library accepts, with the 7- and the 19-point Laplacian, and the
+192^3 problem set itself in its autotuned plan.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1004_0480_amd import rd
+from paper_1004_0480_amd import workloads as W
+from paper_1004_0480_amd.workloads import GHOST, HELD, MIRROR, PERIODIC, ModelSpec, uniform_bc
+from test_gpu_parity import TOL, compiled_plans, gpu_run, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def atmos(shape, stencil, ns=1, T=0.5, bc=None, seed=0):
+    """A fast-turning vertical wind (u_z sin(t / 0.5) at dt 0.25) so the
+    upwind side of z flips within a few steps; sources in the interior."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    cells = np.array([((nz // 2) * ny + ny // 2) * nx + nx // 3, ((nz // 3) * ny + 2) * nx + nx - 5], np.int64)
+    spec = ModelSpec("atmos", ns, 0.25, 1.0, [[0.2] * 3] * ns, bc if bc is not None else uniform_bc(ns, MIRROR),
+                     {"ux": 0.5, "uy": -0.25, "uz": 0.5, "uz_period": T, "t0": 0.25},
+                     sources=(cells, np.array([0, ns - 1], np.int32), np.array([10.0, 4.0])), stencil=stencil)
+    return W.Workload("atmos", shape, spec, [rng.uniform(0.0, 1.0, shape) for _ in range(ns)], 8, seed)
+
+
+def case(name):
+    if name.startswith("turing"):
+        st = 19 if name.endswith("19") else 7
+        shape = (9, 10, 256)
+        rng = np.random.default_rng(1)
+        spec = W.turing_spec(stencil=st)
+        return W.Workload(name, shape, spec, [1.0 + rng.uniform(-0.05, 0.05, shape) for _ in range(2)], 6, 1)
+    if name.startswith("front"):
+        st = 19 if name.endswith("19") else 7
+        shape = (9, 10, 70)
+        rng = np.random.default_rng(2)
+        # the paper's dt = 0.02 is inside the Cahn-Hilliard bound only with the
+        # 19-point spectral radius 16/3 (7-point: 12 -> 0.02 * 156 > 1)
+        spec = W.paper_front_spec(stencil=st, dt=0.02 if st == 19 else 0.005)
+        A = rng.uniform(0.0, 2.0, shape)
+        A[:, :, 0] = 10.0
+        fields = [A, rng.uniform(0.5, 1.0, shape), rng.uniform(-1.0, 1.0, shape)]
+        return W.Workload(name, shape, spec, [f.astype(np.float32).astype(np.float64) for f in fields], 6, 2)
+    if name == "atmos7":
+        return atmos((10, 12, 256), 7)
+    if name == "atmos19":
+        return atmos((10, 12, 256), 19)
+    if name == "atmos2_faces":
+        faces = [(GHOST, 0.0), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0), (HELD, 0.5), (MIRROR, 0)]
+        return atmos((9, 11, 70), 7, ns=2, bc=[faces, faces], seed=3)
+    if name == "atmos3_19":
+        return atmos((8, 9, 256), 19, ns=3, seed=4)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["turing7", "turing19", "front7", "front19", "atmos7", "atmos19",
+                                  "atmos2_faces", "atmos3_19"])
+def test_table1_models_every_plan(name):
+    """Every accepted plan gives the same bits, within 1e-5 of the oracle."""
+    w = case(name)
+    steps = w.steps
+    ref = oracle.run(w.spec, w.fields, steps)
+    plans = compiled_plans(w, czs=(0, 4))
+    if w.spec.stencil == 19:
+        assert all(p["kernel"] in ("direct", "lds") for p in plans), name
+    if w.shape[2] == 256 and w.spec.model in ("turing", "atmos"):
+        assert any(p["kernel"] == "lds" for p in plans), name
+    base = None
+    for plan in plans:
+        got, _ = gpu_run(w, steps, plan=plan)
+        if base is None:
+            base = got
+            for s in range(w.spec.ns):
+                e = rel_l2(got[s], ref[s])
+                print("%s species %d rel-L2 %.3e (%d plans)" % (name, s, e, len(plans)))
+                assert e <= TOL, (name, s, e)
+            continue
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], base[s]), (name, plan, s)
+
+
+@pytest.mark.parametrize("stencil", [7, 19])
+def test_atmos_clock_across_calls_graphs_and_autotune(stencil):
+    """The vertical wind follows the step count whether the steps come in one
+    call, split over calls, from graph replays, or after an autotune (which
+    must put the clock back with the state)."""
+    import torch
+    w = atmos((10, 12, 256), stencil)
+    n = 13
+    ref = oracle.run(w.spec, w.fields, n)
+
+    def run(split, chunk=0, tune=False):
+        g = rd.Grid(w.shape, 1, w.spec.h, "f32", stream=torch.cuda.Stream() if chunk else None)
+        g.set_model(w.spec)
+        g.write(0, w.fields[0])
+        if tune:
+            g.autotune(3)
+        g.set_plan(graph_chunk=chunk)
+        for k in split:
+            g.step(k)
+        out = g.read(0)
+        g.close()
+        return out
+
+    eager = run([n])
+    assert rel_l2(eager, ref[0]) <= TOL
+    assert np.array_equal(run([5, 8]), eager)
+    assert np.array_equal(run([1, 1, 11]), eager)
+    assert np.array_equal(run([n], chunk=4), eager)
+    assert np.array_equal(run([6, 7], chunk=4), eager)
+    assert np.array_equal(run([n], tune=True), eager)
+
+
+@pytest.mark.parametrize("name,steps", [("t1_diffusion192", 4), ("t1_turing192", 4), ("t1_front192", 3),
+                                        ("t1_atmos192", 4)])
+def test_table1_at_192_autotuned(name, steps):
+    """The paper's problem set at its own size, 19-point, autotuned plan."""
+    w = W.make_workload(name)
+    g = rd.Grid.from_workload(w)
+    g.autotune(2)
+    plan = g.plan()
+    g.step(steps)
+    got = g.read_all()
+    g.close()
+    ref = oracle.run(w.spec, w.fields, steps)
+    for s in range(w.spec.ns):
+        e = rel_l2(got[s], ref[s])
+        print("%s species %d rel-L2 %.3e plan %s" % (name, s, e, plan))
+        assert e <= TOL, (name, s, e)
