@@ -29,10 +29,11 @@ PROFILES = os.path.join(ROOT, "profiles")
 # form additionally writes and reads the FP32 chemical potential (8 B/cell).
 def alg_bytes_per_cell(name: str, storage: str) -> int:
     ns = {"brusselator256": 2, "diffusion64": 1, "diffusion512": 1, "front384": 3,
-          "pollutant512": 4}[name]
+          "pollutant512": 4, "t1_diffusion192": 1, "t1_turing192": 2, "t1_front192": 3,
+          "t1_atmos192": 1}[name]
     es = 4 if storage == "f32" else 2
     b = 2 * ns * es
-    if name == "front384":
+    if name in ("front384", "t1_front192"):
         b += 8 + es          # mu written (4) and read (4) + C read again by pass 1
     return b
 
@@ -76,10 +77,13 @@ def measured_traffic(name: str, digest: str):
     return rec
 
 
-def cpu_baseline(w, budget_s: float = 12.0):
-    """The FP64 oracle as it stands, on all host cores, on a bounded sample
-    (whole grid, a few steps) of the same workload."""
+def cpu_baseline(w, budget_s: float = 12.0, threads: int = 0):
+    """The FP64 oracle as it stands, on all host cores (or `threads` of them;
+    the paper's CPU baseline is one thread), on a bounded sample (whole grid,
+    a few steps) of the same workload."""
     import oracle
+    if threads > 0:
+        oracle.set_threads(threads)
     t0 = time.perf_counter()
     oracle.run(w.spec, w.fields, 1)
     one = time.perf_counter() - t0
@@ -87,10 +91,12 @@ def cpu_baseline(w, budget_s: float = 12.0):
     t0 = time.perf_counter()
     oracle.run(w.spec, w.fields, steps)
     dt = time.perf_counter() - t0
+    nthr = oracle.threads()
     return {"value": w.cells * steps / dt / 1e9, "unit": "Gcell-updates/s",
-            "cores": oracle.threads(), "kind": "oracle",
-            "sample": "%s %dx%dx%d, %d FP64 steps (whole grid), OpenMP over z"
-                      % (w.name, w.shape[2], w.shape[1], w.shape[0], steps)}
+            "cores": nthr, "kind": "oracle",
+            "sample": "%s %dx%dx%d, %d FP64 steps (whole grid), %s"
+                      % (w.name, w.shape[2], w.shape[1], w.shape[0], steps,
+                         "one thread" if nthr == 1 else "OpenMP over z, %d threads" % nthr)}
 
 
 COPY_PROBE_BYTES = 2 * 256 * 1024 * 1024    # copy-ceiling probe: bytes read (and written)
@@ -287,7 +293,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="brusselator256",
                     choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64",
-                             "serve"])
+                             "t1_diffusion192", "t1_turing192", "t1_front192", "t1_atmos192", "serve"])
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16", "both"])
     ap.add_argument("--stencil", type=int, default=7, choices=[7, 19],
                     help="Laplacian: 7-point, or the 19-point form of Eqs. (3)-(4) (x coefficient on every axis)")
@@ -297,6 +303,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=50)
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads for the CPU baseline (0 = all host cores; the paper used 1)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--plan", default=None,
                     help="JSON plan (kernel, vx, ry, waves, cz) to use instead of autotuning")
@@ -390,13 +398,13 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
-                   "species": w.spec.ns, "storage": args.storage, "stencil": args.stencil, "dt": w.spec.dt,
+                   "species": w.spec.ns, "storage": args.storage, "stencil": w.spec.stencil, "dt": w.spec.dt,
                    "plan": plan, "wall_s": wall},
         "roofline": roof,
     }
     g.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, threads=args.cpu_threads)
     print(json.dumps(out), flush=True)
 
 

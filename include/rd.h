@@ -152,9 +152,10 @@ enum {
                               wave64 lane shifts for x, LDS for inter-wave rows */
     RD_KERNEL_BLOCK = 3,   /* xy tile x cz-plane slab per workgroup, all planes
                               loaded up front; same lane shifts and LDS rows    */
-    RD_KERNEL_LDS = 4,     /* FP32 rows of 256 or 512 cells: z-march over a ring
-                              of LDS plane slots filled by direct-to-LDS loads
-                              from one producer wave                           */
+    RD_KERNEL_LDS = 4,     /* FP32 rows of up to 256 (vx 4) or 512 (vx 8) cells,
+                              more than 256 for vx 8, nx a multiple of 4:
+                              z-march over a ring of LDS plane slots filled by
+                              direct-to-LDS loads from one producer wave       */
     RD_KERNEL_LDS2 = 5     /* as RD_KERNEL_LDS, two time steps per launch
                               (temporal blocking; diffusion and Brusselator).
                               rd_step with an odd count finishes with one
@@ -163,7 +164,8 @@ enum {
 typedef struct rd_plan {
     int32_t kernel;       /* RD_KERNEL_*                                        */
     int32_t vx;           /* TILED/BLOCK: cells per lane along x (1, 2 or 4);
-                             LDS/LDS2: 4 (rows of 256 cells) or 8 (of 512)     */
+                             LDS: 4 (rows of <= 256 cells) or 8 (257..512);
+                             LDS2: 4 (rows of 256 cells) or 8 (of 512)         */
     int32_t ry;           /* TILED/BLOCK: rows per wave (1, 2 or 4);
                              LDS/LDS2: rows per workgroup                      */
     int32_t waves;        /* TILED/BLOCK: waves per workgroup (1 or 4);

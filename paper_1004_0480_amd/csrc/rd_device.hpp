@@ -1317,7 +1317,9 @@ __global__ __launch_bounds__(64 * W) void tiled_kernel(const StepArgs* __restric
 
 // ---- LDS-ring z-march kernel ------------------------------------------------
 //
-// Whole rows of nx = 256*NCH FP32 cells.  A workgroup owns rows [yb, yb+BY)
+// Whole rows of 256*(NCH-1) < nx <= 256*NCH FP32 cells (nx a multiple of 4;
+// the lanes past the row end in the last 256-cell chunk load, compute and
+// store nothing of use).  A workgroup owns rows [yb, yb+BY)
 // and marches planes [z0, z1).  One producer wave streams every plane it
 // needs (its BY rows plus one halo row on each side, every field) from HBM
 // into a ring of D plane slots in LDS with global_load_lds_dwordx4, so the
@@ -1366,6 +1368,7 @@ __device__ __forceinline__ void lds_producer(const StepArgs& a, RD_LDS float* ri
     using R = LdsRing<M::NF, NCH, BY, D>;
     constexpr int NF = M::NF, ROWS = R::ROWS, TXT = R::TXT;
     const int lane = threadIdx.x & 63;
+    const bool in_row = lane < ((a.nx - 256 * (NCH - 1)) >> 2);   // of the last chunk
     // grid row of LDS row j is yb - 1 + j, resolved by the face rules
     int ridx[NF][ROWS];
 #pragma unroll
@@ -1382,8 +1385,10 @@ __device__ __forceinline__ void lds_producer(const StepArgs& a, RD_LDS float* ri
             for (int j = 0; j < ROWS; ++j)
 #pragma unroll
                 for (int c = 0; c < NCH; ++c)
-                    __builtin_amdgcn_global_load_lds(base + (long long)ridx[f][j] * a.pitch + c * 256,
-                                                     (RD_LDS void*)(slot + (f * ROWS + j) * TXT + c * 256), 16, 0, 0);
+                    if (c < NCH - 1 || in_row)
+                        __builtin_amdgcn_global_load_lds(base + (long long)ridx[f][j] * a.pitch + c * 256,
+                                                         (RD_LDS void*)(slot + (f * ROWS + j) * TXT + c * 256), 16, 0,
+                                                         0);
         }
     };
     // planes z0-1 .. z0+D-3 into slots 0 .. D-2; plane p lives in slot (p - z0 + 1) % D
@@ -1425,6 +1430,9 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
         }
         rows_fix = rows_fix || (a.held[f] & 3) != 0;
     }
+    // the last cell of a row sits in lane `last` of the last chunk
+    const int last = ((a.nx - 256 * (NCH - 1)) >> 2) - 1;
+    const bool at_end = lane == last;
     // x sides of a whole row: rotate (periodic), own edge value (mirror) or
     // the face value, held in registers across the plane loop
     int xsl[NF], xsr[NF];
@@ -1518,13 +1526,14 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
                     auto xnb = [&](int f, const float (&row)[NCH][4], int c, float k, float& left, float& right)
                                    __attribute__((always_inline)) {
                         const float fl = c > 0 ? lane_from_left_wrap(row[c - 1][3])
-                                         : rot_l[f] ? lane_from_left_wrap(row[NCH - 1][3])
+                                         : rot_l[f] ? bcast_lane(row[NCH - 1][3], last)
                                          : own_l[f] ? row[0][0] : k * fill_l[f];
                         const float fr = c < NCH - 1 ? lane_from_right_wrap(row[c + 1][0])
-                                         : rot_r[f] ? lane_from_right_wrap(row[0][0])
+                                         : rot_r[f] ? bcast_lane(row[0][0], 0)
                                          : own_r[f] ? row[NCH - 1][3] : k * fill_r[f];
                         left = lane_from_left(row[c][3], fl);
                         right = lane_from_right(row[c][0], fr);
+                        if (c == NCH - 1) right = at_end ? fr : right;
                     };
 #pragma unroll
                     for (int f = 0; f < NF; ++f) {
@@ -1584,7 +1593,7 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
 #pragma unroll
                             for (int s = 0; s < NO; ++s) o[s][i] = held ? held_out(a, s, xl + i, y, z, oi[s]) : oi[s];
                         }
-                        if (y < a.ny) {
+                        if (y < a.ny && (c < NCH - 1 || lane <= last)) {
                             const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
 #pragma unroll
                             for (int s = 0; s < NO; ++s) store_vec<StF32, 4>(a.out[s], idx, o[s]);

@@ -50,7 +50,10 @@ struct LdsCfg { int nch, by, wc, d; };
 constexpr LdsCfg kLdsCfgs[] = {
     {1, 8, 4, 7}, {1, 8, 8, 7}, {2, 8, 4, 6}, {2, 4, 4, 6}, {2, 8, 8, 6}, {2, 4, 4, 7},
     {2, 8, 8, 7}, {1, 12, 6, 5}, {2, 12, 6, 5}, {2, 6, 6, 5},
+    // four-field shapes (the front model's update pass reads A, B, C and mu)
+    {1, 4, 4, 6}, {2, 2, 2, 5},
 };
+constexpr int kFirstLds4Cfg = 10;
 constexpr int kNumLdsCfgs = sizeof(kLdsCfgs) / sizeof(kLdsCfgs[0]);
 
 // Ring shapes of the two-steps-per-launch LDS kernel (same fields).
@@ -106,9 +109,13 @@ constexpr int pm_fields(int pm) {
 }
 
 // LDS-ring shape i is compiled for this storage and pass model: FP32 fields,
-// at most two of them, and a ring that fits the LDS and the vmcnt range.
+// a ring that fits the LDS and the vmcnt range; models of one or two fields
+// take the first shapes, the two passes of the front model the four-field
+// ones (both passes of a step share one plan).
 constexpr bool lds_ok(int storage, int pm, int i) {
-    if (storage != ST_F32 || pm_fields(pm) > 2 || pm == PM_CHMU || i < 0 || i >= kNumLdsCfgs) return false;
+    if (storage != ST_F32 || i < 0 || i >= kNumLdsCfgs) return false;
+    const bool front = pm == PM_CHMU || pm == PM_FRONT;
+    if (front != (i >= kFirstLds4Cfg) || (!front && pm_fields(pm) > 2)) return false;
     const LdsCfg c = kLdsCfgs[i];
     const int nf = pm_fields(pm), rows = c.by + 2;
     const long long bytes = 4LL * c.d * nf * rows * 256 * c.nch;

@@ -633,6 +633,54 @@ def test_stencil19_full_size_autotuned(name, steps):
         assert e <= TOL
 
 
+@pytest.mark.parametrize("case", ["diff192", "bruss196_periodic", "poll384", "faces260_held", "diff452",
+                                  "diff192_19", "bruss384_19_periodic", "faces196_19_held"])
+def test_partial_ring_rows_every_plan(case):
+    """Rows that end inside a 256-cell chunk of the LDS ring: the lanes past
+    the row end load and store nothing and the row's last cell takes its x
+    face rule (a periodic wrap comes from the row's other end).  Every plan
+    agrees bit for bit and with the oracle."""
+    rng = np.random.default_rng(sum(map(ord, case)))
+    if case.startswith("diff"):
+        nx = int(case[4:7])
+        shape = (7, 9, nx)
+        spec = bc_spec(1, [(MIRROR, 0)] * 6, K=(1.0, 1.0, 1.0), dt=0.1)
+        fields = [rng.uniform(0, 1, shape)]
+    elif case.startswith("bruss"):
+        nx = int(case[5:8])
+        w = W.make_workload("brusselator256", shape=(6, 10, nx))
+        spec, fields, shape = w.spec, w.fields, w.shape
+    elif case.startswith("poll"):
+        w = W.make_workload("pollutant512", shape=(8, 10, 384))
+        spec, shape = w.spec, w.shape
+        fields = [rng.uniform(0, 1, shape) for _ in range(spec.ns)]
+    else:
+        nx = int(case[5:8])
+        shape = (8, 9, nx)
+        faces = [(HELD, 1.0), (GHOST, -0.5), (PERIODIC, 0), (PERIODIC, 0), (GHOST, 2.0), (HELD, -1.0)]
+        spec = bc_spec(2, faces, K=(1.0, 1.0, 1.0), dt=0.1)
+        fields = [rng.uniform(0, 1, shape) for _ in range(2)]
+    if "_19" in case:
+        spec = spec.copy()
+        spec.stencil = 19
+        spec.K = [[k[0]] * 3 for k in spec.K]
+    w = W.Workload(case, shape, spec, fields, 6, 0)
+    steps = 6
+    ref = oracle.run(w.spec, w.fields, steps)
+    plans = compiled_plans(w, czs=(0, 4))
+    assert any(p["kernel"] == "lds" for p in plans), case
+    base = None
+    for plan in plans:
+        got, _ = gpu_run(w, steps, plan=plan)
+        if base is None:
+            base = got
+            for s in range(w.spec.ns):
+                assert rel_l2(got[s], ref[s]) <= TOL, (case, s)
+            continue
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], base[s]), (case, plan, s)
+
+
 @pytest.mark.parametrize("name,shape", [("brusselator256", (6, 12, 256)), ("diffusion512", (9, 7, 512))])
 def test_two_step_plans_with_graphs_and_odd_counts(name, shape):
     """Two steps per launch: graph chunks of 2, 4 and 6 steps and odd step
