@@ -32,6 +32,7 @@ _PARAM_SLOTS = {
     "turing": ("alpha", "beta", "gamma"),
     "atmos": ("ux", "uy", "uz", "uz_period", "t0"),
 }
+_INTEGRATOR = {"euler": 1, "rk2": 2, "rk3": 3}
 # constants that may be left out of a spec's params (then 0)
 _OPTIONAL = ("k2", "uz_period", "t0")
 
@@ -51,6 +52,7 @@ class _Problem(C.Structure):
         ("src_species", C.POINTER(C.c_int32)),
         ("src_rate", C.POINTER(C.c_double)),
         ("stencil", C.c_int32),
+        ("integrator", C.c_int32),
     ]
 
 
@@ -91,6 +93,7 @@ def _problem(spec, shape):
     P.h = float(spec.h)
     P.dt = float(spec.dt)
     P.stencil = int(getattr(spec, "stencil", 7))
+    P.integrator = _INTEGRATOR[getattr(spec, "integrator", "euler")]
     for s in range(spec.ns):
         for d in range(3):
             P.K[s][d] = float(spec.K[s][d])

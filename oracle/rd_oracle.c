@@ -160,6 +160,8 @@ static int valid(const or_problem *P)
     if (P->model < OR_DIFFUSION || P->model > OR_ATMOS) return 0;
     if (P->model == OR_POLLUTANT && !P->wind) return 0;
     if (P->stencil != 7 && P->stencil != 19) return 0;
+    if (P->integrator < 0 || P->integrator > OR_RK3) return 0;
+    if (P->integrator >= OR_RK2 && P->model == OR_ATMOS) return 0;
     if (P->stencil == 19)
         for (int s = 0; s < P->ns; ++s)
             if (P->K[s][1] != P->K[s][0] || P->K[s][2] != P->K[s][0]) return 0;
@@ -311,6 +313,29 @@ int or_run(const or_problem *P, double *state, int64_t nsteps)
         }
         nsrc = P->nsrc;
         qsort(src, (size_t)nsrc, sizeof(source_t), cmp_source);
+    }
+    if (P->integrator >= OR_RK2) {
+        /* two more stage arrays: u = E(c) and E(u) */
+        double *u = (double *)malloc(bytes), *eu = (double *)malloc(bytes);
+        if (!u || !eu) { free(u); free(eu); free(work); free(mu); free(src); return -1; }
+        const size_t total = (size_t)P->ns * (size_t)N;
+        for (int64_t n = 0; n < nsteps; ++n) {
+            step(P, state, u, mu, src, nsrc, 0.0);          /* u1 = E(c)      */
+            step(P, u, eu, mu, src, nsrc, 0.0);             /* E(u1)          */
+            if (P->integrator == OR_RK2) {
+                for (size_t q = 0; q < total; ++q) state[q] = 0.5 * state[q] + 0.5 * eu[q];
+                continue;
+            }
+            for (size_t q = 0; q < total; ++q) u[q] = 0.75 * state[q] + 0.25 * eu[q];   /* u2 */
+            step(P, u, eu, mu, src, nsrc, 0.0);             /* E(u2)          */
+            for (size_t q = 0; q < total; ++q) state[q] = state[q] / 3.0 + 2.0 * eu[q] / 3.0;
+        }
+        free(u);
+        free(eu);
+        free(work);
+        free(mu);
+        free(src);
+        return 0;
     }
     double *a = state, *b = work;
     for (int64_t n = 0; n < nsteps; ++n) {

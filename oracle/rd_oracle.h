@@ -87,7 +87,18 @@ typedef struct or_problem {
     const int32_t *src_species;
     const double *src_rate;
     int32_t stencil;                      /* 7, or 19 (needs K[s][0]=K[s][1]=K[s][2]) */
+    int32_t integrator;                   /* OR_EULER (0 or 1), OR_RK2, OR_RK3 */
 } or_problem;
+
+/* Time integrators.  Forward Euler is Eq. (5); the others are the
+ * strong-stability-preserving Runge-Kutta methods of order 2 (Heun) and 3
+ * (Shu-Osher), built from Euler steps E(u) = u + dt F(u):
+ *   OR_RK2:  u1 = E(c);  c' = c/2 + E(u1)/2
+ *   OR_RK3:  u1 = E(c);  u2 = 3c/4 + E(u1)/4;  c' = c/3 + 2 E(u2)/3
+ * (the paper notes that more accurate steppers exist, section 2).  Held
+ * layers keep their value through every stage.  Models whose terms depend
+ * on time (the atmospheric wind) take forward Euler only. */
+enum { OR_EULER = 1, OR_RK2 = 2, OR_RK3 = 3 };
 
 /* Advance `state` (ns*nz*ny*nx doubles) by nsteps explicit Euler steps in
  * place.  Returns 0, or -1 on a bad argument / allocation failure. */

@@ -64,7 +64,9 @@ class ModelSpec:
     (pollutant only) is a tuple (cell, species, rate) of equal-length arrays,
     ``cell`` the linear index z*ny*nx + y*nx + x.  ``stencil`` is the
     Laplacian: 7 (the workloads' 7-point form) or 19 (the paper's 19-point
-    form, isotropic coefficients only).
+    form, isotropic coefficients only).  ``integrator`` is "euler" (Eq. (5)),
+    "rk2" or "rk3" (strong-stability-preserving Runge-Kutta of order 2 or 3
+    built from Euler steps).
     """
     model: str
     ns: int
@@ -76,6 +78,7 @@ class ModelSpec:
     wind: Optional[np.ndarray] = None
     sources: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
     stencil: int = 7
+    integrator: str = "euler"
 
     def copy(self) -> "ModelSpec":
         return ModelSpec(self.model, self.ns, self.dt, self.h,
@@ -83,7 +86,7 @@ class ModelSpec:
                          [list(r) for r in self.bc], dict(self.params),
                          None if self.wind is None else self.wind.copy(),
                          None if self.sources is None else
-                         tuple(a.copy() for a in self.sources), self.stencil)
+                         tuple(a.copy() for a in self.sources), self.stencil, self.integrator)
 
 
 @dataclass

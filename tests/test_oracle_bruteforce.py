@@ -257,6 +257,37 @@ CASES = {
 }
 
 
+def exact_rk(spec, state, integrator):
+    """One SSP Runge-Kutta step of order 2 or 3 from exact Euler steps."""
+    u1 = exact_step(spec, state)
+    eu1 = exact_step(spec, u1)
+    if integrator == "rk2":
+        return [{p: (c[p] + e[p]) / 2 for p in c} for c, e in zip(state, eu1)]
+    u2 = [{p: 3 * c[p] / 4 + e[p] / 4 for p in c} for c, e in zip(state, eu1)]
+    eu2 = exact_step(spec, u2)
+    return [{p: c[p] / 3 + 2 * e[p] / 3 for p in c} for c, e in zip(state, eu2)]
+
+
+@pytest.mark.parametrize("case", ["brusselator_mixed", "front_held", "diffusion19_ghost_held", "turing19_mixed"])
+@pytest.mark.parametrize("integrator", ["rk2", "rk3"])
+def test_oracle_rk_matches_exact_expansion(oracle, case, integrator):
+    spec = CASES[case]()
+    spec.integrator = integrator
+    rng = np.random.default_rng(sum(map(ord, case + integrator)))
+    if spec.model == "brusselator":
+        fields = [4.5 + dyadic_field(rng, -0.5, 0.5), 1.5 + dyadic_field(rng, -0.5, 0.5)]
+    else:
+        fields = [dyadic_field(rng) for _ in range(spec.ns)]
+    state = [to_exact(f) for f in fields]
+    for _ in range(2):
+        state = exact_rk(spec, state, integrator)
+    got = oracle.run(spec, fields, 2)
+    for s in range(spec.ns):
+        exact = to_array(state[s])
+        scale = max(1.0, np.max(np.abs(exact)))
+        assert np.max(np.abs(got[s] - exact)) <= 1e-13 * scale, (case, s)
+
+
 @pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("steps", [1, 3])
 def test_oracle_matches_exact_expansion(oracle, case, steps):

@@ -610,3 +610,69 @@ def test_atmos_mass_budget(oracle, stencil):
                for d in range(3))
     expect = dt * (rates.sum() - flux)
     assert abs((out.sum() - c0.sum()) - expect) < 1e-12 * c0.sum()
+
+
+# ------------------------------------------------------------------ P13
+# Strong-stability-preserving Runge-Kutta steps built from Euler steps.
+
+RK_FACTOR = {
+    "euler": lambda z: 1 + z,
+    "rk2": lambda z: 1 + z + z * z / 2,
+    "rk3": lambda z: 1 + z + z * z / 2 + z**3 / 6,
+}
+
+
+@pytest.mark.parametrize("integrator", ["rk2", "rk3"])
+@pytest.mark.parametrize("stencil", [7, 19])
+@pytest.mark.parametrize("kinds", [(MIRROR, MIRROR, MIRROR), (PERIODIC, MIRROR, GHOST)])
+def test_rk_fourier_mode_factor(oracle, integrator, stencil, kinds):
+    """On a linear problem each stage is a polynomial in dt L, so a discrete
+    Fourier mode is multiplied per step by the method's stability polynomial
+    R(z) at z = dt lambda: 1 + z + z^2/2 (order 2), + z^3/6 (order 3)."""
+    shape = (5, 6, 11)
+    nz, ny, nx = shape
+    h, D, dt, n = 1.3, 0.6, 0.2, 15
+    vx, lx = mode_1d(kinds[0], nx, 2, h)
+    vy, ly = mode_1d(kinds[1], ny, 1, h)
+    vz, lz = mode_1d(kinds[2], nz, 3, h)
+    mode = vz[:, None, None] * vy[None, :, None] * vx[None, None, :]
+    z = dt * D * laplacian_symbol([lx, ly, lz], h, stencil)
+    spec = ModelSpec("diffusion", 1, dt, h, [[D] * 3], axis_bc(kinds), stencil=stencil, integrator=integrator)
+    out = oracle.run(spec, [mode], n)[0]
+    assert np.max(np.abs(out - RK_FACTOR[integrator](z) ** n * mode)) < 1e-14
+
+
+@pytest.mark.parametrize("integrator,order", [("euler", 1), ("rk2", 2), ("rk3", 3)])
+def test_rk_order_of_accuracy(oracle, integrator, order):
+    """Against the exact decay exp(lambda T) of one mode of the semi-discrete
+    problem, halving dt divides the error at a fixed time by about 2^order."""
+    shape = (4, 4, 16)
+    vx, lx = mode_1d(PERIODIC, 16, 1, 1.0)
+    mode = np.broadcast_to(vx, shape).copy()
+    D, T = 1.0, 2.0
+    errs = []
+    for n in (10, 20, 40):
+        spec = ModelSpec("diffusion", 1, T / n, 1.0, [[D] * 3], axis_bc((PERIODIC, MIRROR, MIRROR)),
+                         integrator=integrator)
+        out = oracle.run(spec, [mode], n)[0]
+        errs.append(np.max(np.abs(out - np.exp(D * lx * T) * mode)))
+    for a, b in zip(errs, errs[1:]):
+        assert 0.85 * 2**order < a / b < 1.15 * 2**order, errs
+
+
+@pytest.mark.parametrize("integrator", ["rk2", "rk3"])
+def test_rk_keeps_held_layers_and_rejects_clocked_wind(oracle, integrator):
+    shape = (5, 6, 7)
+    rng = np.random.default_rng(3)
+    faces = [(HELD, 1.5), (MIRROR, 0), (GHOST, 0.25), (MIRROR, 0), (MIRROR, 0), (HELD, -0.5)]
+    spec = ModelSpec("diffusion", 1, 0.1, 1.0, [[1.0] * 3], [faces], integrator=integrator)
+    c0 = rng.uniform(0, 1, shape)
+    c0[:, :, 0] = 1.5
+    c0[-1, :, :] = -0.5
+    c0[-1, :, 0] = 1.5                      # x- decides where the two held faces meet
+    out = oracle.run(spec, [c0], 7)[0]
+    assert np.all(np.abs(out[:, :, 0] - 1.5) < 1e-15) and np.all(np.abs(out[-1, :, 1:] + 0.5) < 1e-15)
+    a = ModelSpec("atmos", 1, 0.1, 1.0, [[0.1] * 3], uniform_bc(1, MIRROR),
+                  {"ux": 1.0, "uy": 0.0, "uz": 1.0, "uz_period": 2.0}, integrator=integrator)
+    with pytest.raises(ValueError):
+        oracle.run(a, [c0], 1)
