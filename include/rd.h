@@ -120,6 +120,17 @@ enum { RD_FACE_XLO = 0, RD_FACE_XHI, RD_FACE_YLO, RD_FACE_YHI, RD_FACE_ZLO, RD_F
  *              faces takes the rule of the first of them in x, y, z order.
  *              19-point grids run on the direct and LDS-ring plans and are
  *              not batched.
+ * integrator   0 or RD_EULER: forward Euler, Eq. (5).  RD_RK2 / RD_RK3: the
+ *              strong-stability-preserving Runge-Kutta steps of order 2
+ *              (Heun) and 3 (Shu-Osher) built from Euler steps E(u) = u +
+ *              dt F(u): RK2  c' = c + (E(E(c)) - c)/2;  RK3  u = c +
+ *              (E(E(c)) - c)/4,  c' = c + 2 (E(u) - c)/3 (the paper notes
+ *              that more accurate steppers exist, section 2).  Each Euler
+ *              stage keeps held layers, and the combinations keep them
+ *              exactly.  A Runge-Kutta grid allocates one more buffer per
+ *              species, takes no two-step plan (RD_KERNEL_LDS2), is not
+ *              batched, and rejects the atmospheric model (its wind depends
+ *              on time) with RD_EINVAL.
  * dt           time step; rd_set_model rejects a dt outside the stable range
  *              (RD_EUNSTABLE): per species dt*(2*sum_d K_d/h^2 + max u/h) <= 1
  *              (19-point: dt*(4 D/h^2 + max u/h) <= 1; for ATMOS, max u is
@@ -142,7 +153,11 @@ typedef struct rd_model_desc {
     const int32_t *src_species;
     const double *src_rate;
     int32_t stencil;
+    int32_t integrator;
 } rd_model_desc;
+
+/* time integrators (rd_model_desc.integrator) */
+enum { RD_EULER = 1, RD_RK2 = 2, RD_RK3 = 3 };
 
 /* kernel plan of a grid (all plans give bitwise-identical fields) */
 enum {

@@ -2097,6 +2097,22 @@ __global__ __launch_bounds__(256) void unpack_kernel(const void* src, DstT* dst,
 
 // One 16-byte element per thread, streamed with non-temporal load/store:
 // the read+write bandwidth ceiling a kernel can reach.
+// Runge-Kutta stage combination over whole arrays, four elements a thread:
+// out = a + w (c - a) (out may be a).  A held layer has a == c, so it
+// keeps its value exactly.
+template <class S>
+__global__ __launch_bounds__(256) void rk_combine_kernel(const void* a, const void* c, void* out, float w,
+                                                        long long n4) {
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
+        float va[4], vc[4], o[4];
+        load_vec<S, 4>(a, i * 4, va);
+        load_vec<S, 4>(c, i * 4, vc);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[k] = __fmaf_rn(w, vc[k] - va[k], va[k]);
+        store_vec<S, 4>(out, i * 4, o);
+    }
+}
+
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
                                                    float4* __restrict__ dst, long long n4) {
     typedef float v4f __attribute__((ext_vector_type(4)));

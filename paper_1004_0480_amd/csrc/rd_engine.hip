@@ -188,7 +188,10 @@ struct rd_grid {
     int npass = 0;
     int pass_pm[2] = {-1, -1};
     StepArgs args[2][2];               // [input parity][pass], host copy
-    StepArgs* d_args = nullptr;        // same, in device memory
+    StepArgs rk_args[2][2];            // Runge-Kutta stage step: other parity -> stage
+    StepArgs* d_args = nullptr;        // args then rk_args, in device memory
+    int integrator = RD_EULER;
+    void* stage[RD_MAX_SPECIES] = {};  // Runge-Kutta stage buffers (allocated on demand)
     rd_plan plan{};                    // requested plan (kernel 0 = auto)
     rd_plan eff{};                     // plan in use
     int cfg = -1;
@@ -319,6 +322,8 @@ int tune_model_key(const rd_grid* g) { return g->model * 2 + (g->args[0][0].s19 
 int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
     if (p.graph_chunk != 0 && (p.graph_chunk < 2 || (p.graph_chunk & 1)))
         return fail(RD_EINVAL, "graph_chunk must be 0 or an even number >= 2");
+    if (g->integrator >= RD_RK2 && p.kernel == RD_KERNEL_LDS2)
+        return fail(RD_EINVAL, "two-step plans take forward Euler only");
     if (g->args[0][0].s19 && p.kernel != RD_KERNEL_DIRECT && p.kernel != RD_KERNEL_LDS)
         return fail(RD_EINVAL, "the 19-point Laplacian runs on the direct and LDS-ring plans only");
     if (p.kernel == RD_KERNEL_DIRECT) {
@@ -387,9 +392,12 @@ int apply_plan(rd_grid* g) {
         for (int k = 0; k < g->npass; ++k) {
             StepArgs& a = g->args[par][k];
             if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS ||
-                p.kernel == RD_KERNEL_LDS2)
+                p.kernel == RD_KERNEL_LDS2) {
                 g->blocks[k] = set_tiling(a, p);
-            else g->blocks[k] = 0;
+                (void)set_tiling(g->rk_args[par][k], p);
+            } else {
+                g->blocks[k] = 0;
+            }
         }
     for (int k = 0; k < g->npass; ++k)
         if (g->blocks[k] > 0x7fffffffLL)
@@ -398,6 +406,7 @@ int apply_plan(rd_grid* g) {
     g->cfg = cfg;
     drop_graphs(g);
     RD_HIP(hipMemcpy(g->d_args, g->args, sizeof(g->args), hipMemcpyHostToDevice));
+    RD_HIP(hipMemcpy(g->d_args + 4, g->rk_args, sizeof(g->rk_args), hipMemcpyHostToDevice));
     return RD_OK;
 }
 
@@ -411,10 +420,67 @@ int launch_one_step(rd_grid* g, int parity) {
     return RD_OK;
 }
 
+// Euler step of a Runge-Kutta stage: from the other parity's buffers into
+// the stage buffers.
+int launch_stage_step(rd_grid* g, int parity) {
+    for (int k = 0; k < g->npass; ++k) {
+        const hipError_t e = launch_pass(g->storage, g->pass_pm[k], g->eff.kernel, g->cfg,
+                                         g->rk_args[parity][k], g->d_args + 4 + parity * 2 + k,
+                                         g->blocks[k], g->stream);
+        if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return RD_OK;
+}
+
+// out = a + w (c - a) for every species' whole array.
+int rk_combine(rd_grid* g, void* const* a, void* const* c, void* const* out, float w) {
+    const long long n4 = (long long)(g->elems / 4);
+    const unsigned blocks = unsigned(std::min<long long>((n4 + 255) / 256, 8LL * num_cus()));
+    for (int s = 0; s < g->ns; ++s) {
+        switch (g->storage) {
+        case RD_F32:
+            hipLaunchKernelGGL((rk_combine_kernel<StF32>), dim3(blocks), dim3(256), 0, g->stream, a[s], c[s],
+                               out[s], w, n4);
+            break;
+        case RD_BF16:
+            hipLaunchKernelGGL((rk_combine_kernel<StBF16>), dim3(blocks), dim3(256), 0, g->stream, a[s], c[s],
+                               out[s], w, n4);
+            break;
+        default:
+            hipLaunchKernelGGL((rk_combine_kernel<StF16>), dim3(blocks), dim3(256), 0, g->stream, a[s], c[s],
+                               out[s], w, n4);
+            break;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
+    return RD_OK;
+}
+
+// One strong-stability-preserving Runge-Kutta step from Euler steps E; the
+// state stays in the current parity's buffers A, B is the other parity, C
+// the stage buffers.  Order 2: B = E(A), C = E(B), A = A + (C - A)/2.
+// Order 3: then B = A + (C - A)/4, C = E(B), A = A + 2 (C - A)/3.
+int launch_rk_step(rd_grid* g) {
+    const int p = g->cur;
+    void* const* A = g->buf[p];
+    void* const* B = g->buf[p ^ 1];
+    void* const* C = g->stage;
+    int rc = launch_one_step(g, p);
+    if (!rc) rc = launch_stage_step(g, p);
+    if (rc) return rc;
+    if (g->integrator == RD_RK2) return rk_combine(g, A, C, A, 0.5f);
+    rc = rk_combine(g, A, C, B, 0.25f);
+    if (!rc) rc = launch_stage_step(g, p);
+    if (!rc) rc = rk_combine(g, A, C, A, float(2.0 / 3.0));
+    return rc;
+}
+
 int build_graph(rd_grid* g, int parity, int launches, hipGraphExec_t* out) {
     RD_HIP(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
     int rc = RD_OK;
-    for (int i = 0; i < launches && rc == RD_OK; ++i) rc = launch_one_step(g, (parity + i) & 1);
+    for (int i = 0; i < launches && rc == RD_OK; ++i)
+        rc = g->integrator >= RD_RK2 ? launch_rk_step(g) : launch_one_step(g, (parity + i) & 1);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(g->stream, &graph);
     if (rc != RD_OK) {
@@ -442,6 +508,27 @@ int launch_direct_step(rd_grid* g, int parity) {
 }
 
 int step_grid(rd_grid* g, int64_t n) {
+    if (g->integrator >= RD_RK2) {
+        // the state stays in the current parity: one graph of `chunk` steps
+        const int chunk = g->eff.graph_chunk;
+        if (chunk >= 2 && g->stream != nullptr && n >= chunk) {
+            if (g->gchunk != chunk) {
+                drop_graphs(g);
+                const int rc = build_graph(g, g->cur, chunk, &g->gexec[g->cur]);
+                if (rc) {
+                    drop_graphs(g);
+                    return rc;
+                }
+                g->gchunk = chunk;
+            }
+            for (; n >= chunk; n -= chunk) RD_HIP(hipGraphLaunch(g->gexec[g->cur], g->stream));
+        }
+        for (; n > 0; --n) {
+            const int rc = launch_rk_step(g);
+            if (rc) return rc;
+        }
+        return RD_OK;
+    }
     const int chunk = g->eff.graph_chunk;          // steps per graph (even)
     const int sp = steps_per_launch(g);
     const int launches = chunk / sp;               // launches per graph
@@ -487,7 +574,7 @@ extern "C" size_t rd_grid_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t nspe
     const size_t e = field_elems(nx, ny, nz);
     size_t b = 2 * size_t(nspecies) * e * elem_size(storage_dtype);
     if (with_aux) b += e * sizeof(float);
-    b += 4 * sizeof(StepArgs) + 2 * kRedBlocks * sizeof(double) + 2 * sizeof(double);
+    b += 8 * sizeof(StepArgs) + 2 * sizeof(StepClock) + 2 * kRedBlocks * sizeof(double) + 2 * sizeof(double);
     return b;
 }
 
@@ -560,6 +647,9 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
         return fail(RD_EINVAL, "point sources need the pollutant or atmospheric model");
     }
     if (m->stencil != 0 && m->stencil != 7 && m->stencil != 19) return fail(RD_EINVAL, "stencil must be 7 or 19");
+    if (m->integrator < 0 || m->integrator > RD_RK3) return fail(RD_EINVAL, "unknown integrator");
+    if (m->integrator >= RD_RK2 && m->model == RD_MODEL_ATMOS)
+        return fail(RD_EINVAL, "Runge-Kutta steps take models without a time-dependent term");
     const bool s19 = m->stencil == 19;
     if (s19)
         for (int s = 0; s < ns; ++s)
@@ -630,7 +720,7 @@ extern "C" int rd_create_grid(int64_t nx, int64_t ny, int64_t nz, int32_t nspeci
             if (hipMemsetAsync(g->buf[p][s], 0, bytes, g->stream) != hipSuccess)
                 return cleanup(RD_EDEVICE, "hipMemsetAsync failed");
         }
-    if (hipMalloc(&g->d_args, sizeof(g->args)) != hipSuccess ||
+    if (hipMalloc(&g->d_args, sizeof(g->args) + sizeof(g->rk_args)) != hipSuccess ||
         hipMalloc(&g->d_clock, 2 * sizeof(StepClock)) != hipSuccess ||
         hipMalloc(&g->d_part, 2 * kRedBlocks * sizeof(double)) != hipSuccess ||
         hipMalloc(&g->d_red, 2 * sizeof(double)) != hipSuccess)
@@ -648,6 +738,7 @@ extern "C" int rd_destroy_grid(rd_grid* g) {
     drop_graphs(g);
     for (auto& row : g->buf)
         for (auto& b : row) (void)hipFree(b);
+    for (auto& b : g->stage) (void)hipFree(b);
     (void)hipFree(g->aux);
     (void)hipFree(g->d_args);
     (void)hipFree(g->d_clock);
@@ -817,6 +908,27 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
             }
         }
     }
+    // Runge-Kutta: stage buffers, and the stage step's arguments -- the same
+    // step reading the other parity's buffers and writing the stage buffers
+    g->integrator = m->integrator >= RD_RK2 ? m->integrator : RD_EULER;
+    if (g->integrator >= RD_RK2) {
+        const size_t bytes = g->elems * elem_size(g->storage);
+        for (int s = 0; s < ns; ++s)
+            if (!g->stage[s]) {
+                RD_HIP(hipMalloc(&g->stage[s], bytes));
+                RD_HIP(hipMemset(g->stage[s], 0, bytes));
+            }
+    }
+    for (int par = 0; par < 2; ++par)
+        for (int k = 0; k < 2; ++k) {
+            StepArgs r = g->args[par][k];
+            for (int f = 0; f < MAXF; ++f)
+                for (int s = 0; s < ns; ++s) {
+                    if (r.in[f] == g->buf[par][s]) r.in[f] = g->buf[par ^ 1][s];
+                    if (r.out[f] == g->buf[par ^ 1][s]) r.out[f] = g->stage[s];
+                }
+            g->rk_args[par][k] = r;
+        }
     g->model = m->model;
     if (m->model == RD_MODEL_FRONT_CH) {
         g->npass = 2;
@@ -1247,6 +1359,7 @@ extern "C" int rd_batch_add(rd_batch* b, rd_grid* g, int64_t steps) {
     if (!(g->model == RD_MODEL_BRUSSELATOR || (g->model == RD_MODEL_DIFFUSION && g->ns == 1)))
         return fail(RD_EINVAL, "batches take 1-species diffusion or Brusselator grids");
     if (g->args[0][0].s19) return fail(RD_EINVAL, "batches take 7-point grids");
+    if (g->integrator >= RD_RK2) return fail(RD_EINVAL, "batches take forward Euler grids");
     if (g->storage != b->storage) return fail(RD_EINVAL, "grid storage differs from the batch's");
     if (g->stream != b->stream) return fail(RD_EINVAL, "grid and batch must use the same stream");
     if (int(b->members.size()) >= b->max_grids) return fail(RD_EINVAL, "batch is full");

@@ -22,6 +22,7 @@ STORAGE = {"f32": F32, "bf16": BF16, "f16": F16}
 MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3, "turing": 4, "atmos": 5}
 BC = {"mirror": 0, "periodic": 1, "ghost": 2, "held": 3}
 KERNEL = {"auto": 0, "direct": 1, "tiled": 2, "block": 3, "lds": 4, "lds2": 5}
+INTEGRATOR = {"euler": 1, "rk2": 2, "rk3": 3}
 PARAMS = {
     "diffusion": (),
     "brusselator": ("a", "b"),
@@ -52,6 +53,7 @@ class ModelDesc(C.Structure):
         ("src_species", C.POINTER(C.c_int32)),
         ("src_rate", C.POINTER(C.c_double)),
         ("stencil", C.c_int32),
+        ("integrator", C.c_int32),
     ]
 
 
@@ -144,6 +146,7 @@ def model_desc(spec, shape) -> Tuple[ModelDesc, list]:
     m.nspecies = spec.ns
     m.dt = float(spec.dt)
     m.stencil = int(getattr(spec, "stencil", 7))
+    m.integrator = INTEGRATOR[getattr(spec, "integrator", "euler")]
     for s in range(spec.ns):
         for d in range(3):
             m.diff[s][d] = float(spec.K[s][d])
