@@ -295,6 +295,8 @@ def main():
                     choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64",
                              "t1_diffusion192", "t1_turing192", "t1_front192", "t1_atmos192", "serve"])
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16", "both"])
+    ap.add_argument("--integrator", default="euler", choices=["euler", "rk2", "rk3"],
+                    help="forward Euler (Eq. (5)) or the SSP Runge-Kutta step of order 2 or 3")
     ap.add_argument("--stencil", type=int, default=7, choices=[7, 19],
                     help="Laplacian: 7-point, or the 19-point form of Eqs. (3)-(4) (x coefficient on every axis)")
     ap.add_argument("--requests", type=int, default=4096)
@@ -334,6 +336,7 @@ def main():
     from paper_1004_0480_amd import workloads as W
 
     w = with_stencil(W.make_workload(args.workload), args.stencil)
+    w.spec.integrator = args.integrator
     stream = torch.cuda.Stream()
     print("bench: %s %s storage=%s stencil=%d steps=%d warmup=%d" % (w.name, w.shape, args.storage, args.stencil,
                                                                      args.steps, args.warmup),
@@ -373,24 +376,32 @@ def main():
     bpc = alg_bytes_per_cell(args.workload, args.storage)
     passes = g.passes()
     steps_per_launch = 2 if plan.get("kernel") == 5 else 1     # two-step (temporally blocked) plan
+    # a Runge-Kutta step runs 2 or 3 Euler stages and 1 or 2 combinations,
+    # each reading two arrays and writing one per species
+    stages = {"euler": 1, "rk2": 2, "rk3": 3}[args.integrator]
+    es = 4 if args.storage == "f32" else 2
+    rk_bytes = (stages - 1) * 3 * w.spec.ns * es
     # dominant kernel: the step kernel.  A launch reads and writes every field
     # once (for one step, or two with a two-step plan); with one pass its
     # average launch duration is the event-timed time of the steps it covers.
     # A step of several passes is reported per step (all its kernels).
     launch_ms = ms_per_step * steps_per_launch
     achieved = bpc * w.cells / (launch_ms * 1e-3) / 1e9
+    if stages > 1:      # reported per step over all its kernels
+        achieved = (stages * bpc + rk_bytes) * w.cells / (ms_per_step * 1e-3) / 1e9
     digest = kernel_source_digest()
     pmc = measured_traffic(profile_name(args), digest)
     traffic = None
-    if pmc is not None and pmc.get("steps_per_launch", 1) == steps_per_launch:
+    if pmc is not None and stages == 1 and pmc.get("steps_per_launch", 1) == steps_per_launch:
         traffic = pmc.get("hbm_bytes_per_launch") if passes == 1 else pmc.get("hbm_bytes_per_step")
     ceiling = copy_ceiling(torch, stream, COPY_PROBE_BYTES)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "per": "launch" if passes == 1 else "step (%d kernels)" % passes,
+            "per": ("step (%d Euler stages + %d combinations)" % (stages, stages - 1) if stages > 1
+                    else "launch" if passes == 1 else "step (%d kernels)" % passes),
             "steps_per_launch": steps_per_launch,
-            "kernel_avg_ms": launch_ms if passes == 1 else None,
-            "alg_bytes_per_cell": bpc, "copy_ceiling_GBs": ceiling,
+            "kernel_avg_ms": launch_ms if passes == 1 and stages == 1 else None,
+            "alg_bytes_per_cell": stages * bpc + rk_bytes, "copy_ceiling_GBs": ceiling,
             "frac_of_copy_ceiling": achieved / ceiling, "source_digest": digest}
     out = {
         "metric": "Gcell-updates/s", "value": value, "unit": "Gcell-updates/s",
@@ -398,7 +409,8 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
-                   "species": w.spec.ns, "storage": args.storage, "stencil": w.spec.stencil, "dt": w.spec.dt,
+                   "species": w.spec.ns, "storage": args.storage, "stencil": w.spec.stencil,
+                   "integrator": args.integrator, "dt": w.spec.dt,
                    "plan": plan, "wall_s": wall},
         "roofline": roof,
     }
