@@ -676,3 +676,32 @@ def test_rk_keeps_held_layers_and_rejects_clocked_wind(oracle, integrator):
                   {"ux": 1.0, "uy": 0.0, "uz": 1.0, "uz_period": 2.0}, integrator=integrator)
     with pytest.raises(ValueError):
         oracle.run(a, [c0], 1)
+
+
+# ------------------------------------------------------------------ P14
+# Counter-based random bits for stochastic rounding (oracle side).
+
+def test_philox_known_answers():
+    """Philox-2x32-10 against the known-answer vectors of its authors'
+    reference distribution."""
+    from oracle.stochastic import philox2x32_10
+    cases = [((0x00000000, 0x00000000), 0x00000000, (0xff1dae59, 0x6cd10df2)),
+             ((0xffffffff, 0xffffffff), 0xffffffff, (0x2c3f628b, 0xab4fd7ad)),
+             ((0x243f6a88, 0x85a308d3), 0x13198a2e, (0xdd7ce038, 0xf62a4c12))]
+    for (c0, c1), k, want in cases:
+        got = philox2x32_10(c0, c1, k)
+        assert (int(got[0]), int(got[1])) == want
+
+
+def test_bf16_stochastic_rounding_is_unbiased():
+    """Rounding up happens for exactly the random draws at or above 2^16
+    minus the discarded bits, so over all 2^16 draws the mean is x."""
+    from oracle.stochastic import bf16_stochastic
+    x = np.float32(1.0 - 2.0**-10)          # 3/4 of the way from 1 - 2^-8 to 1
+    r = np.arange(65536, dtype=np.uint32)
+    y = bf16_stochastic(np.full(65536, x), r)
+    assert set(np.unique(y).tolist()) == {1.0 - 2.0**-8, 1.0}
+    assert np.count_nonzero(y == 1.0) == 49152
+    assert np.mean(y.astype(np.float64)) == float(x)
+    z = bf16_stochastic(np.float32([0.5, -3.0]), np.uint32([65535, 65535]))
+    assert z.tolist() == [0.5, -3.0]         # representable values never move
