@@ -267,6 +267,23 @@ int rd_get_plan(const rd_grid *g, rd_plan *p);   /* the plan rd_step uses    */
  * without a model. */
 int rd_get_passes(const rd_grid *g, int32_t *out);
 
+/* rounding of stored BF16 values (rd_set_rounding) */
+enum { RD_ROUND_NEAREST = 0, RD_ROUND_STOCHASTIC = 1 };
+
+/* How a step rounds the values it stores into BF16 fields (the arithmetic
+ * stays FP32).  RD_ROUND_NEAREST (the default): round to nearest even.
+ * RD_ROUND_STOCHASTIC: round the magnitude up with probability (discarded low
+ * 16 bits) / 2^16, so the expected stored value is the FP32 result and
+ * increments smaller than half a BF16 unit do not stagnate.  The random bits
+ * are Philox-2x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) of counter (element
+ * index in the padded [nz][ny][pitch] layout, step index since rd_set_model)
+ * and key (low 32 bits of seed + species): the same inputs give the same bits
+ * on every plan and in graphs.  Kept across rd_set_model.  RD_EINVAL:
+ * unknown mode, or stochastic rounding with storage other than RD_BF16 or a
+ * Runge-Kutta model; RD_ESTATE: the grid is in a batch (batches refuse
+ * grids with stochastic rounding). */
+int rd_set_rounding(rd_grid *g, int32_t mode, uint64_t seed);
+
 /* Time candidate plans on this grid (trial_steps steps each, hipEvents on the
  * grid's stream), keep the fastest, store it in a per-process cache keyed by
  * shape, species, model and storage, and return it in *best.  The grid's state

@@ -65,6 +65,9 @@ struct StepArgs {
     StepClock* clk_out;           // clock of its output state
     int clk_pass;                 // this pass advances the clock
     double t0, dt64, wamp, wper, inv_h;
+    // stochastic rounding of BF16 stores: on/off, generator key (seed)
+    int sr;
+    unsigned sr_key;
 };
 
 // How a model's cell function gets its per-plane wind argument.
@@ -197,6 +200,56 @@ __device__ __forceinline__ void store_vec(void* base, long long idx, const float
 template <class S>
 __device__ __forceinline__ float load1(const void* base, long long idx) {
     return S::up(gload_ptr<typename S::T>(base)[idx]);
+}
+
+// ---- stochastic rounding of BF16 stores --------------------------------
+//
+// Counter-based random bits: Philox-2x32 with 10 rounds (Salmon, Moraes,
+// Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11): each
+// round multiplies the first counter word by 0xD256D193, the new first word
+// is the high half xor the key xor the second word, the new second word the
+// low half, and the key is bumped by 0x9E3779B9.  A stored element draws the
+// low 16 bits of the first output word for counter (element index in the
+// padded array, step index) and key (seed + species).
+__device__ __forceinline__ unsigned philox2x32_10(unsigned c0, unsigned c1, unsigned k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const unsigned hi = __umulhi(0xD256D193u, c0);
+        const unsigned lo = 0xD256D193u * c0;
+        c0 = hi ^ k ^ c1;
+        c1 = lo;
+        k += 0x9E3779B9u;
+    }
+    return c0;
+}
+
+// Stochastic rounding to BF16: add 16 random bits to the FP32 pattern and
+// keep the high half, so the magnitude rounds up with probability (low 16
+// bits) / 2^16 and the expected stored value is the FP32 one.  Infinities
+// and NaN round as to nearest.
+__device__ __forceinline__ uint16_t bf16_stochastic(float f, unsigned r16) {
+    const unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) >= 0x7f800000u) return StBF16::down(f);
+    return uint16_t((u + r16) >> 16);
+}
+
+// Store VX output values of species s (of this pass) at element idx in the
+// storage type, rounding stochastically when the grid asks for it.
+template <class S, int VX>
+__device__ __forceinline__ void store_field(const StepArgs& a, int s, long long idx, const float (&o)[VX]) {
+    if constexpr (std::is_same_v<S, StBF16>) {
+        if (a.sr) {
+            const unsigned n = unsigned(gload_ptr<StepClock>(a.clk_in)->n);
+            const unsigned key = a.sr_key + unsigned(a.sp0 + s);
+            Vec<uint16_t, VX> r;
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                r.v[i] = bf16_stochastic(o[i], philox2x32_10(unsigned(idx + i), n, key) & 0xffffu);
+            *(RD_GLOBAL Vec<uint16_t, VX>*)(gstore_ptr<uint16_t>(a.out[s]) + idx) = r;
+            return;
+        }
+    }
+    store_vec<S, VX>(a.out[s], idx, o);
 }
 
 // --------------------------------------------------------- cell arithmetic
@@ -410,17 +463,19 @@ __device__ __forceinline__ float plane_wind(const StepArgs& a, int z) {
 
 // One thread of the clock pass writes the clock of the step's output state:
 // n + 1 and u_z(t_{n+1})/h, in FP64 as the time is formed.
+// The clock also counts steps for stochastic rounding.
 template <class M>
 __device__ __forceinline__ void tick_clock(const StepArgs& a, bool first_thread) {
-    if constexpr (M::WIND == WIND_CLOCK) {
-        if (first_thread && a.clk_pass) {
-            const long long n = gload_ptr<StepClock>(a.clk_in)->n + 1;
+    if (first_thread && a.clk_pass && (M::WIND == WIND_CLOCK || a.sr)) {
+        const long long n = gload_ptr<StepClock>(a.clk_in)->n + 1;
+        double u = 0.0;
+        if constexpr (M::WIND == WIND_CLOCK) {
             const double t = a.t0 + double(n) * a.dt64;
-            const double u = a.wper != 0.0 ? a.wamp * sin(t / a.wper) : a.wamp;
-            StepClock* out = gstore_ptr<StepClock>(a.clk_out);
-            out->n = n;
-            out->uzh = float(u * a.inv_h);
+            u = a.wper != 0.0 ? a.wamp * sin(t / a.wper) : a.wamp;
         }
+        StepClock* out = gstore_ptr<StepClock>(a.clk_out);
+        out->n = n;
+        out->uzh = float(u * a.inv_h);
     }
 }
 
@@ -569,8 +624,12 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
 #pragma unroll
     for (int s = 0; s < M::NO; ++s) {
         const float v = held_out(a, s, x, y, z, o[s]);
-        if (M::f32_out(s)) gstore_ptr<float>(a.out[s])[idx] = v;
-        else gstore_ptr<typename S::T>(a.out[s])[idx] = S::down(v);
+        if (M::f32_out(s)) {
+            gstore_ptr<float>(a.out[s])[idx] = v;
+        } else {
+            const float w[1] = {v};
+            store_field<S, 1>(a, s, idx, w);
+        }
     }
 }
 
@@ -825,7 +884,7 @@ __device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64
 #pragma unroll
             for (int s = 0; s < NO; ++s) {
                 if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
-                else store_vec<S, VX>(a.out[s], idx, o[s]);
+                else store_field<S, VX>(a, s, idx, o[s]);
             }
         }
     }
@@ -1053,7 +1112,7 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
                     for (int s = 0; s < NO; ++s) {
                         if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
-                        else store_vec<S, VX>(a.out[s], idx, o[s]);
+                        else store_field<S, VX>(a, s, idx, o[s]);
                     }
                 }
             }

@@ -191,6 +191,8 @@ struct rd_grid {
     StepArgs rk_args[2][2];            // Runge-Kutta stage step: other parity -> stage
     StepArgs* d_args = nullptr;        // args then rk_args, in device memory
     int integrator = RD_EULER;
+    int sr_mode = RD_ROUND_NEAREST;    // rounding of BF16 stores
+    uint32_t sr_seed = 0;
     void* stage[RD_MAX_SPECIES] = {};  // Runge-Kutta stage buffers (allocated on demand)
     rd_plan plan{};                    // requested plan (kernel 0 = auto)
     rd_plan eff{};                     // plan in use
@@ -754,6 +756,8 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
     if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
     int rc = rd_validate_model(g->nx, g->ny, g->nz, g->ns, g->h, m);
     if (rc) return rc;
+    if (g->sr_mode == RD_ROUND_STOCHASTIC && m->integrator >= RD_RK2)
+        return fail(RD_EINVAL, "stochastic rounding takes forward Euler steps");
     RD_HIP(hipStreamSynchronize(g->stream));
     drop_graphs(g);
     free_model_arrays(g);
@@ -908,6 +912,11 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
             }
         }
     }
+    for (auto& row : g->args)
+        for (StepArgs& a : row) {
+            a.sr = g->sr_mode == RD_ROUND_STOCHASTIC ? 1 : 0;
+            a.sr_key = g->sr_seed;
+        }
     // Runge-Kutta: stage buffers, and the stage step's arguments -- the same
     // step reading the other parity's buffers and writing the stage buffers
     g->integrator = m->integrator >= RD_RK2 ? m->integrator : RD_EULER;
@@ -971,6 +980,31 @@ extern "C" int rd_get_passes(const rd_grid* g, int32_t* out) {
     if (!g || !out) return fail(RD_EINVAL, "NULL argument");
     if (!g->has_model) return fail(RD_ESTATE, "no model set");
     *out = g->npass;
+    return RD_OK;
+}
+
+extern "C" int rd_set_rounding(rd_grid* g, int32_t mode, uint64_t seed) {
+    if (!g) return fail(RD_EINVAL, "grid is NULL");
+    if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
+    if (mode != RD_ROUND_NEAREST && mode != RD_ROUND_STOCHASTIC) return fail(RD_EINVAL, "unknown rounding mode");
+    if (mode == RD_ROUND_STOCHASTIC && g->storage != RD_BF16)
+        return fail(RD_EINVAL, "stochastic rounding needs BF16 storage");
+    if (mode == RD_ROUND_STOCHASTIC && g->has_model && g->integrator >= RD_RK2)
+        return fail(RD_EINVAL, "stochastic rounding takes forward Euler steps");
+    RD_HIP(hipStreamSynchronize(g->stream));
+    g->sr_mode = mode;
+    g->sr_seed = uint32_t(seed);
+    if (!g->has_model) return RD_OK;
+    for (int par = 0; par < 2; ++par)
+        for (int k = 0; k < 2; ++k) {
+            for (StepArgs* a : {&g->args[par][k], &g->rk_args[par][k]}) {
+                a->sr = mode == RD_ROUND_STOCHASTIC ? 1 : 0;
+                a->sr_key = g->sr_seed;
+            }
+        }
+    drop_graphs(g);
+    RD_HIP(hipMemcpy(g->d_args, g->args, sizeof(g->args), hipMemcpyHostToDevice));
+    RD_HIP(hipMemcpy(g->d_args + 4, g->rk_args, sizeof(g->rk_args), hipMemcpyHostToDevice));
     return RD_OK;
 }
 
@@ -1360,6 +1394,7 @@ extern "C" int rd_batch_add(rd_batch* b, rd_grid* g, int64_t steps) {
         return fail(RD_EINVAL, "batches take 1-species diffusion or Brusselator grids");
     if (g->args[0][0].s19) return fail(RD_EINVAL, "batches take 7-point grids");
     if (g->integrator >= RD_RK2) return fail(RD_EINVAL, "batches take forward Euler grids");
+    if (g->sr_mode != RD_ROUND_NEAREST) return fail(RD_EINVAL, "batches take round-to-nearest grids");
     if (g->storage != b->storage) return fail(RD_EINVAL, "grid storage differs from the batch's");
     if (g->stream != b->stream) return fail(RD_EINVAL, "grid and batch must use the same stream");
     if (int(b->members.size()) >= b->max_grids) return fail(RD_EINVAL, "batch is full");

@@ -85,6 +85,7 @@ _SIGS = {
     "rd_set_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
     "rd_get_plan": (C.c_int, [C.c_void_p, C.POINTER(Plan)]),
     "rd_get_passes": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "rd_set_rounding": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint64]),
     "rd_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Plan)]),
     "rd_batch_create": (C.c_int, [C.c_int32, C.c_size_t, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "rd_batch_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
@@ -307,6 +308,10 @@ class Grid:
         n = C.c_int32()
         _check(lib().rd_get_passes(self._p, C.byref(n)))
         return n.value
+
+    def set_rounding(self, mode: str = "nearest", seed: int = 0) -> None:
+        """Rounding of BF16 stores: "nearest" (even) or "stochastic"."""
+        _check(lib().rd_set_rounding(self._p, {"nearest": 0, "stochastic": 1}[mode], int(seed)))
 
     def autotune(self, trial_steps: int = 10) -> Dict[str, int]:
         p = Plan()
