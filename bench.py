@@ -295,6 +295,8 @@ def main():
                     choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64",
                              "t1_diffusion192", "t1_turing192", "t1_front192", "t1_atmos192", "serve"])
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16", "both"])
+    ap.add_argument("--rounding", default="nearest", choices=["nearest", "stochastic"],
+                    help="rounding of BF16 stores (stochastic needs --storage bf16)")
     ap.add_argument("--integrator", default="euler", choices=["euler", "rk2", "rk3"],
                     help="forward Euler (Eq. (5)) or the SSP Runge-Kutta step of order 2 or 3")
     ap.add_argument("--stencil", type=int, default=7, choices=[7, 19],
@@ -342,6 +344,8 @@ def main():
                                                                      args.steps, args.warmup),
           file=sys.stderr, flush=True)
     g = rd.Grid.from_workload(w, storage=args.storage, stream=stream)
+    if args.rounding != "nearest":
+        g.set_rounding(args.rounding, 1)
     if args.plan:
         plan = json.loads(args.plan)
     elif args.no_autotune:
@@ -410,7 +414,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
                    "species": w.spec.ns, "storage": args.storage, "stencil": w.spec.stencil,
-                   "integrator": args.integrator, "dt": w.spec.dt,
+                   "integrator": args.integrator, "rounding": args.rounding, "dt": w.spec.dt,
                    "plan": plan, "wall_s": wall},
         "roofline": roof,
     }

@@ -68,6 +68,10 @@ struct StepArgs {
     // stochastic rounding of BF16 stores: on/off, generator key (seed)
     int sr;
     unsigned sr_key;
+    // Runge-Kutta stage: each stored state value v becomes b + w (v - b),
+    // b = rk_base[s] at the same element (w = 0: a plain Euler step)
+    const void* rk_base[MAXF];
+    float rk_w;
 };
 
 // How a model's cell function gets its per-plane wind argument.
@@ -233,10 +237,27 @@ __device__ __forceinline__ uint16_t bf16_stochastic(float f, unsigned r16) {
     return uint16_t((u + r16) >> 16);
 }
 
-// Store VX output values of species s (of this pass) at element idx in the
-// storage type, rounding stochastically when the grid asks for it.
+// A Runge-Kutta stage's combination of an Euler result v with the state b
+// at the same element: b + w (v - b), which keeps a held value exactly.
 template <class S, int VX>
-__device__ __forceinline__ void store_field(const StepArgs& a, int s, long long idx, const float (&o)[VX]) {
+__device__ __forceinline__ void rk_blend(const StepArgs& a, int s, long long idx, float (&o)[VX]) {
+    if (a.rk_w != 0.f) {
+        float b[VX];
+        load_vec<S, VX>(a.rk_base[s], idx, b);
+#pragma unroll
+        for (int i = 0; i < VX; ++i) o[i] = __fmaf_rn(a.rk_w, o[i] - b[i], b[i]);
+    }
+}
+
+// Store VX output values of species s (of this pass) at element idx in the
+// storage type (after a Runge-Kutta stage's combination), rounding
+// stochastically when the grid asks for it.
+template <class S, int VX>
+__device__ __forceinline__ void store_field(const StepArgs& a, int s, long long idx, const float (&v)[VX]) {
+    float o[VX];
+#pragma unroll
+    for (int i = 0; i < VX; ++i) o[i] = v[i];
+    rk_blend<S, VX>(a, s, idx, o);
     if constexpr (std::is_same_v<S, StBF16>) {
         if (a.sr) {
             const unsigned n = unsigned(gload_ptr<StepClock>(a.clk_in)->n);
@@ -1655,7 +1676,10 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
                         if (y < a.ny && (c < NCH - 1 || lane <= last)) {
                             const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
 #pragma unroll
-                            for (int s = 0; s < NO; ++s) store_vec<StF32, 4>(a.out[s], idx, o[s]);
+                            for (int s = 0; s < NO; ++s) {
+                                if (!M::f32_out(s)) rk_blend<StF32, 4>(a, s, idx, o[s]);
+                                store_vec<StF32, 4>(a.out[s], idx, o[s]);
+                            }
                         }
                     }
                 }
@@ -2156,22 +2180,6 @@ __global__ __launch_bounds__(256) void unpack_kernel(const void* src, DstT* dst,
 
 // One 16-byte element per thread, streamed with non-temporal load/store:
 // the read+write bandwidth ceiling a kernel can reach.
-// Runge-Kutta stage combination over whole arrays, four elements a thread:
-// out = a + w (c - a) (out may be a).  A held layer has a == c, so it
-// keeps its value exactly.
-template <class S>
-__global__ __launch_bounds__(256) void rk_combine_kernel(const void* a, const void* c, void* out, float w,
-                                                        long long n4) {
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n4; i += (long long)gridDim.x * 256) {
-        float va[4], vc[4], o[4];
-        load_vec<S, 4>(a, i * 4, va);
-        load_vec<S, 4>(c, i * 4, vc);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = __fmaf_rn(w, vc[k] - va[k], va[k]);
-        store_vec<S, 4>(out, i * 4, o);
-    }
-}
-
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
                                                    float4* __restrict__ dst, long long n4) {
     typedef float v4f __attribute__((ext_vector_type(4)));

@@ -188,12 +188,13 @@ struct rd_grid {
     int npass = 0;
     int pass_pm[2] = {-1, -1};
     StepArgs args[2][2];               // [input parity][pass], host copy
-    StepArgs rk_args[2][2];            // Runge-Kutta stage step: other parity -> stage
-    StepArgs* d_args = nullptr;        // args then rk_args, in device memory
+    StepArgs rk_args[2][2];            // Runge-Kutta stage 2 (see launch_rk_step)
+    StepArgs rk3_args[2][2];           // Runge-Kutta stage 3 (order 3 only)
+    StepArgs* d_args = nullptr;        // args, rk_args, rk3_args, in device memory
     int integrator = RD_EULER;
     int sr_mode = RD_ROUND_NEAREST;    // rounding of BF16 stores
     uint32_t sr_seed = 0;
-    void* stage[RD_MAX_SPECIES] = {};  // Runge-Kutta stage buffers (allocated on demand)
+    void* stage[RD_MAX_SPECIES] = {};  // order-3 Runge-Kutta stage buffers (allocated on demand)
     rd_plan plan{};                    // requested plan (kernel 0 = auto)
     rd_plan eff{};                     // plan in use
     int cfg = -1;
@@ -397,6 +398,7 @@ int apply_plan(rd_grid* g) {
                 p.kernel == RD_KERNEL_LDS2) {
                 g->blocks[k] = set_tiling(a, p);
                 (void)set_tiling(g->rk_args[par][k], p);
+                (void)set_tiling(g->rk3_args[par][k], p);
             } else {
                 g->blocks[k] = 0;
             }
@@ -409,6 +411,7 @@ int apply_plan(rd_grid* g) {
     drop_graphs(g);
     RD_HIP(hipMemcpy(g->d_args, g->args, sizeof(g->args), hipMemcpyHostToDevice));
     RD_HIP(hipMemcpy(g->d_args + 4, g->rk_args, sizeof(g->rk_args), hipMemcpyHostToDevice));
+    RD_HIP(hipMemcpy(g->d_args + 8, g->rk3_args, sizeof(g->rk3_args), hipMemcpyHostToDevice));
     return RD_OK;
 }
 
@@ -422,59 +425,29 @@ int launch_one_step(rd_grid* g, int parity) {
     return RD_OK;
 }
 
-// Euler step of a Runge-Kutta stage: from the other parity's buffers into
-// the stage buffers.
-int launch_stage_step(rd_grid* g, int parity) {
+// One set of step arguments (`set` 1: rk_args, 2: rk3_args) for the grid's
+// passes.
+int launch_set(rd_grid* g, int set, int parity) {
+    const StepArgs(&h)[2][2] = set == 1 ? g->rk_args : g->rk3_args;
     for (int k = 0; k < g->npass; ++k) {
-        const hipError_t e = launch_pass(g->storage, g->pass_pm[k], g->eff.kernel, g->cfg,
-                                         g->rk_args[parity][k], g->d_args + 4 + parity * 2 + k,
-                                         g->blocks[k], g->stream);
+        const hipError_t e = launch_pass(g->storage, g->pass_pm[k], g->eff.kernel, g->cfg, h[parity][k],
+                                         g->d_args + 4 * set + parity * 2 + k, g->blocks[k], g->stream);
         if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
     return RD_OK;
 }
 
-// out = a + w (c - a) for every species' whole array.
-int rk_combine(rd_grid* g, void* const* a, void* const* c, void* const* out, float w) {
-    const long long n4 = (long long)(g->elems / 4);
-    const unsigned blocks = unsigned(std::min<long long>((n4 + 255) / 256, 8LL * num_cus()));
-    for (int s = 0; s < g->ns; ++s) {
-        switch (g->storage) {
-        case RD_F32:
-            hipLaunchKernelGGL((rk_combine_kernel<StF32>), dim3(blocks), dim3(256), 0, g->stream, a[s], c[s],
-                               out[s], w, n4);
-            break;
-        case RD_BF16:
-            hipLaunchKernelGGL((rk_combine_kernel<StBF16>), dim3(blocks), dim3(256), 0, g->stream, a[s], c[s],
-                               out[s], w, n4);
-            break;
-        default:
-            hipLaunchKernelGGL((rk_combine_kernel<StF16>), dim3(blocks), dim3(256), 0, g->stream, a[s], c[s],
-                               out[s], w, n4);
-            break;
-        }
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
-    }
-    return RD_OK;
-}
-
-// One strong-stability-preserving Runge-Kutta step from Euler steps E; the
-// state stays in the current parity's buffers A, B is the other parity, C
-// the stage buffers.  Order 2: B = E(A), C = E(B), A = A + (C - A)/2.
-// Order 3: then B = A + (C - A)/4, C = E(B), A = A + 2 (C - A)/3.
+// One strong-stability-preserving Runge-Kutta step from Euler steps E, the
+// combinations fused into the stages' stores (each stored value v becomes
+// A + w (v - A), A the state at the same element).  The state stays in the
+// current parity's buffers A; B is the other parity, C the stage buffers.
+//   order 2:  B = E(A);  A = A + (E(B) - A)/2
+//   order 3:  B = E(A);  C = A + (E(B) - A)/4;  A = A + 2 (E(C) - A)/3
 int launch_rk_step(rd_grid* g) {
     const int p = g->cur;
-    void* const* A = g->buf[p];
-    void* const* B = g->buf[p ^ 1];
-    void* const* C = g->stage;
     int rc = launch_one_step(g, p);
-    if (!rc) rc = launch_stage_step(g, p);
-    if (rc) return rc;
-    if (g->integrator == RD_RK2) return rk_combine(g, A, C, A, 0.5f);
-    rc = rk_combine(g, A, C, B, 0.25f);
-    if (!rc) rc = launch_stage_step(g, p);
-    if (!rc) rc = rk_combine(g, A, C, A, float(2.0 / 3.0));
+    if (!rc) rc = launch_set(g, 1, p);
+    if (!rc && g->integrator == RD_RK3) rc = launch_set(g, 2, p);
     return rc;
 }
 
@@ -576,7 +549,7 @@ extern "C" size_t rd_grid_bytes(int64_t nx, int64_t ny, int64_t nz, int32_t nspe
     const size_t e = field_elems(nx, ny, nz);
     size_t b = 2 * size_t(nspecies) * e * elem_size(storage_dtype);
     if (with_aux) b += e * sizeof(float);
-    b += 8 * sizeof(StepArgs) + 2 * sizeof(StepClock) + 2 * kRedBlocks * sizeof(double) + 2 * sizeof(double);
+    b += 12 * sizeof(StepArgs) + 2 * sizeof(StepClock) + 2 * kRedBlocks * sizeof(double) + 2 * sizeof(double);
     return b;
 }
 
@@ -722,7 +695,7 @@ extern "C" int rd_create_grid(int64_t nx, int64_t ny, int64_t nz, int32_t nspeci
             if (hipMemsetAsync(g->buf[p][s], 0, bytes, g->stream) != hipSuccess)
                 return cleanup(RD_EDEVICE, "hipMemsetAsync failed");
         }
-    if (hipMalloc(&g->d_args, sizeof(g->args) + sizeof(g->rk_args)) != hipSuccess ||
+    if (hipMalloc(&g->d_args, sizeof(g->args) + sizeof(g->rk_args) + sizeof(g->rk3_args)) != hipSuccess ||
         hipMalloc(&g->d_clock, 2 * sizeof(StepClock)) != hipSuccess ||
         hipMalloc(&g->d_part, 2 * kRedBlocks * sizeof(double)) != hipSuccess ||
         hipMalloc(&g->d_red, 2 * sizeof(double)) != hipSuccess)
@@ -917,10 +890,11 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
             a.sr = g->sr_mode == RD_ROUND_STOCHASTIC ? 1 : 0;
             a.sr_key = g->sr_seed;
         }
-    // Runge-Kutta: stage buffers, and the stage step's arguments -- the same
-    // step reading the other parity's buffers and writing the stage buffers
+    // Runge-Kutta stages: the same step with other buffers, its stored state
+    // blended with the current state A (see launch_rk_step).  The chemical
+    // potential pass of the front model is no state update and is not blended.
     g->integrator = m->integrator >= RD_RK2 ? m->integrator : RD_EULER;
-    if (g->integrator >= RD_RK2) {
+    if (g->integrator == RD_RK3) {
         const size_t bytes = g->elems * elem_size(g->storage);
         for (int s = 0; s < ns; ++s)
             if (!g->stage[s]) {
@@ -930,13 +904,25 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
     }
     for (int par = 0; par < 2; ++par)
         for (int k = 0; k < 2; ++k) {
-            StepArgs r = g->args[par][k];
+            const bool chmu = m->model == RD_MODEL_FRONT_CH && k == 0;
+            StepArgs r2 = g->args[par][k];     // stage 2: B in; A (order 2) or C out
+            StepArgs r3 = g->args[par][k];     // stage 3 (order 3): C in, A out
             for (int f = 0; f < MAXF; ++f)
                 for (int s = 0; s < ns; ++s) {
-                    if (r.in[f] == g->buf[par][s]) r.in[f] = g->buf[par ^ 1][s];
-                    if (r.out[f] == g->buf[par ^ 1][s]) r.out[f] = g->stage[s];
+                    if (g->args[par][k].in[f] == g->buf[par][s]) {
+                        r2.in[f] = g->buf[par ^ 1][s];
+                        r3.in[f] = g->stage[s];
+                    }
+                    if (g->args[par][k].out[f] == g->buf[par ^ 1][s]) {
+                        r2.out[f] = g->integrator == RD_RK3 ? g->stage[s] : g->buf[par][s];
+                        r3.out[f] = g->buf[par][s];
+                        r2.rk_base[f] = r3.rk_base[f] = g->buf[par][s];
+                    }
                 }
-            g->rk_args[par][k] = r;
+            r2.rk_w = chmu ? 0.f : (g->integrator == RD_RK3 ? 0.25f : 0.5f);
+            r3.rk_w = chmu ? 0.f : float(2.0 / 3.0);
+            g->rk_args[par][k] = r2;
+            g->rk3_args[par][k] = r3;
         }
     g->model = m->model;
     if (m->model == RD_MODEL_FRONT_CH) {
@@ -997,7 +983,7 @@ extern "C" int rd_set_rounding(rd_grid* g, int32_t mode, uint64_t seed) {
     if (!g->has_model) return RD_OK;
     for (int par = 0; par < 2; ++par)
         for (int k = 0; k < 2; ++k) {
-            for (StepArgs* a : {&g->args[par][k], &g->rk_args[par][k]}) {
+            for (StepArgs* a : {&g->args[par][k], &g->rk_args[par][k], &g->rk3_args[par][k]}) {
                 a->sr = mode == RD_ROUND_STOCHASTIC ? 1 : 0;
                 a->sr_key = g->sr_seed;
             }
@@ -1005,6 +991,7 @@ extern "C" int rd_set_rounding(rd_grid* g, int32_t mode, uint64_t seed) {
     drop_graphs(g);
     RD_HIP(hipMemcpy(g->d_args, g->args, sizeof(g->args), hipMemcpyHostToDevice));
     RD_HIP(hipMemcpy(g->d_args + 4, g->rk_args, sizeof(g->rk_args), hipMemcpyHostToDevice));
+    RD_HIP(hipMemcpy(g->d_args + 8, g->rk3_args, sizeof(g->rk3_args), hipMemcpyHostToDevice));
     return RD_OK;
 }
 
