@@ -380,11 +380,12 @@ def main():
     bpc = alg_bytes_per_cell(args.workload, args.storage)
     passes = g.passes()
     steps_per_launch = 2 if plan.get("kernel") == 5 else 1     # two-step (temporally blocked) plan
-    # a Runge-Kutta step runs 2 or 3 Euler stages and 1 or 2 combinations,
-    # each reading two arrays and writing one per species
+    # a Runge-Kutta step runs 2 or 3 Euler stages; every stage after the first
+    # also reads the current state once per species (its combination is
+    # fused into the store)
     stages = {"euler": 1, "rk2": 2, "rk3": 3}[args.integrator]
     es = 4 if args.storage == "f32" else 2
-    rk_bytes = (stages - 1) * 3 * w.spec.ns * es
+    rk_bytes = (stages - 1) * w.spec.ns * es
     # dominant kernel: the step kernel.  A launch reads and writes every field
     # once (for one step, or two with a two-step plan); with one pass its
     # average launch duration is the event-timed time of the steps it covers.
@@ -401,7 +402,7 @@ def main():
     ceiling = copy_ceiling(torch, stream, COPY_PROBE_BYTES)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "per": ("step (%d Euler stages + %d combinations)" % (stages, stages - 1) if stages > 1
+            "per": ("step (%d fused Runge-Kutta stages)" % stages if stages > 1
                     else "launch" if passes == 1 else "step (%d kernels)" % passes),
             "steps_per_launch": steps_per_launch,
             "kernel_avg_ms": launch_ms if passes == 1 and stages == 1 else None,

@@ -127,10 +127,12 @@ enum { RD_FACE_XLO = 0, RD_FACE_XHI, RD_FACE_YLO, RD_FACE_YHI, RD_FACE_ZLO, RD_F
  *              (E(E(c)) - c)/4,  c' = c + 2 (E(u) - c)/3 (the paper notes
  *              that more accurate steppers exist, section 2).  Each Euler
  *              stage keeps held layers, and the combinations keep them
- *              exactly.  A Runge-Kutta grid allocates one more buffer per
- *              species, takes no two-step plan (RD_KERNEL_LDS2), is not
- *              batched, and rejects the atmospheric model (its wind depends
- *              on time) with RD_EINVAL.
+ *              exactly.  The combinations are fused into the stages' stores
+ *              (each stored value v becomes c + w (v - c) at the same
+ *              element).  An order-3 grid allocates one more buffer per
+ *              species.  Runge-Kutta grids take no two-step plan
+ *              (RD_KERNEL_LDS2), are not batched, and refuse the atmospheric
+ *              model (its wind depends on time) with RD_EINVAL.
  * dt           time step; rd_set_model rejects a dt outside the stable range
  *              (RD_EUNSTABLE): per species dt*(2*sum_d K_d/h^2 + max u/h) <= 1
  *              (19-point: dt*(4 D/h^2 + max u/h) <= 1; for ATMOS, max u is
