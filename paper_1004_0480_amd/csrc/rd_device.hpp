@@ -1435,20 +1435,32 @@ __device__ __forceinline__ void ring_barrier() {
     asm volatile("" ::: "memory");
 }
 
-template <int NF, int NCH, int BY, int D>
+// Ring of D plane slots of NF fields x (BY+2) rows x 256*NCH cells of ES
+// bytes.  A lane loads 16 bytes (16/ES cells) per instruction, so a row takes
+// NQ loads: NCH for FP32, half as many for 2-byte cells.
+template <int NF, int NCH, int BY, int D, int ES = 4>
 struct LdsRing {
-    static constexpr int ROWS = BY + 2, TXT = 256 * NCH, SLOT = NF * ROWS * TXT;
-    static constexpr int CH = NF * ROWS * NCH;                 // 1 KB loads per plane
-    static constexpr long long BYTES = 4LL * D * SLOT;
+    static constexpr int ROWS = BY + 2, TXT = 256 * NCH, SLOT = NF * ROWS * TXT;   // cells
+    static constexpr int CPL = 16 / ES, CPQ = 64 * CPL;        // cells per lane / per load
+    static constexpr int NQ = (TXT + CPQ - 1) / CPQ;           // loads per row
+    static constexpr int CH = NF * ROWS * NQ;                  // loads per plane
+    static constexpr int SLOT_W = SLOT * ES / 4;               // a slot in 4-byte words
+    static constexpr long long BYTES = (long long)ES * D * SLOT;
     static constexpr bool FITS = BYTES <= 160 * 1024 && (D - 4) * CH <= 63 && D >= 4;
 };
 
-template <class M, int NCH, int BY, int WC, int D>
+// (The body is compiled for the device only: the host compiler fails to
+// reuse this specialization once a kernel of each stencil form asked for it.)
+template <class M, class S, int NCH, int BY, int WC, int D>
 __device__ __forceinline__ void lds_producer(const StepArgs& a, RD_LDS float* ring, int yb, int z0, int z1) {
-    using R = LdsRing<M::NF, NCH, BY, D>;
-    constexpr int NF = M::NF, ROWS = R::ROWS, TXT = R::TXT;
+#ifndef __HIP_DEVICE_COMPILE__
+    (void)a, (void)ring, (void)yb, (void)z0, (void)z1;
+#else
+    using T = typename S::T;
+    using R = LdsRing<M::NF, NCH, BY, D, int(sizeof(T))>;
+    constexpr int NF = M::NF, ROWS = R::ROWS, TXT = R::TXT, CPL = R::CPL, CPQ = R::CPQ, NQ = R::NQ;
     const int lane = threadIdx.x & 63;
-    const bool in_row = lane < ((a.nx - 256 * (NCH - 1)) >> 2);   // of the last chunk
+    const bool in_row = lane * CPL < a.nx - CPQ * (NQ - 1);      // of a row's last load
     // grid row of LDS row j is yb - 1 + j, resolved by the face rules
     int ridx[NF][ROWS];
 #pragma unroll
@@ -1460,21 +1472,22 @@ __device__ __forceinline__ void lds_producer(const StepArgs& a, RD_LDS float* ri
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const int pz = resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]).idx;
-            const RD_GLOBAL float* base = gload_ptr<float>(a.in[f]) + (long long)pz * a.plane + lane * 4;
+            const RD_GLOBAL T* base = gload_ptr<T>(a.in[f]) + (long long)pz * a.plane + lane * CPL;
+            RD_LDS T* slot_t = (RD_LDS T*)slot;
 #pragma unroll
             for (int j = 0; j < ROWS; ++j)
 #pragma unroll
-                for (int c = 0; c < NCH; ++c)
-                    if (c < NCH - 1 || in_row)
-                        __builtin_amdgcn_global_load_lds(base + (long long)ridx[f][j] * a.pitch + c * 256,
-                                                         (RD_LDS void*)(slot + (f * ROWS + j) * TXT + c * 256), 16, 0,
+                for (int q = 0; q < NQ; ++q)
+                    if (q < NQ - 1 || in_row)
+                        __builtin_amdgcn_global_load_lds(base + (long long)ridx[f][j] * a.pitch + q * CPQ,
+                                                         (RD_LDS void*)(slot_t + (f * ROWS + j) * TXT + q * CPQ), 16, 0,
                                                          0);
         }
     };
     // planes z0-1 .. z0+D-3 into slots 0 .. D-2; plane p lives in slot (p - z0 + 1) % D
 #pragma unroll
     for (int k = 0; k < D - 1; ++k)
-        if (z0 - 1 + k <= z1) issue(ring + k * R::SLOT, z0 - 1 + k);
+        if (z0 - 1 + k <= z1) issue(ring + k * R::SLOT_W, z0 - 1 + k);
     for (int zb = z0; zb < z1; zb += D) {
 #pragma unroll
         for (int J = 0; J < D; ++J) {
@@ -1484,16 +1497,19 @@ __device__ __forceinline__ void lds_producer(const StepArgs& a, RD_LDS float* ri
                 vm_wait_steps<R::CH, D - 4>(min(D - 4, z1 - z - 1));
                 ring_barrier();
                 // every consumer is past plane z-1, so the slot of plane z-2 is free
-                if (z + D - 2 <= z1) issue(ring + ((J + D - 1) % D) * R::SLOT, z + D - 2);
+                if (z + D - 2 <= z1) issue(ring + ((J + D - 1) % D) * R::SLOT_W, z + D - 2);
             }
         }
     }
+#endif
 }
 
-template <class M, int NCH, int BY, int WC, int D, bool S19>
-__device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS float* ring, int cw, int yb, int z0,
+template <class M, class ST, int NCH, int BY, int WC, int D, bool S19>
+__device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS float* ring_w, int cw, int yb, int z0,
                                              int z1) {
-    using R = LdsRing<M::NF, NCH, BY, D>;
+    using T = typename ST::T;
+    using R = LdsRing<M::NF, NCH, BY, D, int(sizeof(T))>;
+    const RD_LDS T* ring = (const RD_LDS T*)ring_w;     // cells of the storage type
     constexpr int NF = M::NF, NO = M::NO, TXT = R::TXT, RY = BY / WC;
     using NBT = std::conditional_t<S19, Nb19, Nb>;
     const int lane = threadIdx.x & 63;
@@ -1545,7 +1561,21 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
     // wave's own rows for the 7-point form (halo = false).
     using Plane = float[NF][RY + 2][NCH][4];
     Plane PA, PB, PC;
-    auto load_plane = [&](const RD_LDS float* S, Plane& v, bool halo) __attribute__((always_inline)) {
+    // four cells of a lane: one 16-byte LDS read (FP32) or one 8-byte read
+    // unpacked to FP32 (2-byte storage)
+    auto ld4 = [&](const RD_LDS T* q, float (&o)[4]) __attribute__((always_inline)) {
+        if constexpr (sizeof(T) == 4) {
+            lds_ld4((const RD_LDS float*)q, o);
+        } else {
+            typedef unsigned lds_v2 __attribute__((ext_vector_type(2)));
+            const lds_v2 t = *(const RD_LDS lds_v2*)q;
+            o[0] = ST::up(T(t.x & 0xffffu));
+            o[1] = ST::up(T(t.x >> 16));
+            o[2] = ST::up(T(t.y & 0xffffu));
+            o[3] = ST::up(T(t.y >> 16));
+        }
+    };
+    auto load_plane = [&](const RD_LDS T* P, Plane& v, bool halo) __attribute__((always_inline)) {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -1553,7 +1583,7 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
 #pragma unroll
                 for (int r = 0; r < RY + 2; ++r)
                     if (halo || (r > 0 && r <= RY))
-                        lds_ld4(S + (f * R::ROWS + r0 + r) * TXT + c * 256 + lane * 4, v[f][r][c]);
+                        ld4(P + (f * R::ROWS + r0 + r) * TXT + c * 256 + lane * 4, v[f][r][c]);
     };
     // boundary rules that replace loaded values (fixed or held rows, the
     // planes at and beyond the z faces, x faces)
@@ -1677,8 +1707,8 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
                             const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
 #pragma unroll
                             for (int s = 0; s < NO; ++s) {
-                                if (!M::f32_out(s)) rk_blend<StF32, 4>(a, s, idx, o[s]);
-                                store_vec<StF32, 4>(a.out[s], idx, o[s]);
+                                if (M::f32_out(s)) store_vec<StF32, 4>(a.out[s], idx, o[s]);
+                                else store_field<ST, 4>(a, s, idx, o[s]);
                             }
                         }
                     }
@@ -1695,11 +1725,11 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
     }
 }
 
-template <class M, int NCH, int BY, int WC, int D, bool S19>
+template <class M, class S, int NCH, int BY, int WC, int D, bool S19>
 __global__ __launch_bounds__(64 * (WC + 1)) void lds_kernel(const StepArgs* __restrict__ pa) {
-    using R = LdsRing<M::NF, NCH, BY, D>;
+    using R = LdsRing<M::NF, NCH, BY, D, int(sizeof(typename S::T))>;
     static_assert(R::FITS && BY % WC == 0, "ring shape does not fit");
-    __shared__ __attribute__((aligned(16))) float ring[D][R::SLOT];
+    __shared__ __attribute__((aligned(16))) float ring[D * R::SLOT_W];
     const StepArgs& a = *pa;
     tick_clock<M>(a, (blockIdx.x | threadIdx.x) == 0);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1707,9 +1737,9 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds_kernel(const StepArgs* __re
     const int yb = tc.y * BY;
     const int z0 = tc.z * a.cz;
     const int z1 = min(z0 + a.cz, a.nz);
-    RD_LDS float* base = (RD_LDS float*)&ring[0][0];
-    if (w == 0) lds_producer<M, NCH, BY, WC, D>(a, base, yb, z0, z1);
-    else lds_consumer<M, NCH, BY, WC, D, S19>(a, base, w - 1, yb, z0, z1);
+    RD_LDS float* base = (RD_LDS float*)&ring[0];
+    if (w == 0) lds_producer<M, S, NCH, BY, WC, D>(a, base, yb, z0, z1);
+    else lds_consumer<M, S, NCH, BY, WC, D, S19>(a, base, w - 1, yb, z0, z1);
 }
 
 // ---- two steps per launch (temporal blocking) on the LDS ring ---------------

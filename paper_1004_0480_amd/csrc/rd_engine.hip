@@ -263,8 +263,10 @@ long long set_tiling(StepArgs& a, const rd_plan& p) {
 }
 
 // The single-step LDS ring takes rows of 256*(nch-1) < nx <= 256*nch cells,
-// nx a multiple of 4 (whole 16-byte lane loads).
-bool ring_row_fits(int64_t nx, int nch) { return nx <= 256 * nch && nx > 256 * (nch - 1) && nx % 4 == 0; }
+// whole 16-byte lane loads: nx a multiple of 4 (FP32) or 8 (2-byte cells).
+bool ring_row_fits(const rd_grid* g, int nch) {
+    return g->nx <= 256 * nch && g->nx > 256 * (nch - 1) && g->nx % (g->storage == RD_F32 ? 4 : 8) == 0;
+}
 
 // Default plan: the plane-block kernel with the compiled slab shape that
 // wastes the fewest lanes and rows (ties: wider rows, one row per wave,
@@ -276,7 +278,7 @@ rd_plan heuristic_plan(const rd_grid* g) {
         // 19-point: the first LDS-ring shape this grid and model take, else direct
         for (int i = 0; i < kNumLdsCfgs; ++i) {
             const LdsCfg c = kLdsCfgs[i];
-            bool ok = ring_row_fits(g->nx, c.nch);
+            bool ok = ring_row_fits(g, c.nch);
             for (int k = 0; k < g->npass; ++k) ok = ok && lds_ok(g->storage, g->pass_pm[k], i);
             if (!ok) continue;
             best.kernel = RD_KERNEL_LDS;
@@ -348,8 +350,9 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
     if (p.kernel == RD_KERNEL_LDS) {
         const int cfg = (p.vx == 4 || p.vx == 8) ? lds_cfg_index(p.vx / 4, p.ry, p.waves, p.prefetch) : -1;
         if (cfg < 0) return fail(RD_EINVAL, "LDS ring shape not available");
-        if (!ring_row_fits(g->nx, p.vx / 4))
-            return fail(RD_EINVAL, "the LDS ring kernel needs 64*vx - 256 < nx <= 64*vx, nx a multiple of 4");
+        if (!ring_row_fits(g, p.vx / 4))
+            return fail(RD_EINVAL,
+                        "the LDS ring kernel needs 64*vx - 256 < nx <= 64*vx, nx a multiple of 4 (FP32) or 8 (BF16)");
         for (int k = 0; k < g->npass; ++k)
             if (!lds_ok(g->storage, g->pass_pm[k], cfg))
                 return fail(RD_EINVAL, "LDS ring shape not compiled for this model and storage");
@@ -1230,7 +1233,7 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     }
     for (int i = 0; i < kNumLdsCfgs; ++i) {
         const LdsCfg c = kLdsCfgs[i];
-        if (!ring_row_fits(g->nx, c.nch)) continue;
+        if (!ring_row_fits(g, c.nch)) continue;
         bool ok = true;
         for (int k = 0; k < g->npass; ++k) ok = ok && lds_ok(g->storage, g->pass_pm[k], i);
         if (!ok) continue;

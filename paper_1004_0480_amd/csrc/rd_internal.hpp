@@ -112,14 +112,21 @@ constexpr int pm_fields(int pm) {
 // a ring that fits the LDS and the vmcnt range; models of one or two fields
 // take the first shapes, the two passes of the front model the four-field
 // ones (both passes of a step share one plan).
+// BF16 storage takes the ring with 2-byte cells for models of one or two
+// fields, on the four shapes that serve those best in FP32.
 constexpr bool lds_ok(int storage, int pm, int i) {
-    if (storage != ST_F32 || i < 0 || i >= kNumLdsCfgs) return false;
+    if (i < 0 || i >= kNumLdsCfgs) return false;
     const bool front = pm == PM_CHMU || pm == PM_FRONT;
-    if (front != (i >= kFirstLds4Cfg) || (!front && pm_fields(pm) > 2)) return false;
+    if (storage == ST_BF16) {
+        if (front || pm_fields(pm) > 2 || !(i == 1 || i == 4 || i == 7 || i == 9)) return false;
+    } else if (storage != ST_F32 || front != (i >= kFirstLds4Cfg) || (!front && pm_fields(pm) > 2)) {
+        return false;
+    }
     const LdsCfg c = kLdsCfgs[i];
-    const int nf = pm_fields(pm), rows = c.by + 2;
-    const long long bytes = 4LL * c.d * nf * rows * 256 * c.nch;
-    return bytes <= 160 * 1024 && (c.d - 4) * nf * rows * c.nch <= 63 && c.d >= 4 && c.by % c.wc == 0;
+    const int es = storage == ST_F32 ? 4 : 2, nf = pm_fields(pm), rows = c.by + 2;
+    const int nq = (256 * c.nch * es + 1023) / 1024;            // 16-byte-per-lane loads per row
+    const long long bytes = 1LL * es * c.d * nf * rows * 256 * c.nch;
+    return bytes <= 160 * 1024 && (c.d - 4) * nf * rows * nq <= 63 && c.d >= 4 && c.by % c.wc == 0;
 }
 
 // Two-steps-per-launch shape i: FP32, diffusion or Brusselator (no point

@@ -67,7 +67,7 @@ template <class M, int I, bool S19>
 hipError_t run_lds(const StepArgs* d, long long blocks, hipStream_t s) {
     if constexpr (lds_ok(kStorage, PmOf<M>::v, I)) {
         constexpr LdsCfg c = kLdsCfgs[I];
-        hipLaunchKernelGGL((lds_kernel<M, c.nch, c.by, c.wc, c.d, S19>), dim3((unsigned)blocks),
+        hipLaunchKernelGGL((lds_kernel<M, S, c.nch, c.by, c.wc, c.d, S19>), dim3((unsigned)blocks),
                            dim3(64 * (c.wc + 1)), 0, s, d);
         return hipGetLastError();
     } else {

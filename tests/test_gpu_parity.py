@@ -681,6 +681,51 @@ def test_partial_ring_rows_every_plan(case):
             assert np.array_equal(got[s], base[s]), (case, plan, s)
 
 
+@pytest.mark.parametrize("case", ["bruss256", "diff512", "poll512", "faces200_held", "diff192_19", "bruss384_19"])
+def test_bf16_ring_every_plan(case):
+    """BF16 storage on the LDS ring (2-byte cells, 8 per 16-byte load, rows
+    that end inside a load): every plan gives the same bits, and a single
+    step is within one BF16 unit of the oracle's step rounded to BF16."""
+    rng = np.random.default_rng(sum(map(ord, case)))
+    if case == "bruss256":
+        w = W.make_workload("brusselator256", shape=(6, 10, 256))
+    elif case == "diff512":
+        w = W.make_workload("diffusion512", shape=(7, 9, 512))
+    elif case == "poll512":
+        w = W.make_workload("pollutant512", shape=(8, 9, 512))
+        w.fields = [rng.uniform(0, 1, w.shape) for _ in range(4)]
+    elif case == "faces200_held":
+        shape = (8, 9, 200)
+        faces = [(HELD, 1.0), (GHOST, -0.5), (PERIODIC, 0), (PERIODIC, 0), (GHOST, 2.0), (HELD, -1.0)]
+        w = W.Workload(case, shape, bc_spec(2, faces, K=(1.0, 1.0, 1.0), dt=0.1),
+                       [rng.uniform(0, 1, shape) for _ in range(2)], 6, 0)
+    elif case == "diff192_19":
+        shape = (7, 9, 192)
+        spec = bc_spec(1, [(MIRROR, 0)] * 6, K=(1.0, 1.0, 1.0), dt=0.1)
+        spec.stencil = 19
+        w = W.Workload(case, shape, spec, [rng.uniform(0, 1, shape)], 6, 0)
+    else:
+        w = W.make_workload("brusselator256", shape=(6, 8, 384))
+        w.spec.stencil = 19
+    fields = [round_bf16(f) for f in w.fields]
+    w = W.Workload(w.name, w.shape, w.spec, fields, 6, 0)
+    plans = compiled_plans(w, storage="bf16", czs=(0, 4))
+    assert any(p["kernel"] == "lds" for p in plans), case
+    base = None
+    for plan in plans:
+        got, _ = gpu_run(w, 3, storage="bf16", plan=plan)
+        if base is None:
+            base = got
+            continue
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], base[s]), (case, plan, s)
+    ring = next(p for p in plans if p["kernel"] == "lds")
+    one, _ = gpu_run(w, 1, storage="bf16", plan=ring)
+    ref = oracle.run(w.spec, w.fields, 1)
+    for s in range(w.spec.ns):
+        assert np.all(np.abs(one[s] - round_bf16(ref[s])) <= ulp(ref[s], "bf16") * 1.01 + 1e-30), (case, s)
+
+
 @pytest.mark.parametrize("name,shape", [("brusselator256", (6, 12, 256)), ("diffusion512", (9, 7, 512))])
 def test_two_step_plans_with_graphs_and_odd_counts(name, shape):
     """Two steps per launch: graph chunks of 2, 4 and 6 steps and odd step
