@@ -169,10 +169,11 @@ enum {
                               wave64 lane shifts for x, LDS for inter-wave rows */
     RD_KERNEL_BLOCK = 3,   /* xy tile x cz-plane slab per workgroup, all planes
                               loaded up front; same lane shifts and LDS rows    */
-    RD_KERNEL_LDS = 4,     /* FP32 rows of up to 256 (vx 4) or 512 (vx 8) cells,
-                              more than 256 for vx 8, nx a multiple of 4:
-                              z-march over a ring of LDS plane slots filled by
-                              direct-to-LDS loads from one producer wave       */
+    RD_KERNEL_LDS = 4,     /* FP32 or BF16 rows of up to 256 (vx 4) or 512 (vx 8)
+                              cells, more than 256 for vx 8, nx a multiple of 4
+                              (FP32) or 8 (BF16): z-march over a ring of LDS
+                              plane slots filled by direct-to-LDS loads from one
+                              producer wave                                    */
     RD_KERNEL_LDS2 = 5     /* as RD_KERNEL_LDS, two time steps per launch
                               (temporal blocking; diffusion and Brusselator).
                               rd_step with an odd count finishes with one
@@ -262,11 +263,11 @@ int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t nspecies, doub
 int rd_set_plan(rd_grid *g, const rd_plan *p);   /* RD_EINVAL if unsupported */
 int rd_get_plan(const rd_grid *g, rd_plan *p);   /* the plan rd_step uses    */
 
-/* Kernel launches per step of the grid's model (*out): 1, or 2 for the
- * front model (chemical-potential pass, then the update) and for more than
- * two pollutants (the coupled pair, then the rest: species groups that share
- * no term, section 2's Eq. (5) evaluated group by group).  RD_ESTATE
- * without a model. */
+/* Kernel launches per Euler step (per Runge-Kutta stage) of the grid's model
+ * (*out): 1, or 2 for the front model (chemical-potential pass, then the
+ * update) and for more than two species of the pollutant and atmospheric
+ * models (species groups that share no term, section 2's Eq. (5) evaluated
+ * group by group).  RD_ESTATE without a model. */
 int rd_get_passes(const rd_grid *g, int32_t *out);
 
 /* rounding of stored BF16 values (rd_set_rounding) */
