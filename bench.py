@@ -63,16 +63,24 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str, digest: str):
-    """The committed rocprofv3 PMC summary of this workload, if it was taken
-    on the current kernel sources; else None."""
-    path = os.path.join(PROFILES, "%s_pmc.json" % name)
+KERNEL_NAMES = {1: "direct_kernel", 2: "tiled_kernel", 3: "block_kernel", 4: "lds_kernel", 5: "lds2_kernel"}
+
+
+def measured_traffic(name: str, digest: str, kernel: int = 0):
+    """The committed rocprofv3 PMC summary of this workload on the kind of
+    kernel the plan runs, if it was taken on the current kernel sources;
+    else None."""
+    path = os.path.join(PROFILES, "%s_%s_pmc.json" % (name, KERNEL_NAMES.get(kernel, "?")))
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("source_digest") != digest:
+        return None
+    names = rec.get("kernel")
+    names = names if isinstance(names, list) else [names]
+    if kernel and not all(KERNEL_NAMES.get(kernel, "?") in str(n) for n in names):
         return None
     return rec
 
@@ -201,7 +209,8 @@ def pmc_summary(args):
            "hbm_bytes_per_step": (rd_b + wr_b) / spl,
            "algorithmic_bytes_per_launch_set": alg,
            "traffic_over_algorithmic": (rd_b + wr_b) / alg}
-    out = os.path.join(PROFILES, "%s_pmc.json" % profile_name(args))
+    kind = next((v for v in KERNEL_NAMES.values() if v in knames[0]), "kernel")
+    out = os.path.join(PROFILES, "%s_%s_pmc.json" % (profile_name(args), kind))
     with open(out, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -242,7 +251,8 @@ def trace_summary(args):
                   % (step[0][:80], bpc, cells, bpc * cells / 1e6),
                   "average %.2f us that is %.0f GB/s, %.1f%% of the 8 TB/s HBM peak."
                   % (step[1], gbs, 100.0 * gbs / HBM_PEAK_GBS)]
-    out = os.path.join(PROFILES, "%s_kernel_trace.md" % profile_name(args))
+    kind = next((v for v in KERNEL_NAMES.values() if step and v in step[0]), "kernel")
+    out = os.path.join(PROFILES, "%s_%s_trace.md" % (profile_name(args), kind))
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -351,7 +361,7 @@ def main():
     elif args.no_autotune:
         plan = g.plan()
     else:
-        plan = g.autotune(10)
+        plan = g.autotune(40)
     chunk = args.graph_chunk if args.graph_chunk >= 2 else 0
     plan["graph_chunk"] = chunk - (chunk & 1)
     g.set_plan(**plan)
@@ -395,7 +405,7 @@ def main():
     if stages > 1:      # reported per step over all its kernels
         achieved = (stages * bpc + rk_bytes) * w.cells / (ms_per_step * 1e-3) / 1e9
     digest = kernel_source_digest()
-    pmc = measured_traffic(profile_name(args), digest)
+    pmc = measured_traffic(profile_name(args), digest, plan.get("kernel", 0))
     traffic = None
     if pmc is not None and stages == 1 and pmc.get("steps_per_launch", 1) == steps_per_launch:
         traffic = pmc.get("hbm_bytes_per_launch") if passes == 1 else pmc.get("hbm_bytes_per_step")
