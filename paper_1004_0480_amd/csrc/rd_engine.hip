@@ -1237,8 +1237,19 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
         bool ok = true;
         for (int k = 0; k < g->npass; ++k) ok = ok && lds_ok(g->storage, g->pass_pm[k], i);
         if (!ok) continue;
-        // one workgroup per CU: small grids need short z chunks to fill the chip
-        for (int cz : {0, 64, 32, 16, 8, 4}) {
+        // One or two workgroups per CU: small grids need short z chunks to
+        // fill the chip.  Besides the fixed lengths, try the chunk lengths
+        // that give at most 1, 2, 3 or 4 workgroups per CU, so that no
+        // launch ends with a partial round of workgroups.
+        std::vector<int> czs = {0, 64, 32, 16, 8, 4};
+        const int yblocks = (g->ny + c.by - 1) / c.by;
+        for (int per_cu = 1; per_cu <= 4; ++per_cu) {
+            const int chunks = per_cu * num_cus() / yblocks;
+            if (chunks < 1) continue;
+            const int cz = (g->nz + chunks - 1) / chunks;
+            if (std::find(czs.begin(), czs.end(), cz) == czs.end()) czs.push_back(cz);
+        }
+        for (int cz : czs) {
             if (cz != 0 && cz >= g->nz) continue;
             rd_plan p{};
             p.kernel = RD_KERNEL_LDS;
