@@ -78,15 +78,16 @@ PassGroups pass_groups(int model, int ns) {
     return p;
 }
 
+// compute units of the current device (the first query is cached; the
+// library runs on one device model at a time)
 int num_cus() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
+    static const int cus = [] {
+        int dev = 0, n = 0;
         hipDeviceProp_t p;
         if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess)
-            cus = p.multiProcessorCount;
-        if (cus <= 0) cus = 256;
-    }
+            n = p.multiProcessorCount;
+        return n > 0 ? n : 256;
+    }();
     return cus;
 }
 
