@@ -110,8 +110,9 @@ constexpr int pm_fields(int pm) {
 
 // LDS-ring shape i is compiled for this storage and pass model: FP32 fields,
 // a ring that fits the LDS and the vmcnt range; models of one or two fields
-// take the first shapes, the two passes of the front model the four-field
-// ones (both passes of a step share one plan).
+// take the first shapes and the first four-field one (1·4·4, D 6: two
+// workgroups per CU for two fields), the two passes of the front model the
+// four-field ones (both passes of a step share one plan).
 // BF16 storage takes the ring with 2-byte cells for models of one or two
 // fields, on the four shapes that serve those best in FP32.
 constexpr bool lds_ok(int storage, int pm, int i) {
@@ -119,7 +120,8 @@ constexpr bool lds_ok(int storage, int pm, int i) {
     const bool front = pm == PM_CHMU || pm == PM_FRONT;
     if (storage == ST_BF16) {
         if (front || pm_fields(pm) > 2 || !(i == 1 || i == 4 || i == 7 || i == 9)) return false;
-    } else if (storage != ST_F32 || front != (i >= kFirstLds4Cfg) || (!front && pm_fields(pm) > 2)) {
+    } else if (storage != ST_F32 || (front ? i < kFirstLds4Cfg : i > kFirstLds4Cfg) ||
+               (!front && pm_fields(pm) > 2)) {
         return false;
     }
     const LdsCfg c = kLdsCfgs[i];

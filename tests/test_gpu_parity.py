@@ -26,7 +26,7 @@ TILE_SHAPES = [(4, 1, 4, 1), (4, 1, 4, 2), (2, 2, 4, 2), (2, 1, 4, 2), (4, 2, 4,
 # LDS-ring shapes (cells per lane = 4 * 256-cell chunks, rows per workgroup,
 # computing waves, ring slots); only rows of exactly 64 * vx cells take them
 LDS_SHAPES = [(4, 8, 4, 7), (4, 8, 8, 7), (8, 8, 4, 6), (8, 4, 4, 6), (8, 8, 8, 6), (8, 4, 4, 7),
-              (8, 8, 8, 7), (4, 12, 6, 5), (8, 12, 6, 5), (8, 6, 6, 5)]
+              (8, 8, 8, 7), (4, 12, 6, 5), (8, 12, 6, 5), (8, 6, 6, 5), (4, 4, 4, 6), (8, 2, 2, 5)]
 # two-steps-per-launch shapes (same fields)
 LDS2_SHAPES = [(4, 4, 8, 6), (8, 4, 8, 6), (4, 8, 8, 5), (8, 6, 6, 4), (4, 6, 12, 4), (8, 6, 12, 4),
                (8, 4, 12, 6), (4, 4, 12, 6)]
