@@ -276,7 +276,8 @@ rd_plan heuristic_plan(const rd_grid* g) {
     rd_plan best{};
     best.kernel = RD_KERNEL_DIRECT;
     if (g->args[0][0].s19) {
-        // 19-point: the first LDS-ring shape this grid and model take, else direct
+        // 19-point: the first LDS-ring shape this grid and model take, with
+        // z chunks that give about two workgroups per CU; else direct
         for (int i = 0; i < kNumLdsCfgs; ++i) {
             const LdsCfg c = kLdsCfgs[i];
             bool ok = ring_row_fits(g, c.nch);
@@ -287,6 +288,10 @@ rd_plan heuristic_plan(const rd_grid* g) {
             best.ry = c.by;
             best.waves = c.wc;
             best.prefetch = c.d;
+            const int yblocks = (g->ny + c.by - 1) / c.by;
+            const int chunks = std::max(1, 2 * num_cus() / yblocks);
+            const int cz = (g->nz + chunks - 1) / chunks;
+            best.cz = cz < g->nz ? cz : 0;
             break;
         }
         return best;

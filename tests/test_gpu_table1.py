@@ -116,6 +116,34 @@ def test_atmos_clock_across_calls_graphs_and_autotune(stencil):
     assert np.array_equal(run([n], tune=True), eager)
 
 
+@pytest.mark.parametrize("name", ["t1_diffusion192", "t1_turing192"])
+def test_table1_default_plan_fills_the_chip(name):
+    """Without autotuning, a 19-point grid takes the LDS ring with z chunks
+    that give about two workgroups per CU, not one chunk of the whole z range
+    (16 to 24 workgroups at 192^3), and matches the oracle in it.  nz = 189
+    keeps the grid out of any autotuned entry of the same process."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    w = W.make_workload(name)
+    fields = [f[:189] for f in w.fields]
+    g = rd.Grid(fields[0].shape, w.spec.ns, w.spec.h, "f32")
+    g.set_model(w.spec)
+    for s, f in enumerate(fields):
+        g.write(s, f)
+    g.step(2)
+    plan = g.plan()
+    got = g.read_all()
+    g.close()
+    nz, ny, _ = fields[0].shape
+    assert plan["kernel"] == rd.KERNEL["lds"], plan
+    assert 0 < plan["cz"] < nz, plan
+    groups = -(-ny // plan["ry"]) * -(-nz // plan["cz"])
+    assert cus <= groups <= 2 * cus, (plan, groups)
+    ref = oracle.run(w.spec, fields, 2)
+    for s in range(w.spec.ns):
+        assert rel_l2(got[s], ref[s]) <= TOL, (name, s, plan)
+
+
 @pytest.mark.parametrize("name,steps", [("t1_diffusion192", 4), ("t1_turing192", 4), ("t1_front192", 3),
                                         ("t1_atmos192", 4)])
 def test_table1_at_192_autotuned(name, steps):
