@@ -163,7 +163,11 @@ enum { RD_EULER = 1, RD_RK2 = 2, RD_RK3 = 3 };
 
 /* kernel plan of a grid (all plans give bitwise-identical fields) */
 enum {
-    RD_KERNEL_AUTO = 0,    /* library choice (autotune cache or heuristic)      */
+    RD_KERNEL_AUTO = 0,    /* library choice: the rd_autotune cache entry for
+                              this shape and model, else a heuristic (a slab
+                              shape for 7-point models; for 19-point ones the
+                              first LDS-ring shape, with z chunks for about two
+                              workgroups per CU)                                */
     RD_KERNEL_DIRECT = 1,  /* one thread per cell, neighbours through the cache */
     RD_KERNEL_TILED = 2,   /* xy tile per workgroup, z-march register window,
                               wave64 lane shifts for x, LDS for inter-wave rows */
