@@ -334,7 +334,7 @@ def main():
     if args.trace_summary:
         return trace_summary(args)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+        print("bench.py: runs on one GPU only (there is no multi-GPU path); "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("RANK", "0")) != 0:
