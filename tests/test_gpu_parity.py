@@ -520,6 +520,14 @@ def case19(case):
         faces = [(GHOST, 0.5), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0), (HELD, 0.25), (GHOST, -1.0)]
         return as19(W.Workload("faces256", shape, bc_spec(1, faces, K=(1.0, 1.0, 1.0)),
                                [rng.uniform(0, 1, shape)], 6, 0))
+    if case == "ghosts256":
+        # fixed ghosts of different values on x-, y+ and z-, none held: the
+        # edge ghosts between two of them take the first axis's value
+        shape = (8, 11, 256)
+        rng = np.random.default_rng(25)
+        faces = [(GHOST, 0.25), (MIRROR, 0), (MIRROR, 0), (GHOST, 0.5), (GHOST, -1.0), (MIRROR, 0)]
+        return as19(W.Workload("ghosts256", shape, bc_spec(1, faces, K=(1.0, 1.0, 1.0)),
+                               [rng.uniform(0, 1, shape)], 6, 0))
     if case == "held512":
         shape = (7, 9, 512)
         rng = np.random.default_rng(23)
@@ -544,7 +552,7 @@ def case19(case):
     raise KeyError(case)
 
 
-@pytest.mark.parametrize("case", ["faces70", "faces256", "held512", "bruss256", "bruss256ragged",
+@pytest.mark.parametrize("case", ["faces70", "faces256", "ghosts256", "held512", "bruss256", "bruss256ragged",
                                   "poll256", "front512"])
 def test_stencil19_every_plan(case):
     """The 19-point Laplacian with edge ghosts on every face kind: the

@@ -230,6 +230,24 @@ CASES = {
         wind=np.array([0.0, 0.5, 0.75, 1.0]),
         sources=(np.array([5, 37], np.int64), np.array([1, 0], np.int32), np.array([10.0, 2.0])),
         stencil=19),
+    # C with fixed-ghost, held and periodic faces: mu keeps mirror ghosts on
+    # every face (section 4.1, boundary rule applied again before the second
+    # Laplacian), so these differ from C's own rules at the faces
+    "front_c_fixed_faces": lambda: ModelSpec(
+        "front_ch", 3, 1 / 64, 1.0, [[1.0] * 3, [0.5] * 3, [0.25] * 3],
+        [[(MIRROR, 0)] * 4 + [(HELD, 1.0), (MIRROR, 0)], [(MIRROR, 0)] * 6,
+         [(GHOST, 0.75), (GHOST, -1.25), (PERIODIC, 0), (PERIODIC, 0), (GHOST, 0.5), (HELD, -0.5)]],
+        {"k": 1.0, "M": 0.1, "kappa": 1.0, "eps": 1.0, "gamma": 1.0}),
+    "front19_c_fixed_faces": lambda: ModelSpec(
+        "front_ch", 3, 1 / 64, 1.0, [[1.0] * 3, [1.0] * 3, [0.0] * 3],
+        [[(MIRROR, 0)] * 6, [(MIRROR, 0)] * 6,
+         [(HELD, 0.5), (GHOST, -0.25), (GHOST, 1.5), (MIRROR, 0), (PERIODIC, 0), (PERIODIC, 0)]],
+        {"k": 0.5, "k2": 0.25, "M": 0.25, "kappa": 1.0, "eps": 1.0, "gamma": 1.0}, stencil=19),
+    # fixed ghosts of different values on faces of all three axes, none held:
+    # the edge ghosts between them take the first axis's value (x, y, z)
+    "diffusion19_two_ghosts": lambda: ModelSpec(
+        "diffusion", 1, 1 / 16, 1.0, [[1.0] * 3],
+        [[(GHOST, 0.25), (MIRROR, 0), (MIRROR, 0), (GHOST, 0.5), (GHOST, -1.0), (MIRROR, 0)]], stencil=19),
     # the rest of Table 1: the Turing model, redissolution in the front
     # model, and the atmospheric wind blowing along every axis in turn
     "turing_mirror": lambda: ModelSpec(

@@ -238,6 +238,85 @@ def test_front_without_reaction_conserves_c(oracle):
     assert abs(math.fsum(out[2].ravel()) - math.fsum(C0.ravel())) < 1e-12 * C0.size
 
 
+def _face_axis_slices(face, n):
+    """Index tuple of the cell layer at distance ``n`` from ``face`` (0..5)."""
+    axis = 2 - face // 2          # arrays are [z][y][x]
+    idx = [slice(None)] * 3
+    idx[axis] = n if face % 2 == 0 else -1 - n
+    return tuple(idx)
+
+
+@pytest.mark.parametrize("face", range(6))
+@pytest.mark.parametrize("h", [1.0, 2.0])
+def test_mu_ghost_is_mirror_closed_form(oracle, face, h):
+    """Section 4.1: the second Laplacian of the Cahn-Hilliard term runs on mu
+    after the boundary rule is applied again -- the no-flux (mirror) rule on
+    every face, whatever fixed ghost C has.  C uniform at c0 with one face a
+    fixed ghost g: Lap(C) is (g - c0)/h^2 on that face's layer and 0 elsewhere,
+    so mu drops by kappa (g - c0)/h^2 there, and with mu mirrored the step moves
+    exactly dt M kappa (g - c0)/h^4 from the second layer into the first.  (With
+    g as mu's ghost as well the first layer would change by a different amount.)"""
+    shape = (6, 5, 7)
+    c0, g, M, kappa, dt = 0.5, -0.75, 0.1, 1.5, 1.0 / 512
+    spec = W.front_spec(k=0.0, M=M, kappa=kappa, eps=1.0, gamma=1.0, DA=0.0, DB=0.0, DC=0.0, dt=dt, h=h)
+    spec.bc[0][4] = (MIRROR, 0.0)
+    spec.bc[2][face] = (GHOST, g)
+    zero = np.zeros(shape)
+    out = oracle.run(spec, [zero, zero, np.full(shape, c0)], 1)[2]
+    d = dt * M * kappa * (g - c0) / h**4
+    expect = np.full(shape, c0)
+    expect[_face_axis_slices(face, 0)] += d
+    expect[_face_axis_slices(face, 1)] -= d
+    assert np.allclose(out, expect, rtol=0, atol=1e-15)
+    assert abs(out[_face_axis_slices(face, 0)][0, 0] - (c0 + d)) < 1e-15
+
+
+@pytest.mark.parametrize("stencil", [7, 19])
+def test_mu_mirror_conserves_c_with_fixed_and_periodic_faces(oracle, stencil):
+    """With A = B = 0 and no Fickian term, C changes by M Lap(mu) only.  mu's
+    mirror ghosts make that a sum of fluxes that cancel, so sum(C) is
+    invariant even where C itself has fixed ghost values or a periodic axis
+    (mu taking C's fixed values as ghosts would add a boundary flux)."""
+    shape = (7, 6, 5)
+    rng = np.random.default_rng(21)
+    spec = W.front_spec(k=0.0, M=0.1, kappa=1.0, eps=1.0, gamma=1.0, DA=0.0, DB=0.0, DC=0.0, dt=0.005)
+    spec.stencil = stencil
+    spec.bc[0][4] = (MIRROR, 0.0)
+    spec.bc[2] = [(GHOST, 1.0), (GHOST, -0.5), (PERIODIC, 0.0), (PERIODIC, 0.0), (GHOST, 0.25), (MIRROR, 0.0)]
+    C0 = rng.uniform(-1, 1, shape)
+    zero = np.zeros(shape)
+    out = oracle.run(spec, [zero, zero, C0], 20)[2]
+    assert abs(math.fsum(out.ravel()) - math.fsum(C0.ravel())) < 1e-12 * C0.size
+    assert np.max(np.abs(out - C0)) > 1e-3          # the step did move C
+
+
+@pytest.mark.parametrize("axes", [(0, 1), (0, 2), (1, 2)])
+@pytest.mark.parametrize("h", [1.0, 2.0])
+def test_stencil19_edge_ghost_takes_first_axis(oracle, axes, h):
+    """An edge neighbour of the 19-point stencil that leaves the grid through
+    two faces with different fixed ghost values takes the value of the first
+    of the two axes in x, y, z order (the reading of the edge ghosts of
+    section 4.1).  Uniform c0, low faces of axes a < b fixed at ga, gb: at a
+    cell on both low faces, inside along the third axis, the stencil of
+    Eq. (4) sums 2 (ga + gb) from the faces and 4 ga + 3 gb from the edges
+    (the shared edge counted with ga), so
+        Lap = D/(6h^2) (6 ga + 5 gb - 11 c0)."""
+    shape = (6, 6, 6)
+    c0, ga, gb, D, dt = 0.25, 1.5, -2.0, 1.0, 0.0625 * h * h
+    bc = [(MIRROR, 0.0)] * 6
+    bc[2 * axes[0]] = (GHOST, ga)
+    bc[2 * axes[1]] = (GHOST, gb)
+    spec = ModelSpec("diffusion", 1, dt, h, [[D] * 3], [bc], stencil=19)
+    out = oracle.run(spec, [np.full(shape, c0)], 1)[0]
+    idx = [slice(1, -1)] * 3          # inside along the third axis
+    idx[2 - axes[0]] = 0
+    idx[2 - axes[1]] = 0
+    expect = c0 + dt * D / (6 * h * h) * (6 * ga + 5 * gb - 11 * c0)
+    got = out[tuple(idx)]
+    assert got.size == 4
+    assert np.allclose(got, expect, rtol=0, atol=1e-14)
+
+
 # ------------------------------------------------------------------ P7
 
 def test_brusselator_uniform_is_scalar_ode(oracle):
