@@ -1,11 +1,13 @@
 """Benchmark: the explicit RD step on one MI355X.
 
-Default workload: the two-species Brusselator on a 256^3 periodic grid (FP32
-fields, dt = 0.01), i.e. one step = one fused 7-point-Laplacian + reaction +
-Euler pass over 16.8 M cells x 2 species.  Prints ONE JSON line with
-Gcell-updates/s, the step kernel's HBM-roofline fraction (timed with HIP
-events on the stream the kernel runs on) and the FP64 CPU oracle timed on a
-bounded sample of the same workload on the host's cores.
+Default workload: the moving-front precipitation problem on a 384x384x512
+grid (3 species, FP32 fields, dt = 0.005), the largest configuration: one step
+= A + B -> C with the Cahn-Hilliard term M Lap(mu), mu = C^3 - C - kappa
+Lap(C), in one fused pass (the chemical potential computed in LDS) over 75.5 M
+cells x 3 species.  Prints ONE JSON line with Gcell-updates/s, the step
+kernel's HBM-roofline fraction (timed with HIP events on the stream the
+kernel runs on) and the FP64 CPU oracle timed on a bounded sample of the same
+workload, on the host's cores and on one thread.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -26,14 +28,15 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 # Algorithmic HBM bytes per cell-update: one read and one write of every
 # stored species (FP32 fields: 4 B each way).  The front model's two-pass
-# form additionally writes and reads the FP32 chemical potential (8 B/cell).
-def alg_bytes_per_cell(name: str, storage: str) -> int:
+# form additionally writes and reads the FP32 chemical potential (8 B/cell)
+# and reads C twice; its one-pass form moves the plain bytes.
+def alg_bytes_per_cell(name: str, storage: str, one_pass: bool = False) -> int:
     ns = {"brusselator256": 2, "diffusion64": 1, "diffusion512": 1, "front384": 3,
           "pollutant512": 4, "t1_diffusion192": 1, "t1_turing192": 2, "t1_front192": 3,
           "t1_atmos192": 1}[name]
     es = 4 if storage == "f32" else 2
     b = 2 * ns * es
-    if name in ("front384", "t1_front192"):
+    if name in ("front384", "t1_front192") and not one_pass:
         b += 8 + es          # mu written (4) and read (4) + C read again by pass 1
     return b
 
@@ -54,16 +57,14 @@ def profile_name(args) -> str:
 
 
 def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1004_0480_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hpp", ".hip")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Digest of the kernel and engine sources (the one compiled into the
+    library)."""
+    from paper_1004_0480_amd import build
+    return build.source_digest()
 
 
-KERNEL_NAMES = {1: "direct_kernel", 2: "tiled_kernel", 3: "block_kernel", 4: "lds_kernel", 5: "lds2_kernel"}
+KERNEL_NAMES = {1: "direct_kernel", 2: "tiled_kernel", 3: "block_kernel", 4: "lds_kernel", 5: "lds2_kernel",
+                6: "fch_kernel"}
 
 
 def measured_traffic(name: str, digest: str, kernel: int = 0):
@@ -85,25 +86,49 @@ def measured_traffic(name: str, digest: str, kernel: int = 0):
     return rec
 
 
-def cpu_baseline(w, budget_s: float = 12.0, threads: int = 0):
+def cpu_sample(w, max_cells: int):
+    """The workload itself, or its lowest z planes when the grid has more than
+    max_cells cells (same physics and boundary rules; the top face of the
+    sample takes the grid's top rule).  Returns (workload, description)."""
+    from paper_1004_0480_amd import workloads as W
+    nz, ny, nx = w.shape
+    if w.cells <= max_cells:
+        return w, "whole grid"
+    kz = max(1, max_cells // (ny * nx))
+    spec = w.spec.copy()
+    if spec.wind is not None:
+        spec.wind = spec.wind[:kz].copy()
+    if spec.sources is not None and len(spec.sources[0]):
+        keep = spec.sources[0] < kz * ny * nx
+        spec.sources = tuple(a[keep] for a in spec.sources)
+    sub = W.Workload(w.name, (kz, ny, nx), spec, [f[:kz].copy() for f in w.fields], w.steps, w.seed)
+    return sub, "the lowest %d of %d z planes" % (kz, nz)
+
+
+def cpu_baseline(w, budget_s: float = 12.0, threads: int = 0, max_cells: int = 1 << 27):
     """The FP64 oracle as it stands, on all host cores (or `threads` of them;
-    the paper's CPU baseline is one thread), on a bounded sample (whole grid,
-    a few steps) of the same workload."""
+    the paper's CPU baseline is one thread), on a bounded sample (the whole
+    grid or its lowest planes, a few steps) of the same workload."""
     import oracle
+    before = oracle.threads()
     if threads > 0:
         oracle.set_threads(threads)
-    t0 = time.perf_counter()
-    oracle.run(w.spec, w.fields, 1)
-    one = time.perf_counter() - t0
-    steps = int(max(1, min(20, budget_s // max(one, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.run(w.spec, w.fields, steps)
-    dt = time.perf_counter() - t0
-    nthr = oracle.threads()
-    return {"value": w.cells * steps / dt / 1e9, "unit": "Gcell-updates/s",
+    try:
+        ws, where = cpu_sample(w, max_cells)
+        t0 = time.perf_counter()
+        oracle.run(ws.spec, ws.fields, 1)
+        one = time.perf_counter() - t0
+        steps = int(max(1, min(20, budget_s // max(one, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.run(ws.spec, ws.fields, steps)
+        dt = time.perf_counter() - t0
+        nthr = oracle.threads()
+    finally:
+        oracle.set_threads(before)
+    return {"value": ws.cells * steps / dt / 1e9, "unit": "Gcell-updates/s",
             "cores": nthr, "kind": "oracle",
-            "sample": "%s %dx%dx%d, %d FP64 steps (whole grid), %s"
-                      % (w.name, w.shape[2], w.shape[1], w.shape[0], steps,
+            "sample": "%s %dx%dx%d (%s), %d FP64 steps, %s"
+                      % (w.name, ws.shape[2], ws.shape[1], ws.shape[0], where, steps,
                          "one thread" if nthr == 1 else "OpenMP over z, %d threads" % nthr)}
 
 
@@ -131,7 +156,7 @@ def copy_ceiling(torch, stream, nbytes: int, reps: int = 10):
 # ------------------------------------------------ profile summaries (rocprofv3)
 
 STEP_KERNELS = ("rdk::block_kernel", "rdk::tiled_kernel", "rdk::direct_kernel", "rdk::lds_kernel",
-                "rdk::lds2_kernel")
+                "rdk::lds2_kernel", "rdk::fch_kernel")
 
 
 def _counter_rows(d: str):
@@ -196,7 +221,9 @@ def pmc_summary(args):
     # one launch set reads and writes every field once: one step, or two for
     # the two-step (temporally blocked) kernel
     spl = 2 if any("rdk::lds2_kernel" in k for k in knames) else 1
-    alg = alg_bytes_per_cell(args.workload, args.storage) * cells
+    one_pass = any("rdk::fch_kernel" in k for k in knames)
+    bpc = alg_bytes_per_cell(args.workload, args.storage, one_pass)
+    alg = bpc * cells
     rec = {"kernel": knames[0] if len(knames) == 1 else knames,
            "workload": "%s %s, %s storage, %d-point Laplacian" % (args.workload, W.DEFAULT_SHAPES[args.workload],
                                                                   args.storage, args.stencil),
@@ -207,7 +234,7 @@ def pmc_summary(args):
            "hbm_read_bytes_per_launch_set": rd_b, "hbm_write_bytes_per_launch_set": wr_b,
            "hbm_bytes_per_launch": (rd_b + wr_b) if len(knames) == 1 else None,
            "hbm_bytes_per_step": (rd_b + wr_b) / spl,
-           "algorithmic_bytes_per_launch_set": alg,
+           "alg_bytes_per_cell": bpc, "algorithmic_bytes_per_launch_set": alg,
            "traffic_over_algorithmic": (rd_b + wr_b) / alg}
     kind = next((v for v in KERNEL_NAMES.values() if v in knames[0]), "kernel")
     out = os.path.join(PROFILES, "%s_%s_pmc.json" % (profile_name(args), kind))
@@ -229,7 +256,8 @@ def trace_summary(args):
     with open(files[0]) as fh:
         rows = list(csv.DictReader(fh))
     cells = int(np.prod(W.DEFAULT_SHAPES[args.workload]))
-    bpc = alg_bytes_per_cell(args.workload, args.storage)
+    one_pass = any("rdk::fch_kernel" in r["Name"] for r in rows)
+    bpc = alg_bytes_per_cell(args.workload, args.storage, one_pass)
     lines = ["# rocprofv3 kernel trace: %s step kernel (MI355X)" % profile_name(args), "",
              "Workload: %s, grid (z, y, x) = %s, %s storage, %d-point Laplacian."
              % (args.workload, W.DEFAULT_SHAPES[args.workload], args.storage, args.stencil),
@@ -301,7 +329,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="brusselator256",
+    ap.add_argument("--workload", default="front384",
                     choices=["brusselator256", "diffusion512", "front384", "pollutant512", "diffusion64",
                              "t1_diffusion192", "t1_turing192", "t1_front192", "t1_atmos192", "serve"])
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16", "both"])
@@ -387,8 +415,8 @@ def main():
     for s in range(w.spec.ns):
         g.reduce(s)
 
-    bpc = alg_bytes_per_cell(args.workload, args.storage)
     passes = g.passes()
+    bpc = alg_bytes_per_cell(args.workload, args.storage, one_pass=passes == 1)
     steps_per_launch = 2 if plan.get("kernel") == 5 else 1     # two-step (temporally blocked) plan
     # a Runge-Kutta step runs 2 or 3 Euler stages; every stage after the first
     # also reads the current state once per species (its combination is
@@ -422,7 +450,7 @@ def main():
         "metric": "Gcell-updates/s", "value": value, "unit": "Gcell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32", "storage_dtype": args.storage, "data": "synthetic",
         "config": {"workload": w.name, "grid_xyz": [w.shape[2], w.shape[1], w.shape[0]],
                    "species": w.spec.ns, "storage": args.storage, "stencil": w.spec.stencil,
                    "integrator": args.integrator, "rounding": args.rounding, "dt": w.spec.dt,
@@ -431,7 +459,12 @@ def main():
     }
     g.close()
     if not args.no_cpu_baseline:
+        print("bench: CPU oracle, all host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, threads=args.cpu_threads)
+        # the paper's CPU baseline ran on one thread: the same oracle on one
+        # host thread, on a smaller sample of the same grid
+        print("bench: CPU oracle, one thread", file=sys.stderr, flush=True)
+        out["cpu_baseline_single_thread"] = cpu_baseline(w, threads=1, max_cells=1 << 23)
     print(json.dumps(out), flush=True)
 
 

@@ -164,10 +164,11 @@ enum { RD_EULER = 1, RD_RK2 = 2, RD_RK3 = 3 };
 /* kernel plan of a grid (all plans give bitwise-identical fields) */
 enum {
     RD_KERNEL_AUTO = 0,    /* library choice: the rd_autotune cache entry for
-                              this shape and model, else a heuristic (a slab
-                              shape for 7-point models; for 19-point ones the
-                              first LDS-ring shape, with z chunks for about two
-                              workgroups per CU)                                */
+                              this shape, model and integrator, else a heuristic
+                              (the one-pass plan for the 7-point front model; a
+                              slab shape for other 7-point models; for 19-point
+                              ones the first LDS-ring shape, with z chunks for
+                              about two workgroups per CU)                      */
     RD_KERNEL_DIRECT = 1,  /* one thread per cell, neighbours through the cache */
     RD_KERNEL_TILED = 2,   /* xy tile per workgroup, z-march register window,
                               wave64 lane shifts for x, LDS for inter-wave rows */
@@ -178,25 +179,35 @@ enum {
                               (FP32) or 8 (BF16): z-march over a ring of LDS
                               plane slots filled by direct-to-LDS loads from one
                               producer wave                                    */
-    RD_KERNEL_LDS2 = 5     /* as RD_KERNEL_LDS, two time steps per launch
+    RD_KERNEL_LDS2 = 5,    /* as RD_KERNEL_LDS, two time steps per launch
                               (temporal blocking; diffusion and Brusselator).
                               rd_step with an odd count finishes with one
                               direct-kernel step                               */
+    RD_KERNEL_FUSED = 6    /* FRONT_CH with the 7-point Laplacian only: the
+                              whole step in one launch (the Cahn-Hilliard
+                              chemical potential computed in LDS one plane
+                              ahead of the update, no mu array in HBM; the two
+                              Laplacian passes of section 4.1 fused).  128-cell
+                              x tiles, any nx (a periodic x axis of C needs
+                              nx <= 128 or a multiple of 128)                  */
 };
 typedef struct rd_plan {
     int32_t kernel;       /* RD_KERNEL_*                                        */
     int32_t vx;           /* TILED/BLOCK: cells per lane along x (1, 2 or 4);
                              LDS: 4 (rows of <= 256 cells) or 8 (257..512);
-                             LDS2: 4 (rows of 256 cells) or 8 (of 512)         */
+                             LDS2: 4 (rows of 256 cells) or 8 (of 512);
+                             FUSED: waves computing the chemical potential    */
     int32_t ry;           /* TILED/BLOCK: rows per wave (1, 2 or 4);
-                             LDS/LDS2: rows per workgroup                      */
+                             LDS/LDS2/FUSED: rows per workgroup                */
     int32_t waves;        /* TILED/BLOCK: waves per workgroup (1 or 4);
-                             LDS/LDS2: computing waves (plus one loading wave) */
-    int32_t cz;           /* TILED/LDS/LDS2: z planes per workgroup, 0 = all;
+                             LDS/LDS2: computing waves (plus one loading wave);
+                             FUSED: waves updating the fields (plus vx waves
+                             for the chemical potential and one loading wave) */
+    int32_t cz;           /* TILED/LDS/LDS2/FUSED: z planes per workgroup, 0 = all;
                              BLOCK: planes per slab (2, 4 or 8)                */
     int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2);
-                             LDS/LDS2: input ring slots                        */
-    int32_t order;        /* BLOCK/LDS/LDS2: tile enumeration, 0 = x, then y, then z chunk;
+                             LDS/LDS2/FUSED: input ring slots                  */
+    int32_t order;        /* BLOCK/LDS/LDS2/FUSED: tile enumeration, 0 = x, then y, then z chunk;
                              1 = z chunk fastest (z-neighbour slabs run together
                              on one XCD and share its L2)                       */
     int32_t graph_chunk;  /* rd_step replays hipGraphs of this many steps (even,
@@ -242,8 +253,8 @@ int rd_read_field(rd_grid *g, int32_t species, void *dst, int32_t dst_dtype,
 int rd_reduce(rd_grid *g, int32_t species, double out_mass_energy[2]);
 
 /* FRONT_CH only: the Cahn-Hilliard chemical potential mu of the current state
- * (FP32, the first of the two Laplacian passes), dense [nz][ny][nx] on the
- * host.  Synchronises. */
+ * (FP32, the first of the two Laplacian passes; with the one-pass plan the
+ * direct kernel computes it), dense [nz][ny][nx] on the host.  Synchronises. */
 int rd_chemical_potential(rd_grid *g, float *dst_host);
 
 /* Wait for the grid's stream; RD_EDEVICE if a kernel failed. */
@@ -269,7 +280,7 @@ int rd_get_plan(const rd_grid *g, rd_plan *p);   /* the plan rd_step uses    */
 
 /* Kernel launches per Euler step (per Runge-Kutta stage) of the grid's model
  * (*out): 1, or 2 for the front model (chemical-potential pass, then the
- * update) and for more than two species of the pollutant and atmospheric
+ * update; 1 with RD_KERNEL_FUSED) and for more than two species of the pollutant and atmospheric
  * models (species groups that share no term, section 2's Eq. (5) evaluated
  * group by group).  RD_ESTATE without a model. */
 int rd_get_passes(const rd_grid *g, int32_t *out);
@@ -282,10 +293,14 @@ enum { RD_ROUND_NEAREST = 0, RD_ROUND_STOCHASTIC = 1 };
  * RD_ROUND_STOCHASTIC: round the magnitude up with probability (discarded low
  * 16 bits) / 2^16, so the expected stored value is the FP32 result and
  * increments smaller than half a BF16 unit do not stagnate.  The random bits
- * are Philox-2x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) of counter (element
- * index in the padded [nz][ny][pitch] layout, step index since rd_set_model)
- * and key (low 32 bits of seed + species): the same inputs give the same bits
- * on every plan and in graphs.  Kept across rd_set_model.  RD_EINVAL:
+ * are Philox-2x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): element e of a
+ * field (its dense index (z*ny + y)*nx + x) takes 16 of the 64 output bits of
+ * counter (e/4 mod 2^32, step index since rd_set_model) and key (low 32 bits
+ * of seed + species) -- bits 0-15 of the first output word for e%4 = 0, bits
+ * 16-31 for 1, the same halves of the second word for 2 and 3 -- so one call
+ * serves four elements.  The same inputs give the same bits on every plan, in
+ * graphs and whatever the internal padding (fields of up to 2^34 elements
+ * have distinct counters).  Kept across rd_set_model.  RD_EINVAL:
  * unknown mode, or stochastic rounding with storage other than RD_BF16 or a
  * Runge-Kutta model; RD_ESTATE: the grid is in a batch (batches refuse
  * grids with stochastic rounding). */
@@ -337,6 +352,12 @@ int rd_copy_probe(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 const char *rd_last_error(void);
 int rd_abi_version(void);
+
+/* Digest of the kernel and engine sources this library was built from (16
+ * hex digits of a SHA-256 over csrc/, computed by the build and compiled in;
+ * "unknown" if built without it).  Static string, never NULL.  Lets a caller
+ * check that the binary it loaded matches the sources it ships with. */
+const char *rd_source_digest(void);
 
 #ifdef __cplusplus
 }

@@ -12,9 +12,11 @@ multiplied by 0xD256D193, the new first word is the high half xor the key xor
 the second word, the new second word the low half, and the key is bumped by
 0x9E3779B9.
 
-Use in the step: the 16 random bits of a stored element are the low 16 bits
-of the first output word for counter (element index in the padded array,
-step index) and key (seed + species).
+Use in the step: one call gives 64 bits, which serve four stored elements.
+Element e of a field (its dense index (z*ny + y)*nx + x) takes, of the output
+for counter (e // 4, step index) and key (seed + species), bits 0-15 of the
+first word when e % 4 = 0, bits 16-31 when 1, and the same halves of the
+second word when 2 and 3.
 
 Stochastic rounding of a finite FP32 value x to BF16: add the 16 random bits
 to the bit pattern of x and keep the high 16 bits, so the magnitude rounds
@@ -42,11 +44,15 @@ def philox2x32_10(c0, c1, key):
 
 
 def random16(index, step, seed, species):
-    """The 16 random bits of stored element `index` (padded-array index) of
-    `species` at step `step` under `seed`."""
-    w0, _ = philox2x32_10(np.asarray(index, dtype=np.uint64), np.uint64(step),
-                          (np.uint64(seed) + np.uint64(species)) & _MASK)
-    return (w0 & np.uint32(0xFFFF)).astype(np.uint32)
+    """The 16 random bits of stored element `index` (dense index
+    (z*ny + y)*nx + x) of `species` at step `step` under `seed`."""
+    e = np.asarray(index, dtype=np.uint64)
+    w0, w1 = philox2x32_10(e >> np.uint64(2), np.uint64(step),
+                           (np.uint64(seed) + np.uint64(species)) & _MASK)
+    q = e & np.uint64(3)
+    word = np.where(q >= np.uint64(2), w1, w0).astype(np.uint32)
+    return np.where((q & np.uint64(1)) == np.uint64(1), word >> np.uint32(16),
+                    word & np.uint32(0xFFFF)).astype(np.uint32)
 
 
 def bf16_stochastic(x, r16):

@@ -5,6 +5,7 @@ then hipcc links them into ``paper_1004_0480_amd/librdmi.so``.
 """
 import hashlib
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -30,15 +31,51 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _digest(src):
+_INCLUDE_RE = re.compile(r'^\s*#\s*include\s+"([^"]+)"', re.M)
+
+
+def _includes(path, seen):
+    """Transitive project headers of a source file (quoted includes found in
+    csrc/ or include/)."""
+    with open(path, "rb") as fh:
+        text = fh.read().decode("utf-8", "replace")
+    for name in _INCLUDE_RE.findall(text):
+        for d in (CSRC, INCLUDE):
+            cand = os.path.join(d, name)
+            if os.path.exists(cand) and cand not in seen:
+                seen.add(cand)
+                _includes(cand, seen)
+                break
+    return seen
+
+
+def source_digest() -> str:
+    """Hash of every kernel and engine source under csrc/: what the library
+    is built from.  Baked into the library (rd_source_digest) so that a
+    loaded binary can be matched with the sources beside it."""
     h = hashlib.sha256()
-    h.update(" ".join(FLAGS).encode())
-    for f in sorted(os.listdir(CSRC)) + [os.path.join(INCLUDE, "rd.h")]:
-        path = f if os.path.isabs(f) else os.path.join(CSRC, f)
-        if path == src or path.endswith((".hpp", ".h")):
-            with open(path, "rb") as fh:
-                h.update(path.encode())
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hpp", ".hip")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
                 h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _flags(src):
+    f = list(FLAGS)
+    if os.path.basename(src) == "rd_engine.hip":
+        f += ["-DRD_SOURCE_DIGEST=\"%s\"" % source_digest()]
+    return f
+
+
+def _digest(src):
+    """Object key: the flags, the source and the project headers it includes."""
+    h = hashlib.sha256()
+    h.update(" ".join(_flags(src)).encode())
+    for path in [src] + sorted(_includes(src, set())):
+        with open(path, "rb") as fh:
+            h.update(path.encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -47,7 +84,7 @@ def _compile(src, force, verbose):
     obj = os.path.join(BUILD, os.path.basename(src) + "." + _digest(src) + ".o")
     if os.path.exists(obj) and not force:
         return obj
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
+    cmd = [HIPCC] + _flags(src) + ["-c", src, "-o", obj + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -44,6 +44,7 @@ struct StepArgs {
     const void* in[MAXF];         // fields read with the stencil
     void* out[MAXF];              // fields written
     float kx[MAXF], ky[MAXF], kz[MAXF];   // K_{f,d} / h^2
+    float kc[MAXF];               // 2 (kx + ky + kz), formed once on the host
     int bck[MAXF][6];             // boundary kind per field and face
     float bcv[MAXF][6];           // boundary value per field and face
     int held[MAXF];               // bit f set: face f of field is BC_HELD
@@ -212,10 +213,14 @@ __device__ __forceinline__ float load1(const void* base, long long idx) {
 // Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11): each
 // round multiplies the first counter word by 0xD256D193, the new first word
 // is the high half xor the key xor the second word, the new second word the
-// low half, and the key is bumped by 0x9E3779B9.  A stored element draws the
-// low 16 bits of the first output word for counter (element index in the
-// padded array, step index) and key (seed + species).
-__device__ __forceinline__ unsigned philox2x32_10(unsigned c0, unsigned c1, unsigned k) {
+// low half, and the key is bumped by 0x9E3779B9.  One call gives 64 bits,
+// which serve four stored elements: element e of a field (its dense index
+// (z*ny + y)*nx + x) takes 16 bits of the output for counter (e/4, step
+// index) and key (seed + species) -- bits 0-15 of the first word for e%4 = 0,
+// 16-31 for 1, then the same halves of the second word for 2 and 3.
+struct PhiloxOut { unsigned w0, w1; };
+
+__device__ __forceinline__ PhiloxOut philox2x32_10(unsigned c0, unsigned c1, unsigned k) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const unsigned hi = __umulhi(0xD256D193u, c0);
@@ -224,7 +229,12 @@ __device__ __forceinline__ unsigned philox2x32_10(unsigned c0, unsigned c1, unsi
         c1 = lo;
         k += 0x9E3779B9u;
     }
-    return c0;
+    return PhiloxOut{c0, c1};
+}
+
+__device__ __forceinline__ unsigned philox_bits16(const PhiloxOut& r, unsigned q) {
+    const unsigned w = (q & 2u) ? r.w1 : r.w0;
+    return (q & 1u) ? (w >> 16) : (w & 0xffffu);
 }
 
 // Stochastic rounding to BF16: add 16 random bits to the FP32 pattern and
@@ -249,11 +259,12 @@ __device__ __forceinline__ void rk_blend(const StepArgs& a, int s, long long idx
     }
 }
 
-// Store VX output values of species s (of this pass) at element idx in the
-// storage type (after a Runge-Kutta stage's combination), rounding
-// stochastically when the grid asks for it.
+// Store VX output values of species s (of this pass) at row element x of
+// row y, plane z, in the storage type (after a Runge-Kutta stage's
+// combination), rounding stochastically when the grid asks for it.
 template <class S, int VX>
-__device__ __forceinline__ void store_field(const StepArgs& a, int s, long long idx, const float (&v)[VX]) {
+__device__ __forceinline__ void store_field(const StepArgs& a, int s, int x, int y, int z, const float (&v)[VX]) {
+    const long long idx = (long long)z * a.plane + (long long)y * a.pitch + x;
     float o[VX];
 #pragma unroll
     for (int i = 0; i < VX; ++i) o[i] = v[i];
@@ -262,11 +273,28 @@ __device__ __forceinline__ void store_field(const StepArgs& a, int s, long long 
         if (a.sr) {
             const unsigned n = unsigned(gload_ptr<StepClock>(a.clk_in)->n);
             const unsigned key = a.sr_key + unsigned(a.sp0 + s);
-            Vec<uint16_t, VX> r;
+            const unsigned long long e0 = ((unsigned long long)z * unsigned(a.ny) + unsigned(y)) * unsigned(a.nx) +
+                                          unsigned(x);
+            // the VX elements span at most NR consecutive counters
+            constexpr int NR = (VX + 6) / 4;
+            const unsigned c_first = unsigned(e0 >> 2), c_last = unsigned((e0 + VX - 1) >> 2);
+            PhiloxOut r[NR];
 #pragma unroll
-            for (int i = 0; i < VX; ++i)
-                r.v[i] = bf16_stochastic(o[i], philox2x32_10(unsigned(idx + i), n, key) & 0xffffu);
-            *(RD_GLOBAL Vec<uint16_t, VX>*)(gstore_ptr<uint16_t>(a.out[s]) + idx) = r;
+            for (int k = 0; k < NR; ++k) {
+                r[k] = PhiloxOut{0u, 0u};
+                if (c_first + unsigned(k) <= c_last) r[k] = philox2x32_10(c_first + unsigned(k), n, key);
+            }
+            Vec<uint16_t, VX> w;
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                const unsigned long long e = e0 + unsigned(i);
+                const unsigned kk = unsigned(e >> 2) - c_first;
+                PhiloxOut ri = r[0];
+#pragma unroll
+                for (int k = 1; k < NR; ++k) ri = kk == unsigned(k) ? r[k] : ri;
+                w.v[i] = bf16_stochastic(o[i], philox_bits16(ri, unsigned(e) & 3u));
+            }
+            *(RD_GLOBAL Vec<uint16_t, VX>*)(gstore_ptr<uint16_t>(a.out[s]) + idx) = w;
             return;
         }
     }
@@ -304,6 +332,17 @@ __device__ __forceinline__ float lap19(const Nb19& n, float k6) {
     const float edges = (n.sxm + n.sxp) + n.q;
     return k6 * __fmaf_rn(-24.f, n.c, __fmaf_rn(2.f, faces, edges));
 }
+
+// The front model's 7-point form: the neighbour pairs weighted by their axis
+// coefficients, less kc = 2 (kx + ky + kz) times the centre (7 operations
+// against 10; every kernel of that model forms it so).
+__device__ __forceinline__ float lap7s(const Nb& n, float kx, float ky, float kz, float kc) {
+    return __fmaf_rn(-kc, n.c, __fmaf_rn(kx, n.xm + n.xp, __fmaf_rn(ky, n.ym + n.yp, kz * (n.zm + n.zp))));
+}
+__device__ __forceinline__ float lapf(const Nb& n, const StepArgs& a, int f) {
+    return lap7s(n, a.kx[f], a.ky[f], a.kz[f], a.kc[f]);
+}
+__device__ __forceinline__ float lapf(const Nb19& n, const StepArgs& a, int f) { return lap19(n, a.kx[f]); }
 
 // The Laplacian of a neighbourhood: 7-point (per-axis K/h^2) or 19-point
 // (all three coefficients hold K/(6h^2)).
@@ -363,12 +402,14 @@ struct ChemPotential {
     static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return true; }
+    // mu of a cell from C there and Lap(C) there (every kernel forms it so)
+    static __device__ __forceinline__ float mu(const StepArgs& a, float c, float lc) {
+        return __fmaf_rn(-a.p[2], lc, __fmaf_rn(a.p[4] * c, c * c, -(a.p[3] * c)));
+    }
     template <class NB>
     static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[1], float,
                                                 bool, const float (&)[1], float (&o)[1]) {
-        const float c = n[0].c;
-        const float lc = lap(n[0], a.kx[0], a.ky[0], a.kz[0]);
-        o[0] = __fmaf_rn(-a.p[2], lc, __fmaf_rn(a.p[4] * c, c * c, -(a.p[3] * c)));
+        o[0] = mu(a, n[0].c, lapf(n[0], a, 0));
     }
 };
 
@@ -382,19 +423,24 @@ struct FrontCH {
     static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int f) { return f == 3; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
+    // the update from the cell's values and Laplacians; q = k2 A C
+    static __device__ __forceinline__ void rates(const StepArgs& a, float A, float B, float C, float la, float lb,
+                                                 float lc, float lmu, float q, float (&o)[3]) {
+        const float r = (a.p[0] * A) * B;
+        o[0] = __fmaf_rn(a.dt, (la - r) - q, A);
+        o[1] = __fmaf_rn(a.dt, lb - r, B);
+        o[2] = __fmaf_rn(a.dt, __fmaf_rn(a.p[1], lmu, lc + r) - q, C);
+    }
     template <class NB>
     static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[4], float,
                                                 bool, const float (&)[3], float (&o)[3]) {
         const float A = n[0].c, B = n[1].c, C = n[2].c;
-        const float r = (a.p[0] * A) * B;
         const float q = (a.p[5] * A) * C;
-        const float la = lap(n[0], a.kx[0], a.ky[0], a.kz[0]);
-        const float lb = lap(n[1], a.kx[1], a.ky[1], a.kz[1]);
-        const float lc = lap(n[2], a.kx[2], a.ky[2], a.kz[2]);
-        const float lmu = lap(n[3], a.kx[3], a.ky[3], a.kz[3]);
-        o[0] = __fmaf_rn(a.dt, (la - r) - q, A);
-        o[1] = __fmaf_rn(a.dt, lb - r, B);
-        o[2] = __fmaf_rn(a.dt, __fmaf_rn(a.p[1], lmu, lc + r) - q, C);
+        const float la = lapf(n[0], a, 0);
+        const float lb = lapf(n[1], a, 1);
+        const float lc = lapf(n[2], a, 2);
+        const float lmu = lapf(n[3], a, 3);
+        rates(a, A, B, C, la, lb, lc, lmu, q, o);
     }
 };
 
@@ -649,7 +695,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
             gstore_ptr<float>(a.out[s])[idx] = v;
         } else {
             const float w[1] = {v};
-            store_field<S, 1>(a, s, idx, w);
+            store_field<S, 1>(a, s, x, y, z, w);
         }
     }
 }
@@ -905,7 +951,7 @@ __device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64
 #pragma unroll
             for (int s = 0; s < NO; ++s) {
                 if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
-                else store_field<S, VX>(a, s, idx, o[s]);
+                else store_field<S, VX>(a, s, xl, y, z, o[s]);
             }
         }
     }
@@ -1133,7 +1179,7 @@ __device__ __forceinline__ void block_compute(const StepArgs& a, BlockLds<M, W, 
 #pragma unroll
                     for (int s = 0; s < NO; ++s) {
                         if (M::f32_out(s)) store_vec<StF32, VX>(a.out[s], idx, o[s]);
-                        else store_field<S, VX>(a, s, idx, o[s]);
+                        else store_field<S, VX>(a, s, xl, y, z, o[s]);
                     }
                 }
             }
@@ -1708,7 +1754,7 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
 #pragma unroll
                             for (int s = 0; s < NO; ++s) {
                                 if (M::f32_out(s)) store_vec<StF32, 4>(a.out[s], idx, o[s]);
-                                else store_field<ST, 4>(a, s, idx, o[s]);
+                                else store_field<ST, 4>(a, s, xl, y, z, o[s]);
                             }
                         }
                     }

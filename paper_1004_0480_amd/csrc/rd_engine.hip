@@ -15,6 +15,7 @@
 
 #include "rd.h"
 #define RD_DEFINE_ENGINE_KERNELS
+#include "rd_fch_cfg.hpp"
 #include "rd_internal.hpp"
 
 using namespace rdk;
@@ -114,6 +115,21 @@ int lds_cfg_index(int nch, int by, int wc, int d) {
         if (kLdsCfgs[i].nch == nch && kLdsCfgs[i].by == by && kLdsCfgs[i].wc == wc && kLdsCfgs[i].d == d)
             return i;
     return -1;
+}
+
+int fch_cfg_index(int by, int wu, int wm, int d) {
+    for (int i = 0; i < kNumFchCfgs; ++i)
+        if (kFchCfgs[i].by == by && kFchCfgs[i].wu == wu && kFchCfgs[i].wm == wm && kFchCfgs[i].d == d) return i;
+    return -1;
+}
+
+hipError_t launch_fch(int storage, int cfg, const StepArgs&, const StepArgs* d, long long blocks, hipStream_t s) {
+    switch (storage) {
+    case ST_F32: return launch_fch_f32(cfg, d, blocks, s);
+    case ST_BF16: return launch_fch_bf16(cfg, d, blocks, s);
+    case ST_F16: return launch_fch_f16(cfg, d, blocks, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 int lds2_cfg_index(int nch, int by, int wc, int d) {
@@ -251,9 +267,11 @@ void fill_mirror(StepArgs& a, int f) {
 
 // Decomposition of a tiled plan: fills tiles_* / cz, returns workgroups.
 long long set_tiling(StepArgs& a, const rd_plan& p) {
-    // LDS ring: whole rows (vx cells per lane), ry rows per workgroup
-    const bool ring = p.kernel == RD_KERNEL_LDS || p.kernel == RD_KERNEL_LDS2;
-    const int tx = 64 * p.vx, by = ring ? p.ry : p.ry * p.waves;
+    // LDS ring: whole rows (vx cells per lane), ry rows per workgroup; the
+    // one-pass front kernel: 128-cell x tiles, ry rows per workgroup
+    const bool fch = p.kernel == RD_KERNEL_FUSED;
+    const bool ring = p.kernel == RD_KERNEL_LDS || p.kernel == RD_KERNEL_LDS2 || fch;
+    const int tx = fch ? kFchTile : 64 * p.vx, by = ring ? p.ry : p.ry * p.waves;
     const int cz = (p.cz <= 0 || p.cz > a.nz) ? a.nz : p.cz;
     a.tiles_x = (a.nx + tx - 1) / tx;
     a.tiles_y = (a.ny + by - 1) / by;
@@ -272,9 +290,45 @@ bool ring_row_fits(const rd_grid* g, int nch) {
 // Default plan: the plane-block kernel with the compiled slab shape that
 // wastes the fewest lanes and rows (ties: wider rows, one row per wave,
 // four-plane slabs, multi-wave workgroups).
+int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out);
+
+// z chunk length of a ring plan with `tiles` xy tiles and one workgroup per
+// CU: the length that minimises whole rounds of workgroups times the planes a
+// workgroup streams (its chunk plus about three halo planes).
+int balanced_cz(const rd_grid* g, long long tiles) {
+    int best = 0;
+    double best_t = 1e300;
+    for (int cz : {8, 16, 24, 32, 48, 64, 96, 128, 0}) {
+        const int c = (cz <= 0 || cz >= g->nz) ? int(g->nz) : cz;
+        const long long wg = tiles * ((g->nz + c - 1) / c);
+        const double t = double((wg + num_cus() - 1) / num_cus()) * (c + 3);
+        if (t < best_t) {
+            best_t = t;
+            best = c >= g->nz ? 0 : c;
+        }
+    }
+    return best;
+}
+
 rd_plan heuristic_plan(const rd_grid* g) {
     rd_plan best{};
     best.kernel = RD_KERNEL_DIRECT;
+    if (g->model == RD_MODEL_FRONT_CH && !g->args[0][0].s19) {
+        // the one-pass front kernel, its largest shape for this storage
+        for (int i = 0; i < kNumFchCfgs; ++i) {
+            if (!fch_ok(g->storage, i)) continue;
+            rd_plan p{};
+            p.kernel = RD_KERNEL_FUSED;
+            p.vx = kFchCfgs[i].wm;
+            p.ry = kFchCfgs[i].by;
+            p.waves = kFchCfgs[i].wu;
+            p.prefetch = kFchCfgs[i].d;
+            const long long tiles = ((g->nx + kFchTile - 1) / kFchTile) * ((g->ny + p.ry - 1) / p.ry);
+            p.cz = balanced_cz(g, tiles);
+            int cfg = -1;
+            if (check_plan(g, p, &cfg) == RD_OK) return p;
+        }
+    }
     if (g->args[0][0].s19) {
         // 19-point: the first LDS-ring shape this grid and model take, with
         // z chunks that give about two workgroups per CU; else direct
@@ -326,9 +380,11 @@ rd_plan heuristic_plan(const rd_grid* g) {
 }
 
 std::mutex g_tune_mu;
-// autotuned plans by (nx, ny, nz, species, model and stencil, storage)
+// autotuned plans by (nx, ny, nz, species, model, stencil and integrator, storage)
 std::map<std::tuple<int64_t, int64_t, int64_t, int, int, int>, rd_plan> g_tune_cache;
-int tune_model_key(const rd_grid* g) { return g->model * 2 + (g->args[0][0].s19 ? 1 : 0); }
+int tune_model_key(const rd_grid* g) {
+    return (g->model * 2 + (g->args[0][0].s19 ? 1 : 0)) * 4 + g->integrator;
+}
 
 int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
     if (p.graph_chunk != 0 && (p.graph_chunk < 2 || (p.graph_chunk & 1)))
@@ -366,6 +422,21 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
         *cfg_out = cfg;
         return RD_OK;
     }
+    if (p.kernel == RD_KERNEL_FUSED) {
+        const int cfg = fch_cfg_index(p.ry, p.waves, p.vx, p.prefetch);
+        if (cfg < 0) return fail(RD_EINVAL, "one-pass front shape not available");
+        if (g->model != RD_MODEL_FRONT_CH || g->args[0][0].s19)
+            return fail(RD_EINVAL, "the one-pass plan takes the 7-point front model only");
+        if (!fch_ok(g->storage, cfg)) return fail(RD_EINVAL, "one-pass front shape not compiled for this storage");
+        // the chemical potential one column beyond a 128-cell tile needs C
+        // two columns on: a periodic x axis ending one cell into a tile would
+        // wrap there
+        if (g->args[0][1].bck[2][0] == BC_PERIODIC && g->nx > kFchTile && g->nx % kFchTile != 0)
+            return fail(RD_EINVAL, "the one-pass plan needs nx <= 128 or a multiple of 128 for a periodic x axis of C");
+        if (p.cz < 0) return fail(RD_EINVAL, "cz must be >= 0");
+        *cfg_out = cfg;
+        return RD_OK;
+    }
     if (p.kernel == RD_KERNEL_LDS2) {
         const int cfg = (p.vx == 4 || p.vx == 8) ? lds2_cfg_index(p.vx / 4, p.ry, p.waves, p.prefetch) : -1;
         if (cfg < 0) return fail(RD_EINVAL, "two-step LDS ring shape not available");
@@ -390,21 +461,27 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
 // Resolve the plan in use, fill tiling into the argument copies, upload them.
 int apply_plan(rd_grid* g) {
     rd_plan p = g->plan;
+    int cfg = -1;
     if (p.kernel == RD_KERNEL_AUTO) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find({g->nx, g->ny, g->nz, g->ns, tune_model_key(g), g->storage});
         const int gc = p.graph_chunk;
         p = it != g_tune_cache.end() ? it->second : heuristic_plan(g);
         p.graph_chunk = gc;
+        // a cached plan this grid cannot take (other settings since it was
+        // tuned) gives way to the heuristic one
+        if (check_plan(g, p, &cfg) != RD_OK) {
+            p = heuristic_plan(g);
+            p.graph_chunk = gc;
+        }
     }
-    int cfg = -1;
     int rc = check_plan(g, p, &cfg);
     if (rc) return rc;
     for (int par = 0; par < 2; ++par)
         for (int k = 0; k < g->npass; ++k) {
             StepArgs& a = g->args[par][k];
             if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS ||
-                p.kernel == RD_KERNEL_LDS2) {
+                p.kernel == RD_KERNEL_LDS2 || p.kernel == RD_KERNEL_FUSED) {
                 g->blocks[k] = set_tiling(a, p);
                 (void)set_tiling(g->rk_args[par][k], p);
                 (void)set_tiling(g->rk3_args[par][k], p);
@@ -417,6 +494,14 @@ int apply_plan(rd_grid* g) {
             return fail(RD_EINVAL, "too many workgroups for this plan");
     g->eff = p;
     g->cfg = cfg;
+    // the step's first launch advances the step clock: the chemical-potential
+    // pass of the two-pass front step, or the one-pass kernel
+    if (g->model == RD_MODEL_FRONT_CH)
+        for (int par = 0; par < 2; ++par)
+            for (auto* set : {&g->args, &g->rk_args, &g->rk3_args}) {
+                (*set)[par][0].clk_pass = p.kernel == RD_KERNEL_FUSED ? 0 : 1;
+                (*set)[par][1].clk_pass = p.kernel == RD_KERNEL_FUSED ? 1 : 0;
+            }
     drop_graphs(g);
     RD_HIP(hipMemcpy(g->d_args, g->args, sizeof(g->args), hipMemcpyHostToDevice));
     RD_HIP(hipMemcpy(g->d_args + 4, g->rk_args, sizeof(g->rk_args), hipMemcpyHostToDevice));
@@ -424,7 +509,16 @@ int apply_plan(rd_grid* g) {
     return RD_OK;
 }
 
+// The one-pass front step: the update pass's arguments, one launch.
+bool one_pass(const rd_grid* g) { return g->eff.kernel == RD_KERNEL_FUSED; }
+
 int launch_one_step(rd_grid* g, int parity) {
+    if (one_pass(g)) {
+        const hipError_t e = launch_fch(g->storage, g->cfg, g->args[parity][1], g->d_args + parity * 2 + 1,
+                                        g->blocks[1], g->stream);
+        if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        return RD_OK;
+    }
     for (int k = 0; k < g->npass; ++k) {
         const hipError_t e = launch_pass(g->storage, g->pass_pm[k], g->eff.kernel, g->cfg,
                                          g->args[parity][k], g->d_args + parity * 2 + k,
@@ -438,6 +532,12 @@ int launch_one_step(rd_grid* g, int parity) {
 // passes.
 int launch_set(rd_grid* g, int set, int parity) {
     const StepArgs(&h)[2][2] = set == 1 ? g->rk_args : g->rk3_args;
+    if (one_pass(g)) {
+        const hipError_t e = launch_fch(g->storage, g->cfg, h[parity][1], g->d_args + 4 * set + parity * 2 + 1,
+                                        g->blocks[1], g->stream);
+        if (e != hipSuccess) return fail(RD_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        return RD_OK;
+    }
     for (int k = 0; k < g->npass; ++k) {
         const hipError_t e = launch_pass(g->storage, g->pass_pm[k], g->eff.kernel, g->cfg, h[parity][k],
                                          g->d_args + 4 * set + parity * 2 + k, g->blocks[k], g->stream);
@@ -665,6 +765,11 @@ extern "C" int rd_validate_model(int64_t nx, int64_t ny, int64_t nz, int32_t ns,
 
 extern "C" const char* rd_last_error(void) { return g_err.c_str(); }
 extern "C" int rd_abi_version(void) { return RD_ABI_VERSION; }
+
+#ifndef RD_SOURCE_DIGEST
+#define RD_SOURCE_DIGEST "unknown"
+#endif
+extern "C" const char* rd_source_digest(void) { return RD_SOURCE_DIGEST; }
 
 extern "C" int rd_create_grid(int64_t nx, int64_t ny, int64_t nz, int32_t nspecies, double h,
                               int32_t storage_dtype, void* hip_stream, rd_grid** out) {
@@ -898,6 +1003,9 @@ extern "C" int rd_set_model(rd_grid* g, const rd_model_desc* m) {
         for (StepArgs& a : row) {
             a.sr = g->sr_mode == RD_ROUND_STOCHASTIC ? 1 : 0;
             a.sr_key = g->sr_seed;
+            // the centre weight of the front model's Laplacian form, one FP32
+            // value shared by every kernel
+            for (int f = 0; f < MAXF; ++f) a.kc[f] = 2.f * ((a.kx[f] + a.ky[f]) + a.kz[f]);
         }
     // Runge-Kutta stages: the same step with other buffers, its stored state
     // blended with the current state A (see launch_rk_step).  The chemical
@@ -974,7 +1082,7 @@ extern "C" int rd_get_plan(const rd_grid* g, rd_plan* p) {
 extern "C" int rd_get_passes(const rd_grid* g, int32_t* out) {
     if (!g || !out) return fail(RD_EINVAL, "NULL argument");
     if (!g->has_model) return fail(RD_ESTATE, "no model set");
-    *out = g->npass;
+    *out = one_pass(g) ? 1 : g->npass;
     return RD_OK;
 }
 
@@ -1137,8 +1245,11 @@ extern "C" int rd_reduce(rd_grid* g, int32_t species, double out[2]) {
 extern "C" int rd_chemical_potential(rd_grid* g, float* dst_host) {
     if (!g || !dst_host) return fail(RD_EINVAL, "NULL argument");
     if (!g->has_model || g->model != RD_MODEL_FRONT_CH) return fail(RD_ESTATE, "needs the front model");
-    const hipError_t e = launch_pass(g->storage, PM_CHMU, g->eff.kernel, g->cfg, g->args[g->cur][0],
-                                     g->d_args + g->cur * 2, g->blocks[0], g->stream);
+    // the one-pass plan keeps no mu array: the direct kernel's first pass fills it
+    const hipError_t e = one_pass(g) ? launch_pass(g->storage, PM_CHMU, RD_KERNEL_DIRECT, -1, g->args[g->cur][0],
+                                                   g->d_args + g->cur * 2, 0, g->stream)
+                                     : launch_pass(g->storage, PM_CHMU, g->eff.kernel, g->cfg, g->args[g->cur][0],
+                                                   g->d_args + g->cur * 2, g->blocks[0], g->stream);
     if (e != hipSuccess) return fail(RD_EDEVICE, std::string("mu pass: ") + hipGetErrorString(e));
     const size_t n = size_t(g->nx) * g->ny * g->nz;
     float* stage = nullptr;
@@ -1221,6 +1332,28 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
         cands.push_back(p);
         p.order = 1;
         cands.push_back(p);
+    }
+    for (int i = 0; i < kNumFchCfgs && g->model == RD_MODEL_FRONT_CH && !g->args[0][0].s19; ++i) {
+        if (!fch_ok(g->storage, i)) continue;
+        const FchCfg c = kFchCfgs[i];
+        const long long tiles = ((g->nx + kFchTile - 1) / kFchTile) * ((g->ny + c.by - 1) / c.by);
+        std::vector<int> czs = {0, 64, 32, 16};
+        const int bal = balanced_cz(g, tiles);
+        if (std::find(czs.begin(), czs.end(), bal) == czs.end()) czs.push_back(bal);
+        for (int cz : czs) {
+            if (cz != 0 && cz >= g->nz) continue;
+            for (int order : {0, 1}) {
+                rd_plan p{};
+                p.kernel = RD_KERNEL_FUSED;
+                p.vx = c.wm;
+                p.ry = c.by;
+                p.waves = c.wu;
+                p.prefetch = c.d;
+                p.cz = cz;
+                p.order = order;
+                cands.push_back(p);
+            }
+        }
     }
     for (int i = 0; i < kNumLds2Cfgs && g->npass == 1; ++i) {
         const LdsCfg c = kLds2Cfgs[i];

@@ -21,7 +21,7 @@ F32, BF16, F16, F64 = 0, 1, 2, 3
 STORAGE = {"f32": F32, "bf16": BF16, "f16": F16}
 MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3, "turing": 4, "atmos": 5}
 BC = {"mirror": 0, "periodic": 1, "ghost": 2, "held": 3}
-KERNEL = {"auto": 0, "direct": 1, "tiled": 2, "block": 3, "lds": 4, "lds2": 5}
+KERNEL = {"auto": 0, "direct": 1, "tiled": 2, "block": 3, "lds": 4, "lds2": 5, "fused": 6}
 INTEGRATOR = {"euler": 1, "rk2": 2, "rk3": 3}
 PARAMS = {
     "diffusion": (),
@@ -97,6 +97,7 @@ _SIGS = {
     "rd_copy_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "rd_last_error": (C.c_char_p, []),
     "rd_abi_version": (C.c_int, []),
+    "rd_source_digest": (C.c_char_p, []),
 }
 
 
@@ -120,6 +121,22 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def source_digest() -> str:
+    """Digest of the sources the loaded library was built from."""
+    return lib().rd_source_digest().decode()
+
+
+def check_build_matches_sources():
+    """Raise if the loaded library was built from other sources than the
+    csrc/ files beside it (a stale binary would test and time old kernels)."""
+    from . import build as _build
+    want, got = _build.source_digest(), source_digest()
+    if got != want:
+        raise RuntimeError("librdmi.so was built from sources %s but csrc/ hashes to %s: rebuild "
+                           "(__graft_entry__.build())" % (got, want))
+    return got
 
 
 def exported_symbols() -> List[str]:

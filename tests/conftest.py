@@ -18,3 +18,12 @@ def oracle():
     import oracle as _oracle
     _oracle._load()
     return _oracle
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _library_matches_sources(request):
+    """GPU runs test the library built from the sources beside them: a stale
+    librdmi.so (built before a source change) is refused before any test."""
+    if any(item.get_closest_marker("gpu") for item in request.session.items):
+        from paper_1004_0480_amd import rd
+        rd.check_build_matches_sources()

@@ -29,6 +29,13 @@ def test_library_loads_and_exports_header_functions():
     assert L.rd_abi_version() == 1
 
 
+def test_library_built_from_these_sources():
+    """The digest compiled into the library is the digest of csrc/ now."""
+    from paper_1004_0480_amd import build
+    assert rd.source_digest() == build.source_digest()
+    assert rd.check_build_matches_sources() == build.source_digest()
+
+
 def test_model_desc_layout_matches_header():
     # int32 model, int32 nspecies, double dt, 4x3 double, 4x6 int32, 4x6 double,
     # 8 double, ptr, int64, int64, ptr, ptr, ptr, int32 stencil (+4 padding)

@@ -43,6 +43,9 @@ def test_algorithmic_bytes_per_cell():
     assert bench.alg_bytes_per_cell("pollutant512", "f32") == 32
     assert bench.alg_bytes_per_cell("front384", "f32") == 36
     assert bench.alg_bytes_per_cell("front384", "bf16") == 12 + 8 + 2
+    # the one-pass front step moves each species once each way
+    assert bench.alg_bytes_per_cell("front384", "f32", one_pass=True) == 24
+    assert bench.alg_bytes_per_cell("front384", "bf16", one_pass=True) == 12
     assert bench.alg_bytes_per_cell("t1_turing192", "f32") == 16
 
 
@@ -68,7 +71,8 @@ def test_kernel_source_digest_tracks_the_kernel_sources(tmp_path, monkeypatch):
     assert len(d) == 16 and int(d, 16) >= 0
     csrc = tmp_path / "paper_1004_0480_amd" / "csrc"
     shutil.copytree(os.path.join(ROOT, "paper_1004_0480_amd", "csrc"), csrc)
-    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    from paper_1004_0480_amd import build
+    monkeypatch.setattr(build, "CSRC", str(csrc))
     assert bench.kernel_source_digest() == d
     (csrc / "rd_device.hpp").write_text((csrc / "rd_device.hpp").read_text() + "\n")
     assert bench.kernel_source_digest() != d
@@ -97,7 +101,8 @@ def test_committed_pmc_summary_arithmetic(path):
     assert rec["hbm_read_bytes_per_launch_set"] == pytest.approx(rd)
     assert rec["hbm_write_bytes_per_launch_set"] == pytest.approx(wr)
     cells = int(np.prod(W.DEFAULT_SHAPES[workload]))
-    alg = bench.alg_bytes_per_cell(workload, "f32") * cells
+    one_pass = all("fch_kernel" in n for n in names)
+    alg = bench.alg_bytes_per_cell(workload, "f32", one_pass) * cells
     assert rec["algorithmic_bytes_per_launch_set"] == alg
     assert rec["traffic_over_algorithmic"] == pytest.approx((rd + wr) / alg)
     # a step kernel cannot move less than it must read and write
@@ -121,3 +126,17 @@ def test_every_summary_has_a_kind_the_bench_knows():
     for p in PMC + TRACES:
         b = os.path.basename(p)
         assert any(("_%s_" % k) in b for k in bench.KERNEL_NAMES.values()), b
+
+
+def test_cpu_sample_keeps_the_workload_or_its_lowest_planes():
+    """The CPU baseline's sample: the whole grid when it is small enough, else
+    the lowest z planes of the same problem (wind and sources cut to them)."""
+    w = W.make_workload("pollutant512", shape=(16, 12, 10))
+    same, where = bench.cpu_sample(w, 10 ** 6)
+    assert same is w and where == "whole grid"
+    sub, where = bench.cpu_sample(w, 12 * 10 * 5)
+    assert sub.shape == (5, 12, 10) and "5 of 16" in where
+    assert len(sub.spec.wind) == 5 and np.array_equal(sub.spec.wind, w.spec.wind[:5])
+    assert np.all(sub.spec.sources[0] < 5 * 12 * 10)
+    for a, b in zip(sub.fields, w.fields):
+        assert np.array_equal(a, b[:5])

@@ -30,6 +30,10 @@ LDS_SHAPES = [(4, 8, 4, 7), (4, 8, 8, 7), (8, 8, 4, 6), (8, 4, 4, 6), (8, 8, 8, 
 # two-steps-per-launch shapes (same fields)
 LDS2_SHAPES = [(4, 4, 8, 6), (8, 4, 8, 6), (4, 8, 8, 5), (8, 6, 6, 4), (4, 6, 12, 4), (8, 6, 12, 4),
                (8, 4, 12, 6), (4, 4, 12, 6)]
+# one-pass front shapes (rows per workgroup, update waves, chemical-potential
+# waves, ring slots)
+FCH_SHAPES = [(8, 8, 5, 7), (4, 4, 3, 7), (4, 4, 3, 6), (2, 2, 2, 7), (4, 4, 2, 7), (8, 8, 4, 8), (16, 8, 6, 7),
+              (4, 4, 3, 9), (8, 8, 5, 6), (4, 4, 3, 5), (4, 4, 2, 5), (8, 8, 5, 5)]
 BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
                 (2, 1, 4, 4), (4, 2, 1, 2), (4, 1, 1, 2), (4, 2, 1, 4), (4, 4, 1, 2), (4, 2, 2, 2),
                 (4, 3, 1, 2)]
@@ -66,6 +70,8 @@ def compiled_plans(w, storage="f32", czs=(0, 8)):
               for vx, by, wc, d in LDS_SHAPES for cz in czs for o in (0, 1)]
     cands += [dict(kernel="lds2", vx=vx, ry=by, waves=wc, prefetch=d, cz=cz, order=o)
               for vx, by, wc, d in LDS2_SHAPES for cz in czs for o in (0, 1)]
+    cands += [dict(kernel="fused", vx=wm, ry=by, waves=wu, prefetch=d, cz=cz, order=o)
+              for by, wu, wm, d in FCH_SHAPES for cz in czs for o in (0, 1)]
     for p in cands:
         try:
             g.set_plan(**p)
@@ -214,13 +220,18 @@ def test_pollutant_parity():
 
 
 def test_pass_structure():
-    """One launch per step, or two: the front model's chemical-potential pass,
-    and more than two pollutants split into the coupled pair and the rest."""
-    expect = {"brusselator256": 1, "diffusion64": 1, "front384": 2, "pollutant512": 2}
+    """One launch per step, or two: the front model's chemical-potential pass
+    (one launch with the one-pass plan, the default), and more than two
+    pollutants split into the coupled pair and the rest."""
+    expect = {"brusselator256": 1, "diffusion64": 1, "front384": 1, "pollutant512": 2}
     for name, n in expect.items():
         w = W.make_workload(name, shape=(6, 7, 9))
         g = rd.Grid.from_workload(w)
         assert g.passes() == n, name
+        if name == "front384":
+            assert g.plan()["kernel"] == rd.KERNEL["fused"]
+            g.set_plan(kernel="direct")
+            assert g.passes() == 2
         g.close()
     for ns, n in ((1, 1), (2, 1), (3, 2)):
         shape = (6, 7, 9)
@@ -267,6 +278,94 @@ def test_every_plan_bitwise_identical(name, shape, steps):
             continue
         for s in range(w.spec.ns):
             assert np.array_equal(got[s], base[s]), (name, plan, s)
+
+
+# ------------------------------------------------ one-pass front step (P9)
+
+def front_case(case):
+    """Front-model grids for the one-pass plan: ragged and whole 128-cell
+    tiles, one-cell last tiles, every face kind on C (mu stays mirrored),
+    held and fixed faces on A and B, periodic x (whole tiles)."""
+    base = {"nx70": (9, 10, 70), "nx129": (7, 11, 129), "nx200": (8, 13, 200), "nx256p": (7, 9, 256),
+            "nx384": (6, 17, 384), "nx128p": (10, 8, 128), "nx257": (5, 9, 257)}[case]
+    w = W.make_workload("front384", shape=base)
+    spec = w.spec
+    rng = np.random.default_rng(sum(base))
+    if case in ("nx70", "nx200", "nx257"):
+        spec.bc[2] = [(HELD, 0.3), (GHOST, 0.1), (GHOST, -0.2), (HELD, 0.4), (HELD, 0.5), (GHOST, 0.0)]
+        spec.bc[1] = [(GHOST, 0.2), (HELD, 0.6), (MIRROR, 0), (GHOST, 0.3), (MIRROR, 0), (HELD, 0.1)]
+    elif case == "nx129":
+        spec.bc[2] = [(MIRROR, 0), (HELD, -0.25), (MIRROR, 0), (GHOST, 0.5), (GHOST, -0.5), (MIRROR, 0)]
+        spec.bc[0] = [(HELD, 1.0), (GHOST, 0.0), (PERIODIC, 0), (PERIODIC, 0), (MIRROR, 0), (MIRROR, 0)]
+    elif case in ("nx256p", "nx128p"):
+        for s in range(3):
+            spec.bc[s][0] = spec.bc[s][1] = (PERIODIC, 0.0)
+        spec.bc[2][2] = spec.bc[2][3] = (PERIODIC, 0.0)
+        spec.bc[2][4] = spec.bc[2][5] = (PERIODIC, 0.0)
+    fields = [f.astype(np.float32).astype(np.float64) for f in w.fields]
+    fields[0] = rng.uniform(0.0, 1.0, base).astype(np.float32).astype(np.float64)
+    fields[2] = rng.uniform(-1.0, 1.0, base).astype(np.float32).astype(np.float64)
+    return W.Workload("front_" + case, base, spec, fields, 5, 0)
+
+
+@pytest.mark.parametrize("case", ["nx70", "nx129", "nx200", "nx256p", "nx384", "nx128p", "nx257"])
+def test_front_one_pass_bitwise_equals_two_pass(case):
+    """The one-pass front step computes mu in LDS instead of an array, with
+    the same arithmetic: every one-pass shape gives the bits of the two-pass
+    direct plan, which matches the FP64 oracle."""
+    w = front_case(case)
+    steps = 5
+    ref = oracle.run(w.spec, w.fields, steps)
+    two, _ = gpu_run(w, steps, plan=dict(kernel="direct"))
+    for s in range(3):
+        assert rel_l2(two[s], ref[s]) <= TOL, (case, s)
+    plans = [p for p in compiled_plans(w, czs=(0, 1, 3)) if p["kernel"] == "fused"]
+    assert plans, case
+    for plan in plans:
+        got, _ = gpu_run(w, steps, plan=plan)
+        for s in range(3):
+            assert np.array_equal(got[s], two[s]), (case, plan, s)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_front_one_pass_reduced_storage_and_rk(storage):
+    """2-byte storage and the Runge-Kutta stages on the one-pass plan: the
+    same bits as the two-pass direct plan."""
+    w = front_case("nx200")
+    for integ in ("euler", "rk2", "rk3"):
+        if integ != "euler" and storage == "f16":
+            continue
+        w.spec.integrator = integ
+        two, _ = gpu_run(w, 4, storage=storage, plan=dict(kernel="direct"))
+        plans = [p for p in compiled_plans(w, storage=storage, czs=(0, 3)) if p["kernel"] == "fused"]
+        assert plans
+        for plan in plans:
+            got, _ = gpu_run(w, 4, storage=storage, plan=plan)
+            for s in range(3):
+                assert np.array_equal(got[s], two[s]), (storage, integ, plan, s)
+    w.spec.integrator = "euler"
+
+
+def test_front_one_pass_refusals():
+    """The one-pass plan takes the 7-point front model only, and a periodic x
+    axis of C only for nx <= 128 or a multiple of 128."""
+    w = W.make_workload("brusselator256", shape=(6, 8, 70))
+    g = rd.Grid.from_workload(w)
+    with pytest.raises(rd.RDError):
+        g.set_plan(kernel="fused", vx=3, ry=4, waves=4, prefetch=7)
+    g.close()
+    w = front_case("nx200")
+    for s in range(3):
+        w.spec.bc[s][0] = w.spec.bc[s][1] = (PERIODIC, 0.0)
+    g = rd.Grid.from_workload(w)
+    with pytest.raises(rd.RDError):
+        g.set_plan(kernel="fused", vx=3, ry=4, waves=4, prefetch=7)
+    g.close()
+    w19 = as19(front_case("nx70"))
+    g = rd.Grid.from_workload(w19)
+    with pytest.raises(rd.RDError):
+        g.set_plan(kernel="fused", vx=3, ry=4, waves=4, prefetch=7)
+    g.close()
 
 
 # ---------------------------------------------------- storage precisions

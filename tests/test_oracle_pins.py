@@ -784,3 +784,23 @@ def test_bf16_stochastic_rounding_is_unbiased():
     assert np.mean(y.astype(np.float64)) == float(x)
     z = bf16_stochastic(np.float32([0.5, -3.0]), np.uint32([65535, 65535]))
     assert z.tolist() == [0.5, -3.0]         # representable values never move
+
+
+def test_random16_positions_are_uniform_and_independent():
+    """The four 16-bit draws taken from one Philox-2x32-10 call (elements 4c
+    .. 4c+3) are each uniform on 0 .. 2^16-1 and uncorrelated with their
+    neighbours, over 2^18 consecutive elements of one step."""
+    from oracle.stochastic import random16
+    e = np.arange(1 << 18, dtype=np.uint64)
+    r = random16(e, 7, 20240611, 2).astype(np.float64)
+    n = r.size // 4
+    for q in range(4):
+        x = r[q::4]
+        assert abs(x.mean() - 32767.5) < 5 * 18918.6 / math.sqrt(n)
+        counts = np.bincount((x // 4096).astype(int), minlength=16)
+        chi2 = np.sum((counts - n / 16) ** 2 / (n / 16))
+        assert chi2 < 50.0                                  # 15 dof: p < 1e-5
+    c = np.corrcoef(r[:-1], r[1:])[0, 1]
+    assert abs(c) < 5 / math.sqrt(r.size)
+    # another step gives other bits for the same elements
+    assert np.mean(random16(e[:4096], 8, 20240611, 2) == r[:4096]) < 0.01
