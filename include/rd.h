@@ -257,6 +257,22 @@ int rd_reduce(rd_grid *g, int32_t species, double out_mass_energy[2]);
  * direct kernel computes it), dense [nz][ny][nx] on the host.  Synchronises. */
 int rd_chemical_potential(rd_grid *g, float *dst_host);
 
+/* Allocation-free reduction, for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the FP64 mass sum(c) h^3 and energy sum(c^2) h^3 of a dense
+ * [nz][ny][nx] device field of dtype RD_F32, RD_BF16 or RD_F16 at `field`,
+ * written to out_dev[0], out_dev[1] (caller-owned device memory), with the
+ * same kernels and summation order as rd_reduce (so a grid's field and a
+ * dense copy of it give the same bits).  Asynchronous on hip_stream; nothing
+ * is allocated and nothing synchronised.  The partial sums live in a fixed
+ * 16 KiB per-GPU array inside the library (2 x 1024 doubles, held until the
+ * process ends), so calls that overlap on one GPU race and must be ordered by
+ * the caller (one stream, or events).  Fields up to the largest grid
+ * (extents <= 2^24, 2^40 cells) are accepted, RD_EINVAL beyond; non-finite
+ * values give non-finite results (no check, no synchronisation). */
+int rd_reduce_noalloc(const void *field, int32_t dtype, int64_t nx, int64_t ny, int64_t nz, double h,
+                      double *out_dev, void *hip_stream);
+
 /* Wait for the grid's stream; RD_EDEVICE if a kernel failed. */
 int rd_sync(rd_grid *g);
 

@@ -1265,6 +1265,76 @@ extern "C" int rd_chemical_potential(rd_grid* g, float* dst_host) {
     return RD_OK;
 }
 
+// ------------------------------------------------ allocation-free reduction
+
+namespace {
+
+// The partial sums of one allocation-free reduction: one (sum, sum of
+// squares) pair per block of the first kernel, at most kRedBlocks blocks
+// (16 KiB).  Each GPU the library runs on holds its own copy until the
+// process ends.  Host code never uses this name as an address (it only
+// stands for the symbol); kernels get the device address resolved below.
+__device__ __align__(256) double scratch[2 * kRedBlocks];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// The address of the current device's scratch, resolved once per device.
+int scratch_on_current_device(double** out) {
+    int dev = 0;
+    RD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RD_EDEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RD_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RD_OK;
+}
+
+}  // namespace
+
+extern "C" int rd_reduce_noalloc(const void* field, int32_t dtype, int64_t nx, int64_t ny, int64_t nz, double h,
+                                 double* out_dev, void* hip_stream) {
+    if (!field || !out_dev) return fail(RD_EINVAL, "NULL argument");
+    if (dtype != RD_F32 && dtype != RD_BF16 && dtype != RD_F16)
+        return fail(RD_EINVAL, "dtype must be RD_F32, RD_BF16 or RD_F16");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(RD_EINVAL, "extents must be >= 1");
+    if (nx > (1 << 24) || ny > (1 << 24) || nz > (1 << 24) || (__int128)nx * ny * nz > (__int128)1 << 40)
+        return fail(RD_EINVAL, "field larger than the largest grid (extents <= 2^24, 2^40 cells)");
+    if (!(h > 0.0) || !is_finite(h)) return fail(RD_EINVAL, "h must be a positive finite number");
+    double* part = nullptr;
+    const int rc = scratch_on_current_device(&part);
+    if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    // one block per row, at most kRedBlocks of them: the scratch holds every
+    // partial pair the first kernel writes, so nothing needs clearing
+    const long long rows = ny * nz;
+    const int blocks = int(std::min<long long>(rows, kRedBlocks));
+    const int ix = int(nx), iy = int(ny), iz = int(nz);
+    const long long plane = nx * ny;
+    switch (dtype) {
+    case RD_F32:
+        hipLaunchKernelGGL((reduce_partial<StF32>), dim3(blocks), dim3(256), 0, st, field, ix, iy, iz, ix, plane, part);
+        break;
+    case RD_BF16:
+        hipLaunchKernelGGL((reduce_partial<StBF16>), dim3(blocks), dim3(256), 0, st, field, ix, iy, iz, ix, plane,
+                           part);
+        break;
+    default:
+        hipLaunchKernelGGL((reduce_partial<StF16>), dim3(blocks), dim3(256), 0, st, field, ix, iy, iz, ix, plane, part);
+        break;
+    }
+    hipLaunchKernelGGL(reduce_final, dim3(1), dim3(256), 0, st, part, blocks, h * h * h, out_dev);
+    RD_HIP(hipGetLastError());
+    return RD_OK;
+}
+
 // --------------------------------------------------------------- autotune
 
 extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {

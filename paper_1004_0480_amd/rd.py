@@ -98,6 +98,8 @@ _SIGS = {
     "rd_last_error": (C.c_char_p, []),
     "rd_abi_version": (C.c_int, []),
     "rd_source_digest": (C.c_char_p, []),
+    "rd_reduce_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int64, C.c_double,
+                                    C.c_void_p, C.c_void_p]),
 }
 
 
@@ -121,6 +123,14 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def reduce_noalloc(field_ptr: int, dtype: str, shape, h: float, out_ptr: int, stream=None):
+    """Mass and energy of a dense device field into two device doubles at
+    out_ptr, with no allocation (rd_reduce_noalloc); asynchronous."""
+    nz, ny, nx = shape
+    _check(lib().rd_reduce_noalloc(C.c_void_p(field_ptr), STORAGE[dtype], nx, ny, nz, float(h),
+                                   C.c_void_p(out_ptr), _stream_handle(stream)))
 
 
 def source_digest() -> str:
