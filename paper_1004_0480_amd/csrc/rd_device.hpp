@@ -98,15 +98,28 @@ struct StF32 {
     static __device__ __forceinline__ T down(float v) { return v; }
 };
 
+typedef float rd_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 rd_bf16x2 __attribute__((ext_vector_type(2)));
+
 struct StBF16 {
     using T = uint16_t;
     static __device__ __forceinline__ float up(T v) { return __uint_as_float(uint32_t(v) << 16); }
-    // round to nearest even; NaN stays NaN
+    // round to nearest even (the hardware conversion); NaN stays NaN
     static __device__ __forceinline__ T down(float f) {
-        uint32_t u = __float_as_uint(f);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return T((u >> 16) | 0x40u);
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return T(u >> 16);
+        const __bf16 b = (__bf16)f;
+        T v;
+        __builtin_memcpy(&v, &b, 2);
+        return v;
+    }
+    // two values in one packed conversion, first value in the low half
+    static __device__ __forceinline__ uint32_t down2(float f0, float f1) {
+        rd_f32x2 x;
+        x.x = f0;
+        x.y = f1;
+        const rd_bf16x2 b = __builtin_convertvector(x, rd_bf16x2);
+        uint32_t v;
+        __builtin_memcpy(&v, &b, 4);
+        return v;
     }
 };
 
@@ -181,8 +194,18 @@ template <class S, int VX>
 __device__ __forceinline__ void store_vec(void* base, long long idx, const float (&o)[VX]) {
     using T = typename S::T;
     Vec<T, VX> r;
+    if constexpr (std::is_same_v<S, StBF16> && VX % 2 == 0) {
+        // pairs through the packed conversion
 #pragma unroll
-    for (int i = 0; i < VX; ++i) r.v[i] = S::down(o[i]);
+        for (int i = 0; i < VX; i += 2) {
+            const uint32_t p = StBF16::down2(o[i], o[i + 1]);
+            r.v[i] = T(p & 0xffffu);
+            r.v[i + 1] = T(p >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < VX; ++i) r.v[i] = S::down(o[i]);
+    }
     RD_GLOBAL T* dst = gstore_ptr<T>(base) + idx;
 #if RD_NT_STORE
     // streaming store: the next step reads these values from HBM anyway

@@ -477,12 +477,7 @@ struct FchConsumer {
                 if constexpr (PLAIN) {
                     const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
 #pragma unroll
-                    for (int s = 0; s < 3; ++s) {
-                        Vec<T, 2> v;
-                        v.v[0] = S::down(o[s][0]);
-                        v.v[1] = S::down(o[s][1]);
-                        *(RD_GLOBAL Vec<T, 2>*)(gstore_ptr<T>(a.out[s]) + idx) = v;
-                    }
+                    for (int s = 0; s < 3; ++s) store_vec<S, 2>(a.out[s], idx, o[s]);
                 } else {
 #pragma unroll
                     for (int s = 0; s < 3; ++s) store_field<S, 2>(a, s, xl, y, z, o[s]);
