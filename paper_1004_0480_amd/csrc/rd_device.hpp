@@ -152,9 +152,11 @@ struct StF64 {
 // compiler only parses this code; it gets no address space.)
 #ifdef __HIP_DEVICE_COMPILE__
 #define RD_GLOBAL __attribute__((address_space(1)))
+#define RD_CONST __attribute__((address_space(4)))
 #define RD_LDS __attribute__((address_space(3)))
 #else
 #define RD_GLOBAL
+#define RD_CONST
 #define RD_LDS
 #endif
 template <typename T>
@@ -164,6 +166,15 @@ __device__ __forceinline__ const RD_GLOBAL T* gload_ptr(const void* p) {
 template <typename T>
 __device__ __forceinline__ RD_GLOBAL T* gstore_ptr(void* p) {
     return (RD_GLOBAL T*)p;
+}
+// Tables that no thread of the running launch writes -- the clock of the
+// step's input state, the wind profile, the source lists -- are read as
+// constant memory: a uniform index then becomes a scalar load, and the
+// compiler may reuse one load across the launch's stores instead of issuing
+// a vector load (and a wait on every store in flight) at each use.
+template <typename T>
+__device__ __forceinline__ const RD_CONST T* cload_ptr(const void* p) {
+    return (const RD_CONST T*)p;
 }
 
 // The LDS-ring kernels address their rings through LDS pointers taken from
@@ -191,7 +202,7 @@ __device__ __forceinline__ void load_vec(const void* base, long long idx, float 
 }
 
 template <class S, int VX>
-__device__ __forceinline__ void store_vec(void* base, long long idx, const float (&o)[VX]) {
+__device__ __forceinline__ void store_vec_at(RD_GLOBAL typename S::T* dst, const float (&o)[VX]) {
     using T = typename S::T;
     Vec<T, VX> r;
     if constexpr (std::is_same_v<S, StBF16> && VX % 2 == 0) {
@@ -206,7 +217,6 @@ __device__ __forceinline__ void store_vec(void* base, long long idx, const float
 #pragma unroll
         for (int i = 0; i < VX; ++i) r.v[i] = S::down(o[i]);
     }
-    RD_GLOBAL T* dst = gstore_ptr<T>(base) + idx;
 #if RD_NT_STORE
     // streaming store: the next step reads these values from HBM anyway
     if constexpr (sizeof(r) == 16) {
@@ -223,6 +233,11 @@ __device__ __forceinline__ void store_vec(void* base, long long idx, const float
 #else
     *(RD_GLOBAL Vec<T, VX>*)dst = r;
 #endif
+}
+
+template <class S, int VX>
+__device__ __forceinline__ void store_vec(void* base, long long idx, const float (&o)[VX]) {
+    store_vec_at<S, VX>(gstore_ptr<typename S::T>(base) + idx, o);
 }
 
 template <class S>
@@ -246,10 +261,11 @@ struct PhiloxOut { unsigned w0, w1; };
 __device__ __forceinline__ PhiloxOut philox2x32_10(unsigned c0, unsigned c1, unsigned k) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const unsigned hi = __umulhi(0xD256D193u, c0);
-        const unsigned lo = 0xD256D193u * c0;
-        c0 = hi ^ k ^ c1;
-        c1 = lo;
+        // the whole 64-bit product in one multiply-add (v_mad_u64_u32)
+        // rather than separate high and low multiplies
+        const unsigned long long p = (unsigned long long)0xD256D193u * c0;
+        c0 = unsigned(p >> 32) ^ k ^ c1;
+        c1 = unsigned(p);
         k += 0x9E3779B9u;
     }
     return PhiloxOut{c0, c1};
@@ -294,28 +310,51 @@ __device__ __forceinline__ void store_field(const StepArgs& a, int s, int x, int
     rk_blend<S, VX>(a, s, idx, o);
     if constexpr (std::is_same_v<S, StBF16>) {
         if (a.sr) {
-            const unsigned n = unsigned(gload_ptr<StepClock>(a.clk_in)->n);
+            const unsigned n = unsigned(cload_ptr<StepClock>(a.clk_in)->n);
             const unsigned key = a.sr_key + unsigned(a.sp0 + s);
             const unsigned long long e0 = ((unsigned long long)z * unsigned(a.ny) + unsigned(y)) * unsigned(a.nx) +
                                           unsigned(x);
-            // the VX elements span at most NR consecutive counters
-            constexpr int NR = (VX + 6) / 4;
-            const unsigned c_first = unsigned(e0 >> 2), c_last = unsigned((e0 + VX - 1) >> 2);
-            PhiloxOut r[NR];
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                r[k] = PhiloxOut{0u, 0u};
-                if (c_first + unsigned(k) <= c_last) r[k] = philox2x32_10(c_first + unsigned(k), n, key);
-            }
             Vec<uint16_t, VX> w;
+            // G elements starting at a multiple of G share one counter: then
+            // the VX elements need exactly ceil(VX / 4) calls (the kernels
+            // place a lane's cells at multiples of VX, so this holds whenever
+            // the row length is a multiple of G)
+            constexpr int G = VX >= 4 ? 4 : VX;
+            if (G > 1 && VX % G == 0 && (unsigned(e0) & unsigned(G - 1)) == 0) {
+                const unsigned c0 = unsigned(e0 >> 2);
 #pragma unroll
-            for (int i = 0; i < VX; ++i) {
-                const unsigned long long e = e0 + unsigned(i);
-                const unsigned kk = unsigned(e >> 2) - c_first;
-                PhiloxOut ri = r[0];
+                for (int g = 0; g < VX / G; ++g) {
+                    const PhiloxOut r = philox2x32_10(c0 + unsigned(g * G / 4), n, key);
+                    if constexpr (G == 4) {
+                        w.v[4 * g + 0] = bf16_stochastic(o[4 * g + 0], r.w0 & 0xffffu);
+                        w.v[4 * g + 1] = bf16_stochastic(o[4 * g + 1], r.w0 >> 16);
+                        w.v[4 * g + 2] = bf16_stochastic(o[4 * g + 2], r.w1 & 0xffffu);
+                        w.v[4 * g + 3] = bf16_stochastic(o[4 * g + 3], r.w1 >> 16);
+                    } else {
+                        const unsigned wd = (unsigned(e0) & 2u) ? r.w1 : r.w0;
+                        w.v[0] = bf16_stochastic(o[0], wd & 0xffffu);
+                        w.v[1] = bf16_stochastic(o[1], wd >> 16);
+                    }
+                }
+            } else {
+                // the VX elements span at most NR consecutive counters
+                constexpr int NR = (VX + 6) / 4;
+                const unsigned c_first = unsigned(e0 >> 2), c_last = unsigned((e0 + VX - 1) >> 2);
+                PhiloxOut r[NR];
 #pragma unroll
-                for (int k = 1; k < NR; ++k) ri = kk == unsigned(k) ? r[k] : ri;
-                w.v[i] = bf16_stochastic(o[i], philox_bits16(ri, unsigned(e) & 3u));
+                for (int k = 0; k < NR; ++k) {
+                    r[k] = PhiloxOut{0u, 0u};
+                    if (c_first + unsigned(k) <= c_last) r[k] = philox2x32_10(c_first + unsigned(k), n, key);
+                }
+#pragma unroll
+                for (int i = 0; i < VX; ++i) {
+                    const unsigned long long e = e0 + unsigned(i);
+                    const unsigned kk = unsigned(e >> 2) - c_first;
+                    PhiloxOut ri = r[0];
+#pragma unroll
+                    for (int k = 1; k < NR; ++k) ri = kk == unsigned(k) ? r[k] : ri;
+                    w.v[i] = bf16_stochastic(o[i], philox_bits16(ri, unsigned(e) & 3u));
+                }
             }
             *(RD_GLOBAL Vec<uint16_t, VX>*)(gstore_ptr<uint16_t>(a.out[s]) + idx) = w;
             return;
@@ -362,10 +401,13 @@ __device__ __forceinline__ float lap19(const Nb19& n, float k6) {
 __device__ __forceinline__ float lap7s(const Nb& n, float kx, float ky, float kz, float kc) {
     return __fmaf_rn(-kc, n.c, __fmaf_rn(kx, n.xm + n.xp, __fmaf_rn(ky, n.ym + n.yp, kz * (n.zm + n.zp))));
 }
-__device__ __forceinline__ float lapf(const Nb& n, const StepArgs& a, int f) {
+// (P: the step arguments, or any copy of their coefficients kx, ky, kz, kc)
+template <class P>
+__device__ __forceinline__ float lapf(const Nb& n, const P& a, int f) {
     return lap7s(n, a.kx[f], a.ky[f], a.kz[f], a.kc[f]);
 }
-__device__ __forceinline__ float lapf(const Nb19& n, const StepArgs& a, int f) { return lap19(n, a.kx[f]); }
+template <class P>
+__device__ __forceinline__ float lapf(const Nb19& n, const P& a, int f) { return lap19(n, a.kx[f]); }
 
 // The Laplacian of a neighbourhood: 7-point (per-axis K/h^2) or 19-point
 // (all three coefficients hold K/(6h^2)).
@@ -425,8 +467,10 @@ struct ChemPotential {
     static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return true; }
-    // mu of a cell from C there and Lap(C) there (every kernel forms it so)
-    static __device__ __forceinline__ float mu(const StepArgs& a, float c, float lc) {
+    // mu of a cell from C there and Lap(C) there (every kernel forms it so;
+    // P: the step arguments or a copy of their parameters p)
+    template <class P>
+    static __device__ __forceinline__ float mu(const P& a, float c, float lc) {
         return __fmaf_rn(-a.p[2], lc, __fmaf_rn(a.p[4] * c, c * c, -(a.p[3] * c)));
     }
     template <class NB>
@@ -446,8 +490,10 @@ struct FrontCH {
     static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int f) { return f == 3; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    // the update from the cell's values and Laplacians; q = k2 A C
-    static __device__ __forceinline__ void rates(const StepArgs& a, float A, float B, float C, float la, float lb,
+    // the update from the cell's values and Laplacians; q = k2 A C (P: the
+    // step arguments or a copy of their parameters p and dt)
+    template <class P>
+    static __device__ __forceinline__ void rates(const P& a, float A, float B, float C, float la, float lb,
                                                  float lc, float lmu, float q, float (&o)[3]) {
         const float r = (a.p[0] * A) * B;
         o[0] = __fmaf_rn(a.dt, (la - r) - q, A);
@@ -546,8 +592,8 @@ template <int NS> struct Atmos {
 // The wind argument of a model's cell function on plane z.
 template <class M>
 __device__ __forceinline__ float plane_wind(const StepArgs& a, int z) {
-    if constexpr (M::WIND == WIND_PLANE) return gload_ptr<float>(a.wind_h)[z];
-    else if constexpr (M::WIND == WIND_CLOCK) return gload_ptr<StepClock>(a.clk_in)->uzh;
+    if constexpr (M::WIND == WIND_PLANE) return cload_ptr<float>(a.wind_h)[z];
+    else if constexpr (M::WIND == WIND_CLOCK) return cload_ptr<StepClock>(a.clk_in)->uzh;
     else return 0.f;
 }
 
@@ -557,7 +603,7 @@ __device__ __forceinline__ float plane_wind(const StepArgs& a, int z) {
 template <class M>
 __device__ __forceinline__ void tick_clock(const StepArgs& a, bool first_thread) {
     if (first_thread && a.clk_pass && (M::WIND == WIND_CLOCK || a.sr)) {
-        const long long n = gload_ptr<StepClock>(a.clk_in)->n + 1;
+        const long long n = cload_ptr<StepClock>(a.clk_in)->n + 1;
         double u = 0.0;
         if constexpr (M::WIND == WIND_CLOCK) {
             const double t = a.t0 + double(n) * a.dt64;
@@ -659,9 +705,9 @@ __device__ __forceinline__ Emission<NO> cell_sources(const StepArgs& a, int x, i
     for (int s = 0; s < NO; ++s) r.e[s] = 0.f;
     r.any = false;
     for (int q = s0; q < s1; ++q) {
-        if (gload_ptr<int>(a.src_x)[q] == x) {
-            const int sp = gload_ptr<int>(a.src_sp)[q];
-            const float rate = gload_ptr<float>(a.src_rate)[q];
+        if (cload_ptr<int>(a.src_x)[q] == x) {
+            const int sp = cload_ptr<int>(a.src_sp)[q];
+            const float rate = cload_ptr<float>(a.src_rate)[q];
 #pragma unroll
             for (int s = 0; s < NO; ++s) r.e[s] = sp - a.sp0 == s ? rate : r.e[s];
             r.any = true;
@@ -705,7 +751,7 @@ __global__ __launch_bounds__(256) void direct_kernel(const StepArgs* __restrict_
     Emission<M::NO> em{};
     if (M::SOURCES) {
         const int r = z * a.ny + y;
-        em = cell_sources<M::NO>(a, x, gload_ptr<int>(a.src_row)[r], gload_ptr<int>(a.src_row)[r + 1]);
+        em = cell_sources<M::NO>(a, x, cload_ptr<int>(a.src_row)[r], cload_ptr<int>(a.src_row)[r + 1]);
     }
     const float uh = plane_wind<M>(a, z);
     float o[M::NO];
@@ -953,8 +999,8 @@ __device__ __forceinline__ void plane_cells(const StepArgs& a, BlockLds<M, W, 64
         }
         int s0 = 0, s1 = 0;
         if (M::SOURCES && y < a.ny) {
-            s0 = gload_ptr<int>(a.src_row)[z * a.ny + y];
-            s1 = gload_ptr<int>(a.src_row)[z * a.ny + y + 1];
+            s0 = cload_ptr<int>(a.src_row)[z * a.ny + y];
+            s1 = cload_ptr<int>(a.src_row)[z * a.ny + y + 1];
         }
         float o[NO][VX];
 #pragma unroll
@@ -1681,8 +1727,8 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
                 const float uh = plane_wind<M>(a, z);
                 bool plane_src = false;
                 if (M::SOURCES) {
-                    const int pa0 = gload_ptr<int>(a.src_row)[z * a.ny];
-                    const int pa1 = gload_ptr<int>(a.src_row)[(z + 1) * a.ny];
+                    const int pa0 = cload_ptr<int>(a.src_row)[z * a.ny];
+                    const int pa1 = cload_ptr<int>(a.src_row)[(z + 1) * a.ny];
                     plane_src = pa0 < pa1;
                 }
                 ring_barrier();
@@ -1753,8 +1799,8 @@ __device__ __forceinline__ void lds_consumer(const StepArgs& a, const RD_LDS flo
                     }
                     int s0 = 0, s1 = 0;
                     if (M::SOURCES && plane_src && y < a.ny) {
-                        s0 = gload_ptr<int>(a.src_row)[z * a.ny + y];
-                        s1 = gload_ptr<int>(a.src_row)[z * a.ny + y + 1];
+                        s0 = cload_ptr<int>(a.src_row)[z * a.ny + y];
+                        s1 = cload_ptr<int>(a.src_row)[z * a.ny + y + 1];
                     }
 #pragma unroll
                     for (int c = 0; c < NCH; ++c) {
@@ -2155,17 +2201,24 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds2_kernel(const StepArgs* __r
 struct BatchEntry {
     StepArgs args[2];     // by input parity
     int model;            // 0 diffusion (1 species), 1 Brusselator
+    int shape;            // slab shape: 0 the narrow rows (VX0 cells per lane), 1 the wide (VX1)
     int ntiles;
     int first_item;
     int parity;           // parity of the current state at tick start
     long long steps_left; // at tick start
 };
 
-template <class S, int VX, int RY, int W, int CZ>
+template <class S, int VX0, int VX1, int RY, int W, int CZ>
 __global__ __launch_bounds__(64 * W) void batched_kernel(const int* __restrict__ meta,
                                                           const BatchEntry* __restrict__ ents, int step) {
-    __shared__ BlockLds<Brusselator, W, 64 * VX> smb;
-    __shared__ BlockLds<Diffusion<1>, W, 64 * VX> smd;
+    // one LDS buffer serves every (model, shape): a workgroup steps one item
+    // at a time and synchronises between items
+    constexpr size_t NB = sizeof(BlockLds<Brusselator, W, 64 * VX1>) > sizeof(BlockLds<Brusselator, W, 64 * VX0>)
+                              ? sizeof(BlockLds<Brusselator, W, 64 * VX1>)
+                              : sizeof(BlockLds<Brusselator, W, 64 * VX0>);
+    static_assert(sizeof(BlockLds<Diffusion<1>, W, 64 * VX1>) <= NB &&
+                      sizeof(BlockLds<Diffusion<1>, W, 64 * VX0>) <= NB, "batch LDS");
+    __shared__ __attribute__((aligned(16))) float sm_raw[NB / sizeof(float)];
     const int ng = meta[0];
     const int total = meta[1];
     const int* first = meta + 2;
@@ -2185,8 +2238,21 @@ __global__ __launch_bounds__(64 * W) void batched_kernel(const int* __restrict__
         if (step >= en.steps_left) continue;     // this grid already finished
         const StepArgs& a = en.args[(en.parity + step) & 1];
         const int t = item - first[g];
-        if (en.model == 1) block_step<Brusselator, S, VX, RY, W, CZ>(a, t, smb);
-        else block_step<Diffusion<1>, S, VX, RY, W, CZ>(a, t, smd);
+        if (en.shape == 0) {
+            if (en.model == 1)
+                block_step<Brusselator, S, VX0, RY, W, CZ>(
+                    a, t, *reinterpret_cast<BlockLds<Brusselator, W, 64 * VX0>*>(sm_raw));
+            else
+                block_step<Diffusion<1>, S, VX0, RY, W, CZ>(
+                    a, t, *reinterpret_cast<BlockLds<Diffusion<1>, W, 64 * VX0>*>(sm_raw));
+        } else {
+            if (en.model == 1)
+                block_step<Brusselator, S, VX1, RY, W, CZ>(
+                    a, t, *reinterpret_cast<BlockLds<Brusselator, W, 64 * VX1>*>(sm_raw));
+            else
+                block_step<Diffusion<1>, S, VX1, RY, W, CZ>(
+                    a, t, *reinterpret_cast<BlockLds<Diffusion<1>, W, 64 * VX1>*>(sm_raw));
+        }
     }
 }
 

@@ -141,23 +141,27 @@ int lds2_cfg_index(int nch, int by, int wc, int d) {
 
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h, const StepArgs* d,
                        long long blocks, hipStream_t s) {
-    const bool diff = pm <= PM_DIFF4;
-    const bool react = pm == PM_BRUSS || pm == PM_CHMU || pm == PM_FRONT || pm == PM_TURING;
+    // the model groups, one translation unit each per storage type
+    const int grp = pm <= PM_DIFF4                       ? 0
+                    : pm == PM_BRUSS || pm == PM_TURING  ? 1
+                    : pm == PM_CHMU || pm == PM_FRONT    ? 2
+                    : pm == PM_ATMOS1 || pm == PM_ATMOS2 ? 4
+                                                         : 3;
+#define RD_GROUPS(st)                                                        \
+    switch (grp) {                                                           \
+    case 0: return launch_pass_##st##_diff(pm, kernel, cfg, h, d, blocks, s);  \
+    case 1: return launch_pass_##st##_react(pm, kernel, cfg, h, d, blocks, s); \
+    case 2: return launch_pass_##st##_front(pm, kernel, cfg, h, d, blocks, s); \
+    case 4: return launch_pass_##st##_atmos(pm, kernel, cfg, h, d, blocks, s); \
+    default: return launch_pass_##st##_poll(pm, kernel, cfg, h, d, blocks, s); \
+    }
     switch (storage) {
-    case ST_F32:
-        return diff ? launch_pass_f32_diff(pm, kernel, cfg, h, d, blocks, s)
-             : react ? launch_pass_f32_react(pm, kernel, cfg, h, d, blocks, s)
-                     : launch_pass_f32_poll(pm, kernel, cfg, h, d, blocks, s);
-    case ST_BF16:
-        return diff ? launch_pass_bf16_diff(pm, kernel, cfg, h, d, blocks, s)
-             : react ? launch_pass_bf16_react(pm, kernel, cfg, h, d, blocks, s)
-                     : launch_pass_bf16_poll(pm, kernel, cfg, h, d, blocks, s);
-    case ST_F16:
-        return diff ? launch_pass_f16_diff(pm, kernel, cfg, h, d, blocks, s)
-             : react ? launch_pass_f16_react(pm, kernel, cfg, h, d, blocks, s)
-                     : launch_pass_f16_poll(pm, kernel, cfg, h, d, blocks, s);
+    case ST_F32: RD_GROUPS(f32)
+    case ST_BF16: RD_GROUPS(bf16)
+    case ST_F16: RD_GROUPS(f16)
     default: return hipErrorInvalidValue;
     }
+#undef RD_GROUPS
 }
 
 hipError_t launch_batched(int storage, const int* meta, const BatchEntry* ents, int step, int blocks,
@@ -1657,16 +1661,19 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     BatchEntry* ents = reinterpret_cast<BatchEntry*>(b->h_tab + moff);
     std::memset(b->h_tab, 0, table_bytes(b->max_grids, ng));
     long long items = 0;
-    rd_plan tile{};
-    tile.kernel = RD_KERNEL_BLOCK;
-    tile.vx = kBatchBlock.vx;
-    tile.ry = kBatchBlock.ry;
-    tile.waves = kBatchBlock.w;
-    tile.cz = kBatchBlock.cz;
     int64_t max_steps = 0;
     for (int i = 0; i < ng; ++i) {
         const Member& m = b->members[i];
         BatchEntry& e = ents[i];
+        // the narrow slab shape when its rows cover the grid's
+        e.shape = m.g->nx <= 64 * kBatchBlocks[0].vx ? 0 : 1;
+        const BlockCfg& bc = kBatchBlocks[e.shape];
+        rd_plan tile{};
+        tile.kernel = RD_KERNEL_BLOCK;
+        tile.vx = bc.vx;
+        tile.ry = bc.ry;
+        tile.waves = bc.w;
+        tile.cz = bc.cz;
         for (int par = 0; par < 2; ++par) {
             e.args[par] = m.g->args[par][0];
             e.ntiles = int(set_tiling(e.args[par], tile));

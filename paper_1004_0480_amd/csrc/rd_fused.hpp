@@ -118,50 +118,108 @@ __device__ __forceinline__ void fch_producer(const StepArgs& a, RD_LDS float* ri
 #pragma unroll
     for (int j = 0; j < F::RC; ++j)
         rc[j] = resolve_axis(yb - 2 + j, a.ny, a.bck[2][2], a.bck[2][3], a.bcv[2][2], a.bcv[2][3]).idx;
+    // byte offset, within a plane, of this lane's 16-byte unit of every ring
+    // row (the rows are the same on every plane)
+    unsigned oc[F::RC], oab[2][F::RA];
+#pragma unroll
+    for (int j = 0; j < F::RC; ++j) oc[j] = unsigned(((long long)rc[j] * a.pitch + col[2]) * F::ES);
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int j = 0; j < F::RA; ++j) oab[f][j] = unsigned(((long long)rab[f][j] * a.pitch + col[f]) * F::ES);
+    const long long pbytes = a.plane * F::ES;
     const int last_c = z1 + 3 - z0, first_ab = 3, last_ab = z1 + 4 - z0;   // steps that load
     auto count = [&](int k) __attribute__((always_inline)) {
         return (k >= 0 && k <= last_c ? F::RC : 0) + (k >= first_ab && k <= last_ab ? 2 * F::RA : 0);
     };
+    // plane z of field f (the z face rules apply outside the grid)
+    auto plane_of = [&](int f, int p) __attribute__((always_inline)) {
+        const int pz = unsigned(p) < unsigned(a.nz)
+                           ? p
+                           : resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]).idx;
+        return (const RD_GLOBAL char*)a.in[f] + pz * pbytes;
+    };
+    // steps are issued in order, so their slots advance by one each
+    int slot_c = 0, slot_ab = 0;
     auto issue = [&](int k) __attribute__((always_inline)) {
         if (k <= last_c) {
-            const int p = z0 - 2 + k;
-            RD_LDS T* sl = (RD_LDS T*)(ring_c + (k % DC) * F::SLOTC_W);
-            const int pz = resolve_axis(p, a.nz, a.bck[2][4], a.bck[2][5], a.bcv[2][4], a.bcv[2][5]).idx;
-            const RD_GLOBAL T* base = gload_ptr<T>(a.in[2]) + (long long)pz * a.plane + col[2];
+            RD_LDS T* sl = (RD_LDS T*)(ring_c + slot_c * F::SLOTC_W);
+            const RD_GLOBAL char* base = plane_of(2, z0 - 2 + k);
 #pragma unroll
             for (int j = 0; j < F::RC; ++j)
                 if (act[2])
-                    __builtin_amdgcn_global_load_lds(base + (long long)rc[j] * a.pitch, (RD_LDS void*)(sl + j * F::RW),
-                                                     16, 0, 0);
+                    __builtin_amdgcn_global_load_lds((const RD_GLOBAL void*)(base + oc[j]),
+                                                     (RD_LDS void*)(sl + j * F::RW), 16, 0, 0);
         }
+        slot_c = slot_c + 1 == DC ? 0 : slot_c + 1;
         if (k >= first_ab && k <= last_ab) {
-            const int p = z0 - 4 + k;
-            RD_LDS T* sl = (RD_LDS T*)(ring_ab + ((k - 3) % F::DAB) * F::SLOTAB_W);
+            RD_LDS T* sl = (RD_LDS T*)(ring_ab + slot_ab * F::SLOTAB_W);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
-                const int pz = resolve_axis(p, a.nz, a.bck[f][4], a.bck[f][5], a.bcv[f][4], a.bcv[f][5]).idx;
-                const RD_GLOBAL T* base = gload_ptr<T>(a.in[f]) + (long long)pz * a.plane + col[f];
+                const RD_GLOBAL char* base = plane_of(f, z0 - 4 + k);
 #pragma unroll
                 for (int j = 0; j < F::RA; ++j)
                     if (act[f])
-                        __builtin_amdgcn_global_load_lds(base + (long long)rab[f][j] * a.pitch,
+                        __builtin_amdgcn_global_load_lds((const RD_GLOBAL void*)(base + oab[f][j]),
                                                          (RD_LDS void*)(sl + (f * F::RA + j) * F::RW), 16, 0, 0);
             }
+            slot_ab = slot_ab + 1 == F::DAB ? 0 : slot_ab + 1;
         }
     };
     for (int k = 0; k < DC - 2; ++k) issue(k);
+    // in the steady state every step loads C and A/B
+    constexpr int STEADY = (DC - 5) * (F::RC + 2 * F::RA) < 63 ? (DC - 5) * (F::RC + 2 * F::RA) : 63;
     for (int q = z0 - 3; q < z1; ++q) {
         // step q+5-z0 complete: the steps issued after it may stay in flight
         const int need = q + 5 - z0;
-        int after = 0;
+        if (need + 1 >= first_ab && need + DC - 5 <= last_c) {
+            vm_wait_imm<STEADY>();
+        } else {
+            int after = 0;
 #pragma unroll
-        for (int j = 1; j <= DC - 5; ++j) after += count(need + j);
-        vm_wait_count<0, 63>(min(after, 63));
+            for (int j = 1; j <= DC - 5; ++j) after += count(need + j);
+            vm_wait_count<0, 63>(min(after, 63));
+        }
         ring_barrier();
         issue(q + DC + 1 - z0);
     }
 #endif
 }
+
+// A per-lane copy of a uniform value: the copy lives in a VGPR for the whole
+// z march, so the plane loops issue no scalar reloads of the launch's
+// constants (scalar loads share the LDS reads' wait counter, so each reload
+// would also stall on every LDS read in flight) and the SGPRs stay free for
+// the loop's own scalars.
+__device__ __forceinline__ float vcopy(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+#else
+    return x;
+#endif
+}
+
+// The front model's coefficients, copied once per wave (same names as in the
+// step arguments, so the shared cell arithmetic takes either).
+struct FchConst {
+    float kx[4], ky[4], kz[4], kc[4];
+    float p[6];
+    float dt;
+    __device__ __forceinline__ explicit FchConst(const StepArgs& a) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            kx[f] = vcopy(a.kx[f]);
+            ky[f] = vcopy(a.ky[f]);
+            kz[f] = vcopy(a.kz[f]);
+            kc[f] = vcopy(a.kc[f]);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) p[i] = vcopy(a.p[i]);
+        dt = vcopy(a.dt);
+    }
+};
 
 // The computing waves, in two roles: WU waves update A, B and C on BY/WU rows
 // each, WM waves compute the chemical potential (its rows dealt round-robin;
@@ -182,19 +240,20 @@ struct FchConsumer {
     typedef float v2f __attribute__((ext_vector_type(2)));
 
     const StepArgs& a;
+    const FchConst k;
     const RD_LDS T* ring_c;
     const RD_LDS T* ring_ab;
     RD_LDS float* mring;
     int lane, x0, yb, xl;
     __device__ __forceinline__ FchConsumer(const StepArgs& a_, const RD_LDS float* ring_c_w,
                                            const RD_LDS float* ring_ab_w, RD_LDS float* mring_, int x0_, int yb_)
-        : a(a_), ring_c((const RD_LDS T*)ring_c_w), ring_ab((const RD_LDS T*)ring_ab_w), mring(mring_),
+        : a(a_), k(a_), ring_c((const RD_LDS T*)ring_c_w), ring_ab((const RD_LDS T*)ring_ab_w), mring(mring_),
           lane(threadIdx.x & 63), x0(x0_), yb(yb_), xl(x0_ + 2 * (threadIdx.x & 63)) {}
     // mu from C and Lap(C), and the rates of the front model
-    __device__ __forceinline__ float mu_of(float c, float lc) const { return ChemPotential::mu(a, c, lc); }
+    __device__ __forceinline__ float mu_of(float c, float lc) const { return ChemPotential::mu(k, c, lc); }
     __device__ __forceinline__ void rates(float A, float B, float C, float la, float lb, float lc, float lmu,
                                           float q, float (&o)[3]) const {
-        FrontCH::rates(a, A, B, C, la, lb, lc, lmu, q, o);
+        FrontCH::rates(k, A, B, C, la, lb, lc, lmu, q, o);
     }
 
     // C slot s, A/B slot s, and the slot base of field f (C slot sc or A/B slot sab)
@@ -264,112 +323,162 @@ struct FchConsumer {
 
     // ---- chemical potential ------------------------------------------------
 
-    // mu of plane p on mu row m, from C planes p-1 (P1), p (P2), p+1 (P3)
-    template <bool FIX>
-    __device__ __forceinline__ void mu_row(int p, int m, const RD_LDS T* P1, const RD_LDS T* P2,
-                                           const RD_LDS T* P3) const {
-        const int gm = yb - 1 + m;
-        const int j = m + 1;                       // C ring row of grid row gm
+    // C around this lane's two cells of mu row m: the five points of the
+    // Laplacian from C planes p-1 (P1), p (P2), p+1 (P3), and the row's x
+    // halo cells
+    struct MuIn {
+        float c[2], cym[2], cyp[2], czm[2], czp[2], hl, hr;
+    };
+    __device__ __forceinline__ void mu_read(int m, const RD_LDS T* P1, const RD_LDS T* P2, const RD_LDS T* P3,
+                                            MuIn& in) const {
+        const int j = m + 1;                       // C ring row of grid row yb - 1 + m
         const RD_LDS T* rc = row(P2, 2, j);
-        float c[2], cym[2], cyp[2], czm[2], czp[2];
-        rd2(rc, c);
-        rd2(row(P2, 2, j - 1), cym);
-        rd2(row(P2, 2, j + 1), cyp);
-        rd2(row(P1, 2, j), czm);
-        rd2(row(P3, 2, j), czp);
-        float hl = rd1(rc, hl_off()), hr = rd1(rc, HX + TX);
+        rd2(rc, in.c);
+        rd2(row(P2, 2, j - 1), in.cym);
+        rd2(row(P2, 2, j + 1), in.cyp);
+        rd2(row(P1, 2, j), in.czm);
+        rd2(row(P3, 2, j), in.czp);
+        in.hl = rd1(rc, hl_off());
+        in.hr = rd1(rc, HX + TX);
+    }
+    // mu of plane p, row m, at this lane's two cells
+    template <bool FIX>
+    __device__ __forceinline__ v2f mu_cells(int p, int m, MuIn in) const {
         if constexpr (FIX) {
+            const int gm = yb - 1 + m;
             const Src y0 = ysrc(2, gm), ym = ysrc(2, gm - 1), yp = ysrc(2, gm + 1);
             const Src pm = zsrc(2, p - 1), p0 = zsrc(2, p), pp = zsrc(2, p + 1);
-            fix_row<2>(a, 2, p0, y0, xl, c);
-            fix_row<2>(a, 2, p0, ym, xl, cym);
-            fix_row<2>(a, 2, p0, yp, xl, cyp);
-            fix_row<2>(a, 2, pm, y0, xl, czm);
-            fix_row<2>(a, 2, pp, y0, xl, czp);
-            fix1(a, 2, p0, y0, x0 == 0 ? a.nx - 1 : x0 - 1, hl);
-            fix1(a, 2, p0, y0, x0 + TX, hr);
+            fix_row<2>(a, 2, p0, y0, xl, in.c);
+            fix_row<2>(a, 2, p0, ym, xl, in.cym);
+            fix_row<2>(a, 2, p0, yp, xl, in.cyp);
+            fix_row<2>(a, 2, pm, y0, xl, in.czm);
+            fix_row<2>(a, 2, pp, y0, xl, in.czp);
+            fix1(a, 2, p0, y0, x0 == 0 ? a.nx - 1 : x0 - 1, in.hl);
+            fix1(a, 2, p0, y0, x0 + TX, in.hr);
         }
         float xm[2], xp[2];
-        xnb(2, c, hl, hr, xm, xp);
+        xnb(2, in.c, in.hl, in.hr, xm, xp);
         v2f mu;
-        const Nb n0{c[0], xm[0], xp[0], cym[0], cyp[0], czm[0], czp[0]};
-        const Nb n1{c[1], xm[1], xp[1], cym[1], cyp[1], czm[1], czp[1]};
-        mu.x = mu_of(c[0], lapf(n0, a, 3));
-        mu.y = mu_of(c[1], lapf(n1, a, 3));
-        *(RD_LDS v2f*)(mrow(p, m) + 2 + 2 * lane) = mu;
+        const Nb n0{in.c[0], xm[0], xp[0], in.cym[0], in.cyp[0], in.czm[0], in.czp[0]};
+        const Nb n1{in.c[1], xm[1], xp[1], in.cym[1], in.cyp[1], in.czm[1], in.czp[1]};
+        mu.x = mu_of(in.c[0], lapf(n0, k, 3));
+        mu.y = mu_of(in.c[1], lapf(n1, k, 3));
+        return mu;
     }
 
-    // mu at the columns x0-1 and x0+TX of every mu row of plane p: lane 2m + s
-    // takes mu row m, side s (0: x0-1, 1: x0+TX)
+    // mu at the columns x0-1 and x0+TX of every mu row: lane 2m + s takes mu
+    // row m, side s (0: x0-1, 1: x0+TX).  Where this lane's cell lies, fixed
+    // for the whole march:
+    struct ColAt {
+        int m, j, eo, xe;
+        bool want;      // the cell exists and this tile needs it
+        bool rface;     // x0+TX = nx-1: its right neighbour is the face rule
+    };
+    __device__ __forceinline__ ColAt col_at() const {
+        ColAt c;
+        c.m = lane >> 1;
+        const int side = lane & 1;
+        const int gm = yb - 1 + c.m;
+        c.want = c.m < F::MROWS && gm >= 0 && gm < a.ny && (side ? x0 + TX < a.nx : x0 > 0);
+        c.j = c.want ? c.m + 1 : 1;
+        c.eo = side ? HX + TX : HX - 1;
+        c.xe = side ? x0 + TX : x0 - 1;
+        // (a tile of one cell follows this one, so this tile has no x face
+        // itself; a periodic x axis is refused for such widths)
+        c.rface = x0 + TX + 1 == a.nx && side;
+        return c;
+    }
+    struct ColIn {
+        float e, el, er, eym, eyp, ezm, ezp;
+    };
+    __device__ __forceinline__ void col_read(const ColAt& c, const RD_LDS T* P1, const RD_LDS T* P2,
+                                             const RD_LDS T* P3, ColIn& in) const {
+        const RD_LDS T* rc = row(P2, 2, c.j);
+        in.e = rd1(rc, c.eo);
+        in.el = rd1(rc, c.eo - 1);
+        in.er = rd1(rc, c.eo + 1);
+        in.eym = rd1(row(P2, 2, c.j - 1), c.eo);
+        in.eyp = rd1(row(P2, 2, c.j + 1), c.eo);
+        in.ezm = rd1(row(P1, 2, c.j), c.eo);
+        in.ezp = rd1(row(P3, 2, c.j), c.eo);
+    }
     template <bool FIX>
-    __device__ __forceinline__ void mu_columns(int p, const RD_LDS T* P1, const RD_LDS T* P2,
-                                               const RD_LDS T* P3) const {
-        const int m = lane >> 1, side = lane & 1;
-        const int gm = yb - 1 + m;
-        const bool want = m < F::MROWS && gm >= 0 && gm < a.ny && (side ? x0 + TX < a.nx : x0 > 0);
-        const int j = want ? m + 1 : 1;
-        const int eo = side ? HX + TX : HX - 1;
-        const int xe = side ? x0 + TX : x0 - 1;
-        const RD_LDS T* rc = row(P2, 2, j);
-        float e = rd1(rc, eo), el = rd1(rc, eo - 1), er = rd1(rc, eo + 1);
-        float eym = rd1(row(P2, 2, j - 1), eo), eyp = rd1(row(P2, 2, j + 1), eo);
-        float ezm = rd1(row(P1, 2, j), eo), ezp = rd1(row(P3, 2, j), eo);
+    __device__ __forceinline__ float col_cell(int p, const ColAt& c, ColIn in, bool rmirror, float rval) const {
         if constexpr (FIX) {
+            const int gm = yb - 1 + c.m;
             const Src y0 = ysrc(2, gm), ym = ysrc(2, gm - 1), yp = ysrc(2, gm + 1);
             const Src pm = zsrc(2, p - 1), p0 = zsrc(2, p), pp = zsrc(2, p + 1);
-            fix1(a, 2, p0, y0, xe, e);
-            fix1(a, 2, p0, y0, xe - 1, el);
-            fix1(a, 2, p0, y0, xe + 1, er);
-            fix1(a, 2, p0, ym, xe, eym);
-            fix1(a, 2, p0, yp, xe, eyp);
-            fix1(a, 2, pm, y0, xe, ezm);
-            fix1(a, 2, pp, y0, xe, ezp);
+            fix1(a, 2, p0, y0, c.xe, in.e);
+            fix1(a, 2, p0, y0, c.xe - 1, in.el);
+            fix1(a, 2, p0, y0, c.xe + 1, in.er);
+            fix1(a, 2, p0, ym, c.xe, in.eym);
+            fix1(a, 2, p0, yp, c.xe, in.eyp);
+            fix1(a, 2, pm, y0, c.xe, in.ezm);
+            fix1(a, 2, pp, y0, c.xe, in.ezp);
         }
-        // x0+TX = nx-1 (a tile of one cell follows, so this tile has no x
-        // face itself): its right neighbour is the face rule (a periodic x
-        // axis is refused for such widths)
-        if (x0 + TX + 1 == a.nx && side) er = a.bck[2][1] == BC_MIRROR ? e : a.bcv[2][1];
-        const Nb ne{e, el, er, eym, eyp, ezm, ezp};
-        const float mue = mu_of(e, lapf(ne, a, 3));
-        if (want) mrow(p, m)[side ? TX + 2 : 1] = mue;
+        if (c.rface) in.er = rmirror ? in.e : rval;
+        const Nb ne{in.e, in.el, in.er, in.eym, in.eyp, in.ezm, in.ezp};
+        return mu_of(in.e, lapf(ne, k, 3));
     }
 
     // one mu wave (index mw) over the z range: mu planes z0-1 .. z1
     __device__ __forceinline__ void run_mu(int mw, int z0, int z1) const {
         bool wfix = (a.held[2] & 3) != 0;
+        // this wave's mu rows (clamped into the ring) and whether each lies in
+        // the grid -- the same on every plane
+        int mrows[MPW];
+        bool rowok[MPW];
 #pragma unroll
-        for (int k = 0; k < MPW; ++k)
+        for (int i = 0; i < MPW; ++i) {
+            const int m = mw + i * WM, gm = yb - 1 + m;
+            mrows[i] = min(m, F::MROWS - 1);
+            rowok[i] = m < F::MROWS && gm >= 0 && gm < a.ny;
 #pragma unroll
-            for (int t = -1; t <= 1; ++t) wfix = wfix || ysrc(2, yb - 1 + mw + k * WM + t).cst != CST_NONE;
+            for (int t = -1; t <= 1; ++t) wfix = wfix || ysrc(2, gm + t).cst != CST_NONE;
+        }
         const bool columns = mw == WM - 1;
         if (columns)
             for (int m = 0; m < F::MROWS; ++m)
 #pragma unroll
                 for (int t = -1; t <= 1; ++t) wfix = wfix || ysrc(2, yb - 1 + m + t).cst != CST_NONE;
+        const ColAt cat = col_at();
+        const bool rmirror = a.bck[2][1] == BC_MIRROR;
+        const float rval = a.bcv[2][1];
+        // mu plane p = q + 2 exists for 0 <= p <= min(nz - 1, z1); C planes
+        // p-1 .. p+1 take no z rule unless p <= 1 or p >= nz - 2
+        const int q_last = min(a.nz - 1, z1) - 2, p_hi = a.nz - 2;
         int sq = DC - 1;                  // C slot of plane q (plane z0-2 is slot 0)
         for (int q = z0 - 3; q < z1; ++q) {
             lds_done();
             ring_barrier();
             const int s1 = sq + 1 == DC ? 0 : sq + 1, s2 = s1 + 1 == DC ? 0 : s1 + 1, s3 = s2 + 1 == DC ? 0 : s2 + 1;
             const int p = q + 2;
-            if (p >= 0 && p < a.nz && p <= z1) {
+            if (q >= -2 && q <= q_last) {
                 const RD_LDS T* P1 = cslot(s1);
                 const RD_LDS T* P2 = cslot(s2);
                 const RD_LDS T* P3 = cslot(s3);
-                const bool fx = wfix || near(p - 1) || near(p + 1);
+                // every LDS read first, then the arithmetic
+                MuIn in[MPW];
+                ColIn cin;
 #pragma unroll
-                for (int k = 0; k < MPW; ++k) {
-                    const int m = mw + k * WM;
-                    const int gm = yb - 1 + m;
-                    if (m < F::MROWS && gm >= 0 && gm < a.ny) {
-                        if (fx) mu_row<true>(p, m, P1, P2, P3);
-                        else mu_row<false>(p, m, P1, P2, P3);
-                    }
+                for (int i = 0; i < MPW; ++i) mu_read(mrows[i], P1, P2, P3, in[i]);
+                if (columns) col_read(cat, P1, P2, P3, cin);
+                __builtin_amdgcn_sched_barrier(0);
+                v2f mu[MPW];
+                float mue = 0.f;
+                if (wfix || p <= 1 || p >= p_hi) {
+#pragma unroll
+                    for (int i = 0; i < MPW; ++i) mu[i] = mu_cells<true>(p, mrows[i], in[i]);
+                    if (columns) mue = col_cell<true>(p, cat, cin, rmirror, rval);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < MPW; ++i) mu[i] = mu_cells<false>(p, mrows[i], in[i]);
+                    if (columns) mue = col_cell<false>(p, cat, cin, rmirror, rval);
                 }
-                if (columns) {
-                    if (fx) mu_columns<true>(p, P1, P2, P3);
-                    else mu_columns<false>(p, P1, P2, P3);
-                }
+#pragma unroll
+                for (int i = 0; i < MPW; ++i)
+                    if (rowok[i]) *(RD_LDS v2f*)(mrow(p, mrows[i]) + 2 + 2 * lane) = mu[i];
+                if (columns && cat.want) mrow(p, cat.m)[(lane & 1) ? TX + 2 : 1] = mue;
             }
             sq = s1;
         }
@@ -398,86 +507,99 @@ struct FchConsumer {
     template <bool FIX, bool CD, bool PLAIN>
     __device__ __forceinline__ void update(int r0, int z, const RD_LDS T* PC, const RD_LDS T* PAB,
                                            const float (&cm)[3][RY][2], const float (&c0)[3][RY][2],
-                                           const float (&cp)[3][RY][2]) const {
+                                           const float (&cp)[3][RY][2], RD_GLOBAL T* const (&po)[3][RY],
+                                           const bool (&rowst)[RY]) const {
+        constexpr int NF = CD ? 3 : 2;               // fields with a Laplacian of their own
         const int hlo = hl_off();
         const int zm = max(z - 1, 0), zp = min(z + 1, a.nz - 1);
+        // every LDS read of the plane is issued first, so that their
+        // latencies overlap and one wait covers them
+        float ym[NF][RY][2], yp[NF][RY][2], hl[NF][RY], hr[NF][RY];
+        float mc[RY][2], mym[RY][2], myp[RY][2], mzm[RY][2], mzp[RY][2], ml[RY], mr[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int y = yb + r0 + r;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const int j = r0 + r + F::lead(f);
+                const RD_LDS T* P0 = f == 2 ? PC : PAB;
+                const RD_LDS T* rc = row(P0, f, j);
+                rd2(row(P0, f, j - 1), ym[f][r]);
+                rd2(row(P0, f, j + 1), yp[f][r]);
+                hl[f][r] = rd1(rc, hlo);
+                hr[f][r] = rd1(rc, HX + TX);
+            }
+            // mu: mirror ghosts on every face (rows and planes clamp)
+            const int mi = y - (yb - 1);
+            const RD_LDS float* m0 = mrow(z, mi);
+            mrd2(m0, mc[r]);
+            mrd2(mrow(z, max(y - 1, 0) - (yb - 1)), mym[r]);
+            mrd2(mrow(z, min(y + 1, a.ny - 1) - (yb - 1)), myp[r]);
+            mrd2(mrow(zm, mi), mzm[r]);
+            mrd2(mrow(zp, mi), mzp[r]);
+            ml[r] = m0[1];
+            mr[r] = m0[TX + 2];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int y = yb + r0 + r;
             float lf[3][2];
+            // no Laplacian of C: -0 is the exact identity of the addition it
+            // enters, so that addition is dropped
+            lf[2][0] = lf[2][1] = -0.f;
 #pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                if (f == 2 && !CD) {
-                    lf[2][0] = lf[2][1] = 0.f;
-                    continue;
-                }
-                const int j = r0 + r + F::lead(f);
-                const RD_LDS T* P0 = f == 2 ? PC : PAB;
-                const RD_LDS T* rc = row(P0, f, j);
-                float ym[2], yp[2];
-                rd2(row(P0, f, j - 1), ym);
-                rd2(row(P0, f, j + 1), yp);
-                float hl = rd1(rc, hlo), hr = rd1(rc, HX + TX);
+            for (int f = 0; f < NF; ++f) {
                 if constexpr (FIX) {
                     const Src pz = zsrc(f, z), y0 = ysrc(f, y);
-                    fix_row<2>(a, f, pz, ysrc(f, y - 1), xl, ym);
-                    fix_row<2>(a, f, pz, ysrc(f, y + 1), xl, yp);
-                    fix1(a, f, pz, y0, x0 == 0 ? a.nx - 1 : x0 - 1, hl);
-                    fix1(a, f, pz, y0, x0 + TX, hr);
+                    fix_row<2>(a, f, pz, ysrc(f, y - 1), xl, ym[f][r]);
+                    fix_row<2>(a, f, pz, ysrc(f, y + 1), xl, yp[f][r]);
+                    fix1(a, f, pz, y0, x0 == 0 ? a.nx - 1 : x0 - 1, hl[f][r]);
+                    fix1(a, f, pz, y0, x0 + TX, hr[f][r]);
                 }
                 float xm[2], xp[2];
-                xnb(f, c0[f][r], hl, hr, xm, xp);
+                xnb(f, c0[f][r], hl[f][r], hr[f][r], xm, xp);
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    const Nb n{c0[f][r][i], xm[i], xp[i], ym[i], yp[i], cm[f][r][i], cp[f][r][i]};
-                    lf[f][i] = lapf(n, a, f);
+                    const Nb n{c0[f][r][i], xm[i], xp[i], ym[f][r][i], yp[f][r][i], cm[f][r][i], cp[f][r][i]};
+                    lf[f][i] = lapf(n, k, f);
                 }
             }
             float lmu[2];
             {
-                // mu: mirror ghosts on every face (rows and planes clamp)
-                const int mi = y - (yb - 1);
-                const RD_LDS float* m0 = mrow(z, mi);
-                float mc[2], mym[2], myp[2], mzm[2], mzp[2];
-                mrd2(m0, mc);
-                mrd2(mrow(z, max(y - 1, 0) - (yb - 1)), mym);
-                mrd2(mrow(z, min(y + 1, a.ny - 1) - (yb - 1)), myp);
-                mrd2(mrow(zm, mi), mzm);
-                mrd2(mrow(zp, mi), mzp);
-                float ml = m0[1];
-                if constexpr (XF) ml = x0 == 0 ? mc[0] : ml;
+                float mlr = ml[r];
+                if constexpr (XF) mlr = x0 == 0 ? mc[r][0] : mlr;
                 float xm[2], xp[2];
-                xm[0] = lane_from_left(mc[1], ml);
-                xm[1] = mc[0];
-                xp[0] = mc[1];
-                xp[1] = lane_from_right(mc[0], m0[TX + 2]);
+                xm[0] = lane_from_left(mc[r][1], mlr);
+                xm[1] = mc[r][0];
+                xp[0] = mc[r][1];
+                xp[1] = lane_from_right(mc[r][0], mr[r]);
                 if constexpr (XF) {
                     if (x0 + TX >= a.nx) {
-                        if (xl == a.nx - 1) xp[0] = mc[0];
-                        if (xl + 1 == a.nx - 1) xp[1] = mc[1];
+                        if (xl == a.nx - 1) xp[0] = mc[r][0];
+                        if (xl + 1 == a.nx - 1) xp[1] = mc[r][1];
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    const Nb n{mc[i], xm[i], xp[i], mym[i], myp[i], mzm[i], mzp[i]};
-                    lmu[i] = lapf(n, a, 3);
+                    const Nb n{mc[r][i], xm[i], xp[i], mym[r][i], myp[r][i], mzm[r][i], mzp[r][i]};
+                    lmu[i] = lapf(n, k, 3);
                 }
             }
             float o[3][2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const float A = c0[0][r][i], B = c0[1][r][i], C = c0[2][r][i];
-                const float q = CD ? (a.p[5] * A) * C : 0.f;
+                const float q = CD ? (k.p[5] * A) * C : 0.f;
                 float oi[3];
                 rates(A, B, C, lf[0][i], lf[1][i], lf[2][i], lmu[i], q, oi);
 #pragma unroll
                 for (int s = 0; s < 3; ++s) o[s][i] = FIX ? held_out(a, s, xl + i, y, z, oi[s]) : oi[s];
             }
-            if (y < a.ny && (!XF || xl < a.nx)) {
+            if (rowst[r]) {
                 if constexpr (PLAIN) {
-                    const long long idx = (long long)z * a.plane + (long long)y * a.pitch + xl;
 #pragma unroll
-                    for (int s = 0; s < 3; ++s) store_vec<S, 2>(a.out[s], idx, o[s]);
+                    for (int s = 0; s < 3; ++s) store_vec_at<S, 2>(po[s][r], o[s]);
                 } else {
 #pragma unroll
                     for (int s = 0; s < 3; ++s) store_field<S, 2>(a, s, xl, y, z, o[s]);
@@ -504,6 +626,20 @@ struct FchConsumer {
             for (int f = 0; f < 3; ++f)
 #pragma unroll
                 for (int r = 0; r < RY; ++r) cen[t][f][r][0] = cen[t][f][r][1] = 0.f;
+        // output rows: their addresses on plane z0, advanced a plane per
+        // update, and whether this lane stores there
+        RD_GLOBAL T* po[3][RY];
+        bool rowst[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int y = yb + r0 + r;
+            rowst[r] = y < a.ny && (!XF || xl < a.nx);
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+                po[s][r] = gstore_ptr<T>(a.out[s]) + ((long long)z0 * a.plane + (long long)y * a.pitch + xl);
+        }
+        // planes q-1 .. q+1 take no z rule unless q <= 1 or q >= nz - 2
+        const int q_hi = a.nz - 2;
         int sc = DC - 1;                  // C slot of plane q (plane z0-2 is slot 0)
         int sab = DAB - 2;                // A/B slot of plane q (plane z0-1 is slot 0)
         for (int q = z0 - 3; q < z1; ++q) {
@@ -512,17 +648,21 @@ struct FchConsumer {
             const int sc1 = sc + 1 == DC ? 0 : sc + 1, sab1 = sab + 1 == DAB ? 0 : sab + 1;
             // centre rows of plane q+1
             if (q >= z0 - 2) {
-                if (wfix || near(q + 1)) centre<true>(r0, q + 1, cslot(sc1), abslot(sab1), cen[2]);
+                if (wfix || q <= -1 || q >= q_hi) centre<true>(r0, q + 1, cslot(sc1), abslot(sab1), cen[2]);
                 else centre<false>(r0, q + 1, cslot(sc1), abslot(sab1), cen[2]);
             }
             // update plane q
             if (q >= z0) {
                 const RD_LDS T* PC = cslot(sc);
                 const RD_LDS T* PAB = abslot(sab);
-                if (wfix || near(q - 1) || near(q + 1))
-                    update<true, CD, PLAIN>(r0, q, PC, PAB, cen[0], cen[1], cen[2]);
+                if (wfix || q <= 1 || q >= q_hi)
+                    update<true, CD, PLAIN>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst);
                 else
-                    update<false, CD, PLAIN>(r0, q, PC, PAB, cen[0], cen[1], cen[2]);
+                    update<false, CD, PLAIN>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst);
+#pragma unroll
+                for (int s = 0; s < 3; ++s)
+#pragma unroll
+                    for (int r = 0; r < RY; ++r) po[s][r] += a.plane;
             }
 #pragma unroll
             for (int f = 0; f < 3; ++f)

@@ -156,10 +156,12 @@ int block_cfg_index(int vx, int ry, int w, int cz);  // -1 if no such shape
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h,
                        const StepArgs* d, long long blocks, hipStream_t s);
 
-// Batched persistent kernel (slab shape kBatchBlock: 128-cell rows cover the
-// served grid edges of up to 128 cells in one tile): one step of every table
-// entry whose steps_left > step.
-constexpr BlockCfg kBatchBlock = {2, 2, 1, 2};
+// Batched persistent kernel: one step of every table entry whose steps_left >
+// step.  Two slab shapes of four waves, two rows per wave and four planes,
+// with 64- and 128-cell rows: each grid takes the narrower one that covers
+// its rows (one tile per row up to 128 cells), so small grids keep their
+// lanes busy.
+constexpr BlockCfg kBatchBlocks[2] = {{1, 2, 4, 4}, {2, 2, 4, 4}};
 hipError_t launch_batched(int storage, const int* meta, const BatchEntry* ents, int step, int blocks,
                           hipStream_t s);
 int batched_blocks_per_cu(int storage);
@@ -171,13 +173,19 @@ int batched_blocks_per_cu(int storage);
                                  const StepArgs* d, long long blocks, hipStream_t s);
 RD_DECLARE_GROUP(f32_diff)
 RD_DECLARE_GROUP(f32_react)
+RD_DECLARE_GROUP(f32_front)
 RD_DECLARE_GROUP(f32_poll)
+RD_DECLARE_GROUP(f32_atmos)
 RD_DECLARE_GROUP(bf16_diff)
 RD_DECLARE_GROUP(bf16_react)
+RD_DECLARE_GROUP(bf16_front)
 RD_DECLARE_GROUP(bf16_poll)
+RD_DECLARE_GROUP(bf16_atmos)
 RD_DECLARE_GROUP(f16_diff)
 RD_DECLARE_GROUP(f16_react)
+RD_DECLARE_GROUP(f16_front)
 RD_DECLARE_GROUP(f16_poll)
+RD_DECLARE_GROUP(f16_atmos)
 #undef RD_DECLARE_GROUP
 
 hipError_t launch_batched_f32(const int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);

@@ -2,7 +2,7 @@
 // and one group of models.  Included by rd_launch_<storage>_<group>.hip with
 //   RD_STORAGE      the storage struct (rdk::StF32, ...)
 //   RD_STORAGE_ID   its rdk::Storage value
-//   RD_GROUP_DIFF / RD_GROUP_REACT / RD_GROUP_POLL   which models to build
+//   RD_GROUP_DIFF / _REACT / _FRONT / _POLL / _ATMOS   which models to build
 //   RD_FN(name)     the group's function-name suffixing
 //   RD_WITH_BATCH   also build the batched kernel (once per storage)
 #pragma once
@@ -147,14 +147,18 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 #endif
 #ifdef RD_GROUP_REACT
     case PM_BRUSS: return run_model<Brusselator>(kernel, cfg, h, d, blocks, s);
+    case PM_TURING: return run_model<Turing>(kernel, cfg, h, d, blocks, s);
+#endif
+#ifdef RD_GROUP_FRONT
     case PM_CHMU: return run_model<ChemPotential>(kernel, cfg, h, d, blocks, s);
     case PM_FRONT: return run_model<FrontCH>(kernel, cfg, h, d, blocks, s);
-    case PM_TURING: return run_model<Turing>(kernel, cfg, h, d, blocks, s);
 #endif
 #ifdef RD_GROUP_POLL
     case PM_POLL1: return run_model<Pollutant<1, false>>(kernel, cfg, h, d, blocks, s);
     case PM_POLL2: return run_model<Pollutant<2, true>>(kernel, cfg, h, d, blocks, s);
     case PM_POLL2U: return run_model<Pollutant<2, false>>(kernel, cfg, h, d, blocks, s);
+#endif
+#ifdef RD_GROUP_ATMOS
     case PM_ATMOS1: return run_model<Atmos<1>>(kernel, cfg, h, d, blocks, s);
     case PM_ATMOS2: return run_model<Atmos<2>>(kernel, cfg, h, d, blocks, s);
 #endif
@@ -163,17 +167,22 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 }
 
 #ifdef RD_WITH_BATCH
-#define RD_BATCH_KERNEL batched_kernel<S, kBatchBlock.vx, kBatchBlock.ry, kBatchBlock.w, kBatchBlock.cz>
+static_assert(kBatchBlocks[0].ry == kBatchBlocks[1].ry && kBatchBlocks[0].w == kBatchBlocks[1].w &&
+                  kBatchBlocks[0].cz == kBatchBlocks[1].cz,
+              "the batch shapes differ in row length only");
+#define RD_BATCH_KERNEL                                                                          \
+    batched_kernel<S, kBatchBlocks[0].vx, kBatchBlocks[1].vx, kBatchBlocks[0].ry, kBatchBlocks[0].w, \
+                   kBatchBlocks[0].cz>
 hipError_t RD_BATCH_FN(launch_batched)(const int* meta, const BatchEntry* ents, int step, int blocks,
                                        hipStream_t s) {
-    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchBlock.w), 0, s, meta, ents, step);
+    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchBlocks[0].w), 0, s, meta, ents, step);
     return hipGetLastError();
 }
 
 int RD_BATCH_FN(batched_blocks_per_cu)() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&RD_BATCH_KERNEL),
-                                                     64 * kBatchBlock.w, 0) != hipSuccess)
+                                                     64 * kBatchBlocks[0].w, 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
