@@ -64,7 +64,7 @@ def kernel_source_digest() -> str:
 
 
 KERNEL_NAMES = {1: "direct_kernel", 2: "tiled_kernel", 3: "block_kernel", 4: "lds_kernel", 5: "lds2_kernel",
-                6: "fch_kernel"}
+                6: "fch_kernel", 7: "tr_kernel"}
 
 
 def measured_traffic(name: str, digest: str, kernel: int = 0):
@@ -156,7 +156,7 @@ def copy_ceiling(torch, stream, nbytes: int, reps: int = 10):
 # ------------------------------------------------ profile summaries (rocprofv3)
 
 STEP_KERNELS = ("rdk::block_kernel", "rdk::tiled_kernel", "rdk::direct_kernel", "rdk::lds_kernel",
-                "rdk::lds2_kernel", "rdk::fch_kernel")
+                "rdk::lds2_kernel", "rdk::fch_kernel", "rdk::tr_kernel")
 
 
 def _counter_rows(d: str):
@@ -243,6 +243,35 @@ def pmc_summary(args):
     print(json.dumps(rec))
 
 
+def counter_summary(args):
+    """profiles/<workload>_<kernel>_counters.md from one rocprofv3 --pmc run
+    of this script: every counter of the run per dispatch of the step
+    kernel(s), and per wave where the run counted waves (SQ_WAVES)."""
+    from paper_1004_0480_amd import workloads as W
+    rows = _counter_rows(args.counter_summary)
+    knames = _step_kernels(rows)
+    counters = sorted({r["Counter_Name"] for r in rows})
+    lines = ["# rocprofv3 counters: %s step kernel (MI355X)" % profile_name(args), "",
+             "Workload: %s, grid (z, y, x) = %s, %s storage, %d-point Laplacian; kernel sources %s."
+             % (args.workload, W.DEFAULT_SHAPES[args.workload], args.storage, args.stencil,
+                kernel_source_digest()),
+             "", "Command:", "", "```", args.counter_command, "```", ""]
+    for k in knames:
+        lines += ["Kernel `%s`:" % k[:160], "", "| counter | per dispatch | per wave | dispatches |", "|---|---|---|---|"]
+        waves, _ = _per_dispatch(rows, "SQ_WAVES", lambda n: n == k)
+        for c in counters:
+            v, n = _per_dispatch(rows, c, lambda n: n == k)
+            if v is None:
+                continue
+            lines.append("| %s | %.6g | %s | %d |" % (c, v, "%.4g" % (v / waves) if waves else "-", n))
+        lines.append("")
+    kind = next((v for v in KERNEL_NAMES.values() if v in knames[0]), "kernel")
+    out = os.path.join(PROFILES, "%s_%s_counters.md" % (profile_name(args), kind))
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def trace_summary(args):
     """profiles/<workload>_kernel_trace.md from a rocprofv3 --kernel-trace
     --stats run of this script: the per-kernel table and the step kernel's
@@ -263,21 +292,28 @@ def trace_summary(args):
              % (args.workload, W.DEFAULT_SHAPES[args.workload], args.storage, args.stencil),
              "", "Command:", "", "```", args.trace_command, "```", "",
              "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
-    step = None
+    steps = []
     for r in rows:
         name = r["Name"]
         avg = float(r["AverageNs"]) / 1e3
         lines.append("| `%s` | %s | %.2f | %.2f | %.2f | %.2f%% |" % (
             name[:100], r["Calls"], avg, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
             float(r["Percentage"])))
-        if step is None and any(k in name for k in STEP_KERNELS):
-            step = (name, avg)
+        if any(k in name for k in STEP_KERNELS):
+            steps.append((name, avg, int(r["Calls"])))
     lines.append("")
+    # the step's kernels: every step-kernel family with the largest call
+    # count (the passes of a multi-pass step), their averages summed
+    top = max((c for _, _, c in steps), default=0)
+    passes = [(n, t) for n, t, c in steps if c == top]
+    step = (passes[0][0], sum(t for _, t in passes)) if passes else None
     if step:
         gbs = bpc * cells / (step[1] * 1e-6) / 1e9
-        lines += ["Step kernel `%s`: %d B/cell algorithmic x %d cells = %.1f MB per launch; at the traced"
-                  % (step[0][:80], bpc, cells, bpc * cells / 1e6),
-                  "average %.2f us that is %.0f GB/s, %.1f%% of the 8 TB/s HBM peak."
+        what = "Step kernel `%s`" % step[0][:80] if len(passes) == 1 else \
+            "The step's %d passes (`%s` ...)" % (len(passes), step[0][:60])
+        lines += ["%s: %d B/cell algorithmic x %d cells = %.1f MB per step; at the traced"
+                  % (what, bpc, cells, bpc * cells / 1e6),
+                  "average %.2f us per step that is %.0f GB/s, %.1f%% of the 8 TB/s HBM peak."
                   % (step[1], gbs, 100.0 * gbs / HBM_PEAK_GBS)]
     kind = next((v for v in KERNEL_NAMES.values() if step and v in step[0]), "kernel")
     out = os.path.join(PROFILES, "%s_%s_trace.md" % (profile_name(args), kind))
@@ -356,9 +392,14 @@ def main():
     ap.add_argument("--trace-summary", metavar="STATS_DIR",
                     help="write profiles/<workload>_kernel_trace.md from rocprofv3 --stats output")
     ap.add_argument("--trace-command", default="", help="the profiling command, recorded in the summary")
+    ap.add_argument("--counter-summary", metavar="PMC_DIR",
+                    help="write profiles/<workload>_<kernel>_counters.md from a rocprofv3 --pmc run")
+    ap.add_argument("--counter-command", default="", help="the profiling command, recorded in the summary")
     args = ap.parse_args()
     if args.pmc_summary:
         return pmc_summary(args)
+    if args.counter_summary:
+        return counter_summary(args)
     if args.trace_summary:
         return trace_summary(args)
     if args.gpus != 1:

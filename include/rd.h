@@ -183,31 +183,38 @@ enum {
                               (temporal blocking; diffusion and Brusselator).
                               rd_step with an odd count finishes with one
                               direct-kernel step                               */
-    RD_KERNEL_FUSED = 6    /* FRONT_CH with the 7-point Laplacian only: the
+    RD_KERNEL_FUSED = 6,   /* FRONT_CH with the 7-point Laplacian only: the
                               whole step in one launch (the Cahn-Hilliard
                               chemical potential computed in LDS one plane
                               ahead of the update, no mu array in HBM; the two
                               Laplacian passes of section 4.1 fused).  128-cell
                               x tiles, any nx (a periodic x axis of C needs
                               nx <= 128 or a multiple of 128)                  */
+    RD_KERNEL_TRING = 7    /* FP32 or BF16, 7-point diffusion of one or two
+                              species, Brusselator and the pollutant's passes
+                              of one or two species: z-march over
+                              128-cell x tiles of ry rows, every field streamed
+                              into an LDS ring by one loading wave, any nx     */
 };
 typedef struct rd_plan {
     int32_t kernel;       /* RD_KERNEL_*                                        */
     int32_t vx;           /* TILED/BLOCK: cells per lane along x (1, 2 or 4);
                              LDS: 4 (rows of <= 256 cells) or 8 (257..512);
                              LDS2: 4 (rows of 256 cells) or 8 (of 512);
-                             FUSED: waves computing the chemical potential    */
+                             FUSED: waves computing the chemical potential;
+                             TRING: 2 (cells per lane)                         */
     int32_t ry;           /* TILED/BLOCK: rows per wave (1, 2 or 4);
-                             LDS/LDS2/FUSED: rows per workgroup                */
+                             LDS/LDS2/FUSED/TRING: rows per workgroup          */
     int32_t waves;        /* TILED/BLOCK: waves per workgroup (1 or 4);
                              LDS/LDS2: computing waves (plus one loading wave);
                              FUSED: waves updating the fields (plus vx waves
-                             for the chemical potential and one loading wave) */
-    int32_t cz;           /* TILED/LDS/LDS2/FUSED: z planes per workgroup, 0 = all;
+                             for the chemical potential and one loading wave);
+                             TRING: computing waves (plus one loading wave)   */
+    int32_t cz;           /* TILED/LDS/LDS2/FUSED/TRING: z planes per workgroup, 0 = all;
                              BLOCK: planes per slab (2, 4 or 8)                */
     int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2);
-                             LDS/LDS2/FUSED: input ring slots                  */
-    int32_t order;        /* BLOCK/LDS/LDS2/FUSED: tile enumeration, 0 = x, then y, then z chunk;
+                             LDS/LDS2/FUSED/TRING: input ring slots            */
+    int32_t order;        /* BLOCK/LDS/LDS2/FUSED/TRING: tile enumeration, 0 = x, then y, then z chunk;
                              1 = z chunk fastest (z-neighbour slabs run together
                              on one XCD and share its L2)                       */
     int32_t graph_chunk;  /* rd_step replays hipGraphs of this many steps (even,

@@ -409,6 +409,41 @@ __device__ __forceinline__ float lapf(const Nb& n, const P& a, int f) {
 template <class P>
 __device__ __forceinline__ float lapf(const Nb19& n, const P& a, int f) { return lap19(n, a.kx[f]); }
 
+// A per-lane copy of a uniform value: the copy lives in a VGPR for the whole
+// z march, so the plane loops of the marching kernels issue no scalar reloads
+// of the launch's constants (scalar loads share the LDS reads' wait counter,
+// so each reload would also stall on every LDS read in flight) and the SGPRs
+// stay free for the loop's own scalars.
+__device__ __forceinline__ float vcopy(float x) {
+#ifdef __HIP_DEVICE_COMPILE__
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+#else
+    return x;
+#endif
+}
+
+// The coefficients the cell functions read, under the step arguments' names
+// (so the cell arithmetic takes either), copied once per wave.
+struct CellConst {
+    float kx[MAXF], ky[MAXF], kz[MAXF], kc[MAXF];
+    float p[8];
+    float dt;
+    __device__ __forceinline__ explicit CellConst(const StepArgs& a) {
+#pragma unroll
+        for (int f = 0; f < MAXF; ++f) {
+            kx[f] = vcopy(a.kx[f]);
+            ky[f] = vcopy(a.ky[f]);
+            kz[f] = vcopy(a.kz[f]);
+            kc[f] = vcopy(a.kc[f]);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) p[i] = vcopy(a.p[i]);
+        dt = vcopy(a.dt);
+    }
+};
+
 // The Laplacian of a neighbourhood: 7-point (per-axis K/h^2) or 19-point
 // (all three coefficients hold K/(6h^2)).
 __device__ __forceinline__ float lap(const Nb& n, float kx, float ky, float kz) { return lap7(n, kx, ky, kz); }
@@ -428,8 +463,8 @@ template <int NS> struct Diffusion {
     static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    template <class NB>
-    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[NF], float,
+    template <class NB, class P>
+    static __device__ __forceinline__ void cell(const P& a, const NB (&n)[NF], float,
                                                 bool, const float (&)[NO], float (&o)[NO]) {
 #pragma unroll
         for (int s = 0; s < NS; ++s)
@@ -444,8 +479,8 @@ struct Brusselator {
     static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    template <class NB>
-    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[2], float,
+    template <class NB, class P>
+    static __device__ __forceinline__ void cell(const P& a, const NB (&n)[2], float,
                                                 bool, const float (&)[2], float (&o)[2]) {
         const float u = n[0].c, v = n[1].c;
         const float uuv = (u * u) * v;
@@ -473,8 +508,8 @@ struct ChemPotential {
     static __device__ __forceinline__ float mu(const P& a, float c, float lc) {
         return __fmaf_rn(-a.p[2], lc, __fmaf_rn(a.p[4] * c, c * c, -(a.p[3] * c)));
     }
-    template <class NB>
-    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[1], float,
+    template <class NB, class P>
+    static __device__ __forceinline__ void cell(const P& a, const NB (&n)[1], float,
                                                 bool, const float (&)[1], float (&o)[1]) {
         o[0] = mu(a, n[0].c, lapf(n[0], a, 0));
     }
@@ -500,8 +535,8 @@ struct FrontCH {
         o[1] = __fmaf_rn(a.dt, lb - r, B);
         o[2] = __fmaf_rn(a.dt, __fmaf_rn(a.p[1], lmu, lc + r) - q, C);
     }
-    template <class NB>
-    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[4], float,
+    template <class NB, class P>
+    static __device__ __forceinline__ void cell(const P& a, const NB (&n)[4], float,
                                                 bool, const float (&)[3], float (&o)[3]) {
         const float A = n[0].c, B = n[1].c, C = n[2].c;
         const float q = (a.p[5] * A) * C;
@@ -523,8 +558,8 @@ template <int NS, bool COUPLED> struct Pollutant {
     static constexpr int WIND = WIND_PLANE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    template <class NB>
-    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[NF], float uh,
+    template <class NB, class P>
+    static __device__ __forceinline__ void cell(const P& a, const NB (&n)[NF], float uh,
                                                 bool has_e, const float (&e)[NO], float (&o)[NO]) {
         const float c0 = n[0].c;
 #pragma unroll
@@ -550,8 +585,8 @@ struct Turing {
     static constexpr int WIND = WIND_NONE;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    template <class NB>
-    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[2], float,
+    template <class NB, class P>
+    static __device__ __forceinline__ void cell(const P& a, const NB (&n)[2], float,
                                                 bool, const float (&)[2], float (&o)[2]) {
         const float u = n[0].c, v = n[1].c;
         const float r1 = (u - (u * u) * u) - v;
@@ -573,8 +608,8 @@ template <int NS> struct Atmos {
     static constexpr int WIND = WIND_CLOCK;
     static __host__ __device__ constexpr bool f32_field(int) { return false; }
     static __host__ __device__ constexpr bool f32_out(int) { return false; }
-    template <class NB>
-    static __device__ __forceinline__ void cell(const StepArgs& a, const NB (&n)[NF], float uzh,
+    template <class NB, class P>
+    static __device__ __forceinline__ void cell(const P& a, const NB (&n)[NF], float uzh,
                                                 bool has_e, const float (&e)[NO], float (&o)[NO]) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -1544,6 +1579,18 @@ __device__ __forceinline__ void vm_wait_steps(int n) {
 
 // A workgroup barrier the compiler may not move memory accesses across, with
 // no fence: a fence would wait for every load in flight.
+// s_waitcnt vmcnt(n) for a run-time n in [LO, HI] (a tree of immediates)
+template <int LO, int HI>
+__device__ __forceinline__ void vm_wait_count(int n) {
+    if constexpr (LO == HI) {
+        vm_wait_imm<LO>();
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (n <= MID) vm_wait_count<LO, MID>(n);
+        else vm_wait_count<MID + 1, HI>(n);
+    }
+}
+
 __device__ __forceinline__ void ring_barrier() {
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();

@@ -16,6 +16,7 @@
 #include "rd.h"
 #define RD_DEFINE_ENGINE_KERNELS
 #include "rd_fch_cfg.hpp"
+#include "rd_tring_cfg.hpp"
 #include "rd_internal.hpp"
 
 using namespace rdk;
@@ -130,6 +131,12 @@ hipError_t launch_fch(int storage, int cfg, const StepArgs&, const StepArgs* d, 
     case ST_F16: return launch_fch_f16(cfg, d, blocks, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+int tr_cfg_index(int by, int wc, int d) {
+    for (int i = 0; i < kNumTrCfgs; ++i)
+        if (kTrCfgs[i].by == by && kTrCfgs[i].wc == wc && kTrCfgs[i].d == d) return i;
+    return -1;
 }
 
 int lds2_cfg_index(int nch, int by, int wc, int d) {
@@ -273,9 +280,9 @@ void fill_mirror(StepArgs& a, int f) {
 long long set_tiling(StepArgs& a, const rd_plan& p) {
     // LDS ring: whole rows (vx cells per lane), ry rows per workgroup; the
     // one-pass front kernel: 128-cell x tiles, ry rows per workgroup
-    const bool fch = p.kernel == RD_KERNEL_FUSED;
-    const bool ring = p.kernel == RD_KERNEL_LDS || p.kernel == RD_KERNEL_LDS2 || fch;
-    const int tx = fch ? kFchTile : 64 * p.vx, by = ring ? p.ry : p.ry * p.waves;
+    const bool fch = p.kernel == RD_KERNEL_FUSED, tr = p.kernel == RD_KERNEL_TRING;
+    const bool ring = p.kernel == RD_KERNEL_LDS || p.kernel == RD_KERNEL_LDS2 || fch || tr;
+    const int tx = fch ? kFchTile : tr ? kTrTile : 64 * p.vx, by = ring ? p.ry : p.ry * p.waves;
     const int cz = (p.cz <= 0 || p.cz > a.nz) ? a.nz : p.cz;
     a.tiles_x = (a.nx + tx - 1) / tx;
     a.tiles_y = (a.ny + by - 1) / by;
@@ -441,6 +448,16 @@ int check_plan(const rd_grid* g, const rd_plan& p, int* cfg_out) {
         *cfg_out = cfg;
         return RD_OK;
     }
+    if (p.kernel == RD_KERNEL_TRING) {
+        const int cfg = p.vx == 2 ? tr_cfg_index(p.ry, p.waves, p.prefetch) : -1;
+        if (cfg < 0) return fail(RD_EINVAL, "tiled LDS ring shape not available (vx must be 2)");
+        for (int k = 0; k < g->npass; ++k)
+            if (!tr_ok(g->storage, g->pass_pm[k], cfg))
+                return fail(RD_EINVAL, "tiled LDS ring shape not compiled for this model and storage");
+        if (p.cz < 0) return fail(RD_EINVAL, "cz must be >= 0");
+        *cfg_out = cfg;
+        return RD_OK;
+    }
     if (p.kernel == RD_KERNEL_LDS2) {
         const int cfg = (p.vx == 4 || p.vx == 8) ? lds2_cfg_index(p.vx / 4, p.ry, p.waves, p.prefetch) : -1;
         if (cfg < 0) return fail(RD_EINVAL, "two-step LDS ring shape not available");
@@ -485,7 +502,7 @@ int apply_plan(rd_grid* g) {
         for (int k = 0; k < g->npass; ++k) {
             StepArgs& a = g->args[par][k];
             if (p.kernel == RD_KERNEL_TILED || p.kernel == RD_KERNEL_BLOCK || p.kernel == RD_KERNEL_LDS ||
-                p.kernel == RD_KERNEL_LDS2 || p.kernel == RD_KERNEL_FUSED) {
+                p.kernel == RD_KERNEL_LDS2 || p.kernel == RD_KERNEL_FUSED || p.kernel == RD_KERNEL_TRING) {
                 g->blocks[k] = set_tiling(a, p);
                 (void)set_tiling(g->rk_args[par][k], p);
                 (void)set_tiling(g->rk3_args[par][k], p);
@@ -1422,6 +1439,30 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
                 p.vx = c.wm;
                 p.ry = c.by;
                 p.waves = c.wu;
+                p.prefetch = c.d;
+                p.cz = cz;
+                p.order = order;
+                cands.push_back(p);
+            }
+        }
+    }
+    for (int i = 0; i < kNumTrCfgs && !g->args[0][0].s19; ++i) {
+        bool ok = true;
+        for (int k = 0; k < g->npass; ++k) ok = ok && tr_ok(g->storage, g->pass_pm[k], i);
+        if (!ok) continue;
+        const TrCfg c = kTrCfgs[i];
+        const long long tiles = ((g->nx + kTrTile - 1) / kTrTile) * ((g->ny + c.by - 1) / c.by);
+        std::vector<int> czs = {0, 64, 32, 16};
+        const int bal = balanced_cz(g, tiles);
+        if (std::find(czs.begin(), czs.end(), bal) == czs.end()) czs.push_back(bal);
+        for (int cz : czs) {
+            if (cz != 0 && cz >= g->nz) continue;
+            for (int order : {0, 1}) {
+                rd_plan p{};
+                p.kernel = RD_KERNEL_TRING;
+                p.vx = 2;
+                p.ry = c.by;
+                p.waves = c.wc;
                 p.prefetch = c.d;
                 p.cz = cz;
                 p.order = order;

@@ -59,18 +59,6 @@ struct Fch {
     static __host__ __device__ constexpr int lead(int f) { return f == 2 ? 2 : 1; }
 };
 
-// s_waitcnt vmcnt(n) for a run-time n in [LO, HI] (a tree of immediates)
-template <int LO, int HI>
-__device__ __forceinline__ void vm_wait_count(int n) {
-    if constexpr (LO == HI) {
-        vm_wait_imm<LO>();
-    } else {
-        constexpr int MID = (LO + HI) / 2;
-        if (n <= MID) vm_wait_count<LO, MID>(n);
-        else vm_wait_count<MID + 1, HI>(n);
-    }
-}
-
 // The producer issues "steps": step k loads C plane z0-2+k (planes z0-2 ..
 // z1+1 exist) into C slot k mod DC and A/B plane z0-4+k (planes z0-1 .. z1)
 // into A/B slot (k-3) mod DAB.  Both planes of step k are first read at
@@ -186,41 +174,6 @@ __device__ __forceinline__ void fch_producer(const StepArgs& a, RD_LDS float* ri
 #endif
 }
 
-// A per-lane copy of a uniform value: the copy lives in a VGPR for the whole
-// z march, so the plane loops issue no scalar reloads of the launch's
-// constants (scalar loads share the LDS reads' wait counter, so each reload
-// would also stall on every LDS read in flight) and the SGPRs stay free for
-// the loop's own scalars.
-__device__ __forceinline__ float vcopy(float x) {
-#ifdef __HIP_DEVICE_COMPILE__
-    float r;
-    asm("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
-    return r;
-#else
-    return x;
-#endif
-}
-
-// The front model's coefficients, copied once per wave (same names as in the
-// step arguments, so the shared cell arithmetic takes either).
-struct FchConst {
-    float kx[4], ky[4], kz[4], kc[4];
-    float p[6];
-    float dt;
-    __device__ __forceinline__ explicit FchConst(const StepArgs& a) {
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            kx[f] = vcopy(a.kx[f]);
-            ky[f] = vcopy(a.ky[f]);
-            kz[f] = vcopy(a.kz[f]);
-            kc[f] = vcopy(a.kc[f]);
-        }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) p[i] = vcopy(a.p[i]);
-        dt = vcopy(a.dt);
-    }
-};
-
 // The computing waves, in two roles: WU waves update A, B and C on BY/WU rows
 // each, WM waves compute the chemical potential (its rows dealt round-robin;
 // the last of them also computes the columns x0-1 and x0+TX of every mu row,
@@ -240,7 +193,7 @@ struct FchConsumer {
     typedef float v2f __attribute__((ext_vector_type(2)));
 
     const StepArgs& a;
-    const FchConst k;
+    const CellConst k;
     const RD_LDS T* ring_c;
     const RD_LDS T* ring_ab;
     RD_LDS float* mring;

@@ -8,6 +8,7 @@
 #pragma once
 
 #include "rd_internal.hpp"
+#include "rd_tring.hpp"
 
 #include <utility>
 
@@ -87,6 +88,22 @@ hipError_t run_lds2(const StepArgs* d, long long blocks, hipStream_t s) {
     }
 }
 
+template <class M, int I>
+hipError_t run_tr(bool plain, const StepArgs* d, long long blocks, hipStream_t s) {
+    if constexpr (tr_ok(kStorage, PmOf<M>::v, I)) {
+        constexpr TrCfg c = kTrCfgs[I];
+        if (plain)
+            hipLaunchKernelGGL((tr_kernel<M, S, c.by, c.wc, c.d, true>), dim3((unsigned)blocks), dim3(64 * (c.wc + 1)),
+                               0, s, d);
+        else
+            hipLaunchKernelGGL((tr_kernel<M, S, c.by, c.wc, c.d, false>), dim3((unsigned)blocks),
+                               dim3(64 * (c.wc + 1)), 0, s, d);
+        return hipGetLastError();
+    } else {
+        return hipErrorNotSupported;
+    }
+}
+
 // Launch table index `cfg` of a shape table: one branch per compiled entry.
 template <class M, int... I>
 hipError_t run_tiled_index(int cfg, const StepArgs* d, long long blocks, hipStream_t s,
@@ -120,6 +137,14 @@ hipError_t run_lds2_index(int cfg, const StepArgs* d, long long blocks, hipStrea
     return r;
 }
 
+template <class M, int... I>
+hipError_t run_tr_index(int cfg, bool plain, const StepArgs* d, long long blocks, hipStream_t s,
+                        std::integer_sequence<int, I...>) {
+    hipError_t r = hipErrorInvalidValue;
+    ((void)(cfg == I && ((r = run_tr<M, I>(plain, d, blocks, s)), true)), ...);
+    return r;
+}
+
 template <class M>
 hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, long long blocks,
                      hipStream_t s) {
@@ -130,6 +155,9 @@ hipError_t run_model(int kernel, int cfg, const StepArgs& h, const StepArgs* d, 
                      : run_lds_index<M, false>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLdsCfgs>{});
     if (h.s19) return hipErrorNotSupported;
     if (kernel == 5) return run_lds2_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumLds2Cfgs>{});
+    if (kernel == 7)
+        return run_tr_index<M>(cfg, h.rk_w == 0.f && !h.sr, d, blocks, s,
+                               std::make_integer_sequence<int, kNumTrCfgs>{});
     if (kernel == 3) return run_block_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumBlockCfgs>{});
     return run_tiled_index<M>(cfg, d, blocks, s, std::make_integer_sequence<int, kNumTileCfgs>{});
 }

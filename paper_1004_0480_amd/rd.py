@@ -21,7 +21,7 @@ F32, BF16, F16, F64 = 0, 1, 2, 3
 STORAGE = {"f32": F32, "bf16": BF16, "f16": F16}
 MODEL = {"diffusion": 0, "brusselator": 1, "front_ch": 2, "pollutant": 3, "turing": 4, "atmos": 5}
 BC = {"mirror": 0, "periodic": 1, "ghost": 2, "held": 3}
-KERNEL = {"auto": 0, "direct": 1, "tiled": 2, "block": 3, "lds": 4, "lds2": 5, "fused": 6}
+KERNEL = {"auto": 0, "direct": 1, "tiled": 2, "block": 3, "lds": 4, "lds2": 5, "fused": 6, "tring": 7}
 INTEGRATOR = {"euler": 1, "rk2": 2, "rk3": 3}
 PARAMS = {
     "diffusion": (),

@@ -34,6 +34,7 @@ LDS2_SHAPES = [(4, 4, 8, 6), (8, 4, 8, 6), (4, 8, 8, 5), (8, 6, 6, 4), (4, 6, 12
 # waves, ring slots)
 FCH_SHAPES = [(8, 8, 5, 7), (4, 4, 3, 7), (4, 4, 3, 6), (2, 2, 2, 7), (4, 4, 2, 7), (8, 8, 4, 8), (16, 8, 6, 7),
               (4, 4, 3, 9), (8, 8, 5, 6), (4, 4, 3, 5), (4, 4, 2, 5), (8, 8, 5, 5)]
+TR_SHAPES = [(8, 8, 6), (4, 4, 7), (8, 4, 6), (4, 4, 6), (8, 8, 5), (16, 8, 5)]
 BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
                 (2, 1, 4, 4), (4, 2, 1, 2), (4, 1, 1, 2), (4, 2, 1, 4), (4, 4, 1, 2), (4, 2, 2, 2),
                 (4, 3, 1, 2)]
@@ -72,6 +73,8 @@ def compiled_plans(w, storage="f32", czs=(0, 8)):
               for vx, by, wc, d in LDS2_SHAPES for cz in czs for o in (0, 1)]
     cands += [dict(kernel="fused", vx=wm, ry=by, waves=wu, prefetch=d, cz=cz, order=o)
               for by, wu, wm, d in FCH_SHAPES for cz in czs for o in (0, 1)]
+    cands += [dict(kernel="tring", vx=2, ry=by, waves=wc, prefetch=d, cz=cz, order=o)
+              for by, wc, d in TR_SHAPES for cz in czs for o in (0, 1)]
     for p in cands:
         try:
             g.set_plan(**p)
@@ -591,6 +594,29 @@ def test_whole_tile_rows_every_plan(case):
             continue
         for s in range(w.spec.ns):
             assert np.array_equal(got[s], base[s]), (case, plan, s)
+
+
+@pytest.mark.parametrize("nx", [130, 200, 256, 384])
+@pytest.mark.parametrize("xface", ["mirror", "periodic", "ghost", "held"])
+def test_tiled_ring_x_faces(nx, xface):
+    """The tiled LDS ring's 128-cell x tiles: rows that end inside a tile or
+    on a tile boundary, under every x face rule (the halo units loaded for a
+    periodic axis, the face rules applied at the first and last tile), for a
+    one-field and a two-field model: bitwise the direct kernel's values."""
+    shape = (7, 9, nx)
+    rng = np.random.default_rng(nx)
+    kind = {"mirror": (MIRROR, 0), "periodic": (PERIODIC, 0), "ghost": (GHOST, 0.75), "held": (HELD, 0.5)}[xface]
+    faces = [kind, kind, (MIRROR, 0), (GHOST, -0.25), (HELD, 1.0), (MIRROR, 0)]
+    for ns in (1, 2):
+        spec = bc_spec(ns, faces)
+        w = W.Workload("xfaces", shape, spec, [rng.uniform(0, 1, shape) for _ in range(ns)], 5, 0)
+        plans = [p for p in compiled_plans(w, czs=(0, 3)) if p["kernel"] == "tring"]
+        assert plans, (nx, xface, ns)
+        base, _ = gpu_run(w, 5, plan=dict(kernel="direct"))
+        for plan in plans:
+            got, _ = gpu_run(w, 5, plan=plan)
+            for s in range(ns):
+                assert np.array_equal(got[s], base[s]), (nx, xface, ns, plan, s)
 
 
 # ------------------------------------------------------ 19-point Laplacian
