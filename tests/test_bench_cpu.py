@@ -50,20 +50,20 @@ def test_algorithmic_bytes_per_cell():
 
 
 def test_traffic_is_read_only_for_its_sources_and_kernel_kind(tmp_path, monkeypatch):
-    src = os.path.join(ROOT, "profiles", "brusselator256_lds_kernel_pmc.json")
+    src = os.path.join(ROOT, "profiles", "diffusion512_lds_kernel_pmc.json")
     rec = json.load(open(src))
     monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
-    shutil.copy(src, tmp_path / "brusselator256_lds_kernel_pmc.json")
+    shutil.copy(src, tmp_path / "diffusion512_lds_kernel_pmc.json")
     d = rec["source_digest"]
-    assert bench.measured_traffic("brusselator256", d, 4)["traffic_over_algorithmic"] == \
+    assert bench.measured_traffic("diffusion512", d, 4)["traffic_over_algorithmic"] == \
         rec["traffic_over_algorithmic"]
-    assert bench.measured_traffic("brusselator256", "0" * 16, 4) is None    # other sources
-    assert bench.measured_traffic("brusselator256", d, 3) is None           # other kind
-    assert bench.measured_traffic("brusselator256_19pt", d, 4) is None      # other workload
+    assert bench.measured_traffic("diffusion512", "0" * 16, 4) is None    # other sources
+    assert bench.measured_traffic("diffusion512", d, 3) is None           # other kind
+    assert bench.measured_traffic("diffusion512_19pt", d, 4) is None      # other workload
     # a summary whose kernel is not of the kind its file name says is ignored
     bad = dict(rec, kernel=rec["kernel"].replace("lds_kernel", "block_kernel"))
-    (tmp_path / "brusselator256_lds_kernel_pmc.json").write_text(json.dumps(bad))
-    assert bench.measured_traffic("brusselator256", d, 4) is None
+    (tmp_path / "diffusion512_lds_kernel_pmc.json").write_text(json.dumps(bad))
+    assert bench.measured_traffic("diffusion512", d, 4) is None
 
 
 def test_kernel_source_digest_tracks_the_kernel_sources(tmp_path, monkeypatch):
