@@ -1941,6 +1941,43 @@ __device__ __forceinline__ void lds_done() {
     __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
 }
 
+// One LDS cell read (waited for in the same block) and one written, in
+// assembly, by a producer wave between its direct-to-LDS loads: for an
+// ordinary LDS access that might overlap a load in flight the compiler
+// drains every load, which would empty the producer's pipeline.  (The cells
+// these touch belong to loads already waited for.)
+template <typename T>
+__device__ __forceinline__ T lds_peek(const RD_LDS T* p) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 2, "cell size");
+    uint32_t v;
+#ifdef __HIP_DEVICE_COMPILE__
+    const uint32_t addr = uint32_t(reinterpret_cast<uintptr_t>(p));
+    if constexpr (sizeof(T) == 4)
+        asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr));
+    else
+        asm volatile("ds_read_u16 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=v"(v) : "v"(addr));
+#else
+    (void)p;
+    v = 0;
+#endif
+    T r;
+    __builtin_memcpy(&r, &v, sizeof(T));
+    return r;
+}
+template <typename T>
+__device__ __forceinline__ void lds_poke(RD_LDS T* p, T x) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 2, "cell size");
+    uint32_t v = 0;
+    __builtin_memcpy(&v, &x, sizeof(T));
+#ifdef __HIP_DEVICE_COMPILE__
+    const uint32_t addr = uint32_t(reinterpret_cast<uintptr_t>(p));
+    if constexpr (sizeof(T) == 4) asm volatile("ds_write_b32 %0, %1" : : "v"(addr), "v"(v));
+    else asm volatile("ds_write_b16 %0, %1" : : "v"(addr), "v"(v));
+#else
+    (void)p;
+#endif
+}
+
 template <class M, int NCH, int BY, int WC, int D>
 __device__ __forceinline__ void lds2_producer(const StepArgs& a, RD_LDS float* iring, int yb, int z0, int z1) {
     using R = Lds2Ring<M::NF, NCH, BY, D>;
@@ -2237,71 +2274,21 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds2_kernel(const StepArgs* __r
     else lds2_consumer<M, NCH, BY, WC, D>(a, ib, mb, w - 1, yb, z0, z1);
 }
 
-// ------------------------------------------------------------ batched kernel
-// A persistent launch walks the (grid, slab) work items of many grids.  The
-// host writes, before each tick, `meta` = {ngrids, total_items, first_item[0..
-// ngrids]} and one entry per grid (its step arguments for both parities,
-// model, parity of the current state, steps left).  Every workgroup takes a
-// contiguous run of items, so it locates its first grid once and then walks
-// forward; consecutive items are neighbouring slabs of the same grid.
+// ------------------------------------------------------------ batch table
+// The batched launch (rd_tring.hpp, batched_tr_kernel) walks the (grid,
+// tile) work items of many grids.  The host writes, before each tick, `meta`
+// = {ngrids, total_items, first_item[0 .. ngrids]} and one entry per grid:
+// its step arguments for both parities (tiled for that kernel), model,
+// parity of the current state, steps left.
 
 struct BatchEntry {
     StepArgs args[2];     // by input parity
     int model;            // 0 diffusion (1 species), 1 Brusselator
-    int shape;            // slab shape: 0 the narrow rows (VX0 cells per lane), 1 the wide (VX1)
     int ntiles;
     int first_item;
     int parity;           // parity of the current state at tick start
     long long steps_left; // at tick start
 };
-
-template <class S, int VX0, int VX1, int RY, int W, int CZ>
-__global__ __launch_bounds__(64 * W) void batched_kernel(const int* __restrict__ meta,
-                                                          const BatchEntry* __restrict__ ents, int step) {
-    // one LDS buffer serves every (model, shape): a workgroup steps one item
-    // at a time and synchronises between items
-    constexpr size_t NB = sizeof(BlockLds<Brusselator, W, 64 * VX1>) > sizeof(BlockLds<Brusselator, W, 64 * VX0>)
-                              ? sizeof(BlockLds<Brusselator, W, 64 * VX1>)
-                              : sizeof(BlockLds<Brusselator, W, 64 * VX0>);
-    static_assert(sizeof(BlockLds<Diffusion<1>, W, 64 * VX1>) <= NB &&
-                      sizeof(BlockLds<Diffusion<1>, W, 64 * VX0>) <= NB, "batch LDS");
-    __shared__ __attribute__((aligned(16))) float sm_raw[NB / sizeof(float)];
-    const int ng = meta[0];
-    const int total = meta[1];
-    const int* first = meta + 2;
-    const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
-    int item = (int)blockIdx.x * per;
-    const int end = min(total, item + per);
-    if (item >= end) return;
-    int lo = 0, hi = ng - 1;                     // last grid with first_item <= item
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (first[mid] <= item) lo = mid; else hi = mid - 1;
-    }
-    int g = lo;
-    for (; item < end; ++item) {
-        while (g + 1 < ng && first[g + 1] <= item) ++g;
-        const BatchEntry& en = ents[g];
-        if (step >= en.steps_left) continue;     // this grid already finished
-        const StepArgs& a = en.args[(en.parity + step) & 1];
-        const int t = item - first[g];
-        if (en.shape == 0) {
-            if (en.model == 1)
-                block_step<Brusselator, S, VX0, RY, W, CZ>(
-                    a, t, *reinterpret_cast<BlockLds<Brusselator, W, 64 * VX0>*>(sm_raw));
-            else
-                block_step<Diffusion<1>, S, VX0, RY, W, CZ>(
-                    a, t, *reinterpret_cast<BlockLds<Diffusion<1>, W, 64 * VX0>*>(sm_raw));
-        } else {
-            if (en.model == 1)
-                block_step<Brusselator, S, VX1, RY, W, CZ>(
-                    a, t, *reinterpret_cast<BlockLds<Brusselator, W, 64 * VX1>*>(sm_raw));
-            else
-                block_step<Diffusion<1>, S, VX1, RY, W, CZ>(
-                    a, t, *reinterpret_cast<BlockLds<Diffusion<1>, W, 64 * VX1>*>(sm_raw));
-        }
-    }
-}
 
 // ------------------------------------------------------------- reductions
 

@@ -1706,15 +1706,15 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     for (int i = 0; i < ng; ++i) {
         const Member& m = b->members[i];
         BatchEntry& e = ents[i];
-        // the narrow slab shape when its rows cover the grid's
-        e.shape = m.g->nx <= 64 * kBatchBlocks[0].vx ? 0 : 1;
-        const BlockCfg& bc = kBatchBlocks[e.shape];
+        // tiles of the tiled LDS ring, each marching a z chunk (short enough
+        // that one grid's march does not set the length of a step)
         rd_plan tile{};
-        tile.kernel = RD_KERNEL_BLOCK;
-        tile.vx = bc.vx;
-        tile.ry = bc.ry;
-        tile.waves = bc.w;
-        tile.cz = bc.cz;
+        tile.kernel = RD_KERNEL_TRING;
+        tile.vx = 2;
+        tile.ry = kBatchTr.by;
+        tile.waves = kBatchTr.wc;
+        tile.prefetch = kBatchTr.d;
+        tile.cz = kBatchTr.cz;
         for (int par = 0; par < 2; ++par) {
             e.args[par] = m.g->args[par][0];
             e.ntiles = int(set_tiling(e.args[par], tile));

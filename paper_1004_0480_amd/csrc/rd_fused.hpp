@@ -198,10 +198,43 @@ struct FchConsumer {
     const RD_LDS T* ring_ab;
     RD_LDS float* mring;
     int lane, x0, yb, xl;
+    // XF: the x face rules of the three fields at this tile (kind and value
+    // on each side), fixed for the march, where the tile meets each face, and
+    // whether this lane's cells are the grid's last; the LDS cell of x0-1
+    int fk[3][2];
+    float fv[3][2];
+    bool lface, rface, last0, last1;
+    int hlo;
     __device__ __forceinline__ FchConsumer(const StepArgs& a_, const RD_LDS float* ring_c_w,
                                            const RD_LDS float* ring_ab_w, RD_LDS float* mring_, int x0_, int yb_)
         : a(a_), k(a_), ring_c((const RD_LDS T*)ring_c_w), ring_ab((const RD_LDS T*)ring_ab_w), mring(mring_),
-          lane(threadIdx.x & 63), x0(x0_), yb(yb_), xl(x0_ + 2 * (threadIdx.x & 63)) {}
+          lane(threadIdx.x & 63), x0(x0_), yb(yb_), xl(x0_ + 2 * (threadIdx.x & 63)) {
+        lface = rface = last0 = last1 = false;
+        hlo = HX - 1;
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                fk[f][side] = BC_MIRROR;
+                fv[f][side] = 0.f;
+            }
+        if constexpr (XF) {
+            lface = x0 == 0;
+            rface = x0 + TX >= a.nx;
+            last0 = xl == a.nx - 1;
+            last1 = xl + 1 == a.nx - 1;
+            // at the left face of a periodic axis the halo holds the 16-byte
+            // unit with cell nx-1
+            hlo = lface ? (a.nx - 1) % HX : HX - 1;
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    fk[f][side] = a.bck[f][side];
+                    fv[f][side] = vcopy(a.bcv[f][side]);
+                }
+        }
+    }
     // mu from C and Lap(C), and the rates of the front model
     __device__ __forceinline__ float mu_of(float c, float lc) const { return ChemPotential::mu(k, c, lc); }
     __device__ __forceinline__ void rates(float A, float B, float C, float la, float lb, float lc, float lmu,
@@ -246,9 +279,8 @@ struct FchConsumer {
         fix_row<1>(a, f, pz, py, x, t);
         v = t[0];
     }
-    // LDS cell of x0-1: at the left face of a periodic axis the halo holds the
-    // 16-byte unit with cell nx-1
-    __device__ __forceinline__ int hl_off() const { return XF && x0 == 0 ? (a.nx - 1) % HX : HX - 1; }
+    // LDS cell of x0-1
+    __device__ __forceinline__ int hl_off() const { return hlo; }
     __device__ __forceinline__ bool near(int p) const { return p <= 0 || p >= a.nz - 1; }
 
     // x neighbours of this lane's two cells (values v; halo cells hl = x0-1,
@@ -257,19 +289,19 @@ struct FchConsumer {
                                         float (&xp)[2]) const {
         float fill = hl;
         if constexpr (XF) {
-            const int kl = a.bck[f][0];
-            if (x0 == 0 && kl != BC_PERIODIC) fill = kl == BC_MIRROR ? v[0] : a.bcv[f][0];
+            const int kl = fk[f][0];
+            if (lface && kl != BC_PERIODIC) fill = kl == BC_MIRROR ? v[0] : fv[f][0];
         }
         xm[0] = lane_from_left(v[1], fill);
         xm[1] = v[0];
         xp[0] = v[1];
         xp[1] = lane_from_right(v[0], hr);
         if constexpr (XF) {
-            if (x0 + TX >= a.nx) {
-                const int kr = a.bck[f][1];
-                const float fv = a.bcv[f][1];
-                if (xl == a.nx - 1) xp[0] = kr == BC_MIRROR ? v[0] : kr == BC_PERIODIC ? hr : fv;
-                if (xl + 1 == a.nx - 1) xp[1] = kr == BC_MIRROR ? v[1] : kr == BC_PERIODIC ? hr : fv;
+            if (rface) {
+                const int kr = fk[f][1];
+                const float g = fv[f][1];
+                if (last0) xp[0] = kr == BC_MIRROR ? v[0] : kr == BC_PERIODIC ? hr : g;
+                if (last1) xp[1] = kr == BC_MIRROR ? v[1] : kr == BC_PERIODIC ? hr : g;
             }
         }
     }
@@ -521,16 +553,16 @@ struct FchConsumer {
             float lmu[2];
             {
                 float mlr = ml[r];
-                if constexpr (XF) mlr = x0 == 0 ? mc[r][0] : mlr;
+                if constexpr (XF) mlr = lface ? mc[r][0] : mlr;
                 float xm[2], xp[2];
                 xm[0] = lane_from_left(mc[r][1], mlr);
                 xm[1] = mc[r][0];
                 xp[0] = mc[r][1];
                 xp[1] = lane_from_right(mc[r][0], mr[r]);
                 if constexpr (XF) {
-                    if (x0 + TX >= a.nx) {
-                        if (xl == a.nx - 1) xp[0] = mc[r][0];
-                        if (xl + 1 == a.nx - 1) xp[1] = mc[r][1];
+                    if (rface) {
+                        if (last0) xp[0] = mc[r][0];
+                        if (last1) xp[1] = mc[r][1];
                     }
                 }
 #pragma unroll

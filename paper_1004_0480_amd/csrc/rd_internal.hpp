@@ -157,11 +157,10 @@ hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs&
                        const StepArgs* d, long long blocks, hipStream_t s);
 
 // Batched persistent kernel: one step of every table entry whose steps_left >
-// step.  Two slab shapes of four waves, two rows per wave and four planes,
-// with 64- and 128-cell rows: each grid takes the narrower one that covers
-// its rows (one tile per row up to 128 cells), so small grids keep their
-// lanes busy.
-constexpr BlockCfg kBatchBlocks[2] = {{1, 2, 4, 4}, {2, 2, 4, 4}};
+// step, each grid tiled for the tiled LDS ring with this shape (rows per
+// workgroup, computing waves, ring slots, z planes per tile).
+struct BatchTrCfg { int by, wc, d, cz; };
+constexpr BatchTrCfg kBatchTr = {8, 8, 6, 32};
 hipError_t launch_batched(int storage, const int* meta, const BatchEntry* ents, int step, int blocks,
                           hipStream_t s);
 int batched_blocks_per_cu(int storage);

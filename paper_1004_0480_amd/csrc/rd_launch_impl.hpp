@@ -195,22 +195,17 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 }
 
 #ifdef RD_WITH_BATCH
-static_assert(kBatchBlocks[0].ry == kBatchBlocks[1].ry && kBatchBlocks[0].w == kBatchBlocks[1].w &&
-                  kBatchBlocks[0].cz == kBatchBlocks[1].cz,
-              "the batch shapes differ in row length only");
-#define RD_BATCH_KERNEL                                                                          \
-    batched_kernel<S, kBatchBlocks[0].vx, kBatchBlocks[1].vx, kBatchBlocks[0].ry, kBatchBlocks[0].w, \
-                   kBatchBlocks[0].cz>
+#define RD_BATCH_KERNEL batched_tr_kernel<S, kBatchTr.by, kBatchTr.wc, kBatchTr.d>
 hipError_t RD_BATCH_FN(launch_batched)(const int* meta, const BatchEntry* ents, int step, int blocks,
                                        hipStream_t s) {
-    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * kBatchBlocks[0].w), 0, s, meta, ents, step);
+    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * (1 + kBatchTr.wc)), 0, s, meta, ents, step);
     return hipGetLastError();
 }
 
 int RD_BATCH_FN(batched_blocks_per_cu)() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&RD_BATCH_KERNEL),
-                                                     64 * kBatchBlocks[0].w, 0) != hipSuccess)
+                                                     64 * (1 + kBatchTr.wc), 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }

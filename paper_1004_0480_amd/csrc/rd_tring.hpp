@@ -21,9 +21,11 @@
 // (so the values are bitwise those of the direct kernel); x neighbours come
 // from the neighbouring lane (DPP) and the halo, y from the ring, z from
 // registers.  Face rules: rows and planes beyond a face are loaded from the
-// mirrored or wrapped row/plane; fixed values, held faces and the x faces of
-// the first and last tile are applied by the computing waves (FIX and XF
-// variants, only where they can matter).
+// mirrored or wrapped row/plane; at the grid's x faces the producer writes
+// the ring cells left of x = 0 and right of x = nx-1; fixed values and held
+// faces are applied by the computing waves (a FIX variant, only where a row
+// or plane of the wave is fixed, which applies the x face rules again from
+// registers).
 #pragma once
 
 #include "rd_tring_cfg.hpp"
@@ -120,6 +122,34 @@ __device__ __forceinline__ void tr_producer(const StepArgs& a, RD_LDS float* rin
         }
         slot = slot + 1 == DR ? 0 : slot + 1;
     };
+    // At the grid's x faces the ring cell left of x = 0 and the one right of
+    // x = nx-1 (in the tile, or the halo unit) take the face rule's value once
+    // a step has landed, so the computing waves read every x neighbour from
+    // the ring.  Lane j patches ring row j of each field.
+    const bool lface = x0 == 0, rface = x0 + R::TX >= a.nx;
+    const int pr = a.nx - x0 + R::HX;              // ring cell of x = nx
+    int patched = -1, pslot = 0;                   // last patched step, slot of the next
+    auto patch = [&](int k) __attribute__((always_inline)) {
+        // one field at a time, so that its face rule is a scalar
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (k > last || lane >= R::RR) continue;
+            RD_LDS T* r = (RD_LDS T*)(ring + pslot * R::SLOT_W) + (f * R::RR + lane) * R::RW;
+            if (lface) {
+                const int kl = a.bck[f][0];
+                const T v = kl == BC_PERIODIC ? lds_peek(r + (a.nx - 1) % R::HX)
+                            : kl == BC_MIRROR ? lds_peek(r + R::HX) : S::down(a.bcv[f][0]);
+                lds_poke(r + R::HX - 1, v);
+            }
+            if (rface) {
+                const int kr = a.bck[f][1];
+                const T v = kr == BC_PERIODIC ? lds_peek(r + R::HX + R::TX)
+                            : kr == BC_MIRROR ? lds_peek(r + pr - 1) : S::down(a.bcv[f][1]);
+                lds_poke(r + pr, v);
+            }
+        }
+        pslot = pslot + 1 == DR ? 0 : pslot + 1;
+    };
     for (int k = 0; k < DR - 2; ++k) issue(k);
     constexpr int PER = NF * R::RR;                // loads per step
     constexpr int STEADY = (DR - 3) * PER < 63 ? (DR - 3) * PER : 63;
@@ -134,15 +164,18 @@ __device__ __forceinline__ void tr_producer(const StepArgs& a, RD_LDS float* rin
             for (int j = 1; j <= DR - 3; ++j) after += need + j <= last ? PER : 0;
             vm_wait_count<0, 63>(min(after, 63));
         }
+        if (lface || rface) {
+            while (patched < need) patch(++patched);
+            lds_done();
+        }
         ring_barrier();
         issue(q + DR + 1 - z0);
     }
 #endif
 }
 
-// A computing wave: RY = BY / WC output rows, two cells per lane.  XF: the
-// tile touches an x face of the grid (x0 = 0 or the row ends in it).
-template <class M, class S, int BY, int WC, int DR, bool XF>
+// A computing wave: RY = BY / WC output rows, two cells per lane.
+template <class M, class S, int BY, int WC, int DR>
 struct TrConsumer {
     using R = Tr<M, S, BY, DR>;
     using T = typename R::T;
@@ -187,16 +220,31 @@ struct TrConsumer {
         fix_row<1>(a, f, pz, py, x, t);
         v = t[0];
     }
-    // LDS cell of x0-1: at the left face of a periodic axis the halo holds the
-    // 16-byte unit with cell nx-1
-    __device__ __forceinline__ int hl_off() const { return XF && x0 == 0 ? (a.nx - 1) % HX : HX - 1; }
+    // LDS cell of x0-1 (at the grid's left face the producer's patch)
+    static constexpr int HL = HX - 1;
+    // The producer's patch holds a fixed x-face value of field f in the
+    // storage type; where that rounds it, the face is applied from registers
+    // (the FIX variant) instead.
+    __device__ __forceinline__ bool xface_rounded(int f) const {
+        bool r = false;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const bool at = side == 0 ? x0 == 0 : x0 + TX >= a.nx;
+            const int kind = a.bck[f][side];
+            const float v = a.bcv[f][side];
+            r = r || (at && kind != BC_MIRROR && kind != BC_PERIODIC && S::up(S::down(v)) != v);
+        }
+        return r;
+    }
 
     // x neighbours of this lane's two cells (values v; halo cells hl = x0-1,
-    // hr = x0+TX), by the x face rules of field f at the grid's faces
+    // hr = x0+TX); FIX: the x face rules of field f applied again at the
+    // grid's faces (the values of a fixed row differ from the loaded ones)
+    template <bool FIX>
     __device__ __forceinline__ void xnb(int f, const float (&v)[2], float hl, float hr, float (&xm)[2],
                                         float (&xp)[2]) const {
         float fill = hl;
-        if constexpr (XF) {
+        if constexpr (FIX) {
             const int kl = a.bck[f][0];
             if (x0 == 0 && kl != BC_PERIODIC) fill = kl == BC_MIRROR ? v[0] : a.bcv[f][0];
         }
@@ -204,7 +252,7 @@ struct TrConsumer {
         xm[1] = v[0];
         xp[0] = v[1];
         xp[1] = lane_from_right(v[0], hr);
-        if constexpr (XF) {
+        if constexpr (FIX) {
             if (x0 + TX >= a.nx) {
                 const int kr = a.bck[f][1];
                 const float fv = a.bcv[f][1];
@@ -234,7 +282,7 @@ struct TrConsumer {
         float ym[NF][RY][2], yp[NF][RY][2], hl[NF][RY], hr[NF][RY];
     };
     __device__ __forceinline__ void rows_read(int r0, const RD_LDS T* P, RowsIn& in) const {
-        const int hlo = hl_off();
+        const int hlo = HL;
 #pragma unroll
         for (int r = 0; r < RY; ++r)
 #pragma unroll
@@ -270,7 +318,7 @@ struct TrConsumer {
                     fix1(a, f, pz, y0, x0 + TX, in.hr[f][r]);
                 }
                 float xm[2], xp[2];
-                xnb(f, c0[f][r], in.hl[f][r], in.hr[f][r], xm, xp);
+                xnb<FIX>(f, c0[f][r], in.hl[f][r], in.hr[f][r], xm, xp);
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
                     n[i][f] = Nb{c0[f][r][i], xm[i], xp[i], in.ym[f][r][i], in.yp[f][r][i], cm[f][r][i], cp[f][r][i]};
@@ -314,7 +362,7 @@ struct TrConsumer {
         bool wfix = false;
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            wfix = wfix || (a.held[f] & 3) != 0;
+            wfix = wfix || (a.held[f] & 3) != 0 || xface_rounded(f);
 #pragma unroll
             for (int r = -1; r <= RY; ++r) wfix = wfix || ysrc(f, yb + r0 + r).cst != CST_NONE;
         }
@@ -333,7 +381,7 @@ struct TrConsumer {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int y = yb + r0 + r;
-            rowst[r] = y < a.ny && (!XF || xl < a.nx);
+            rowst[r] = y < a.ny && xl < a.nx;
 #pragma unroll
             for (int s = 0; s < NO; ++s)
                 po[s][r] = gstore_ptr<T>(a.out[s]) + ((long long)z0 * a.plane + (long long)y * a.pitch + xl);
@@ -381,8 +429,15 @@ struct TrConsumer {
     }
 };
 
+// One workgroup's march over its tile (wave w: 0 loads, the others compute).
+template <class M, class S, int BY, int WC, int DR, bool PLAIN>
+__device__ __forceinline__ void tr_run(const StepArgs& a, RD_LDS float* rg, int w, int x0, int yb, int z0, int z1) {
+    if (w == 0) tr_producer<M, S, BY, DR>(a, rg, x0, yb, z0, z1);
+    else TrConsumer<M, S, BY, WC, DR>(a, rg, x0, yb).template run<PLAIN>(w - 1, z0, z1);
+}
+
 // PLAIN: the launch has no Runge-Kutta combination and no stochastic
-// rounding (tr_plain), so only that store is compiled into it.
+// rounding, so only that store is compiled into it.
 template <class M, class S, int BY, int WC, int DR, bool PLAIN>
 __global__ __launch_bounds__(64 * (1 + WC)) void tr_kernel(const StepArgs* __restrict__ pa) {
     using R = Tr<M, S, BY, DR>;
@@ -392,17 +447,42 @@ __global__ __launch_bounds__(64 * (1 + WC)) void tr_kernel(const StepArgs* __res
     tick_clock<M>(a, (blockIdx.x | threadIdx.x) == 0);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const TileXYZ tc = tile_coords(a, xcd_tile(blockIdx.x, gridDim.x));
-    const int x0 = tc.x * R::TX;
-    const int yb = tc.y * BY;
     const int z0 = tc.z * a.cz;
-    const int z1 = min(z0 + a.cz, a.nz);
+    tr_run<M, S, BY, WC, DR, PLAIN>(a, (RD_LDS float*)&ring[0], w, tc.x * R::TX, tc.y * BY, z0,
+                                    min(z0 + a.cz, a.nz));
+}
+
+// The batched form (served grids of diffusion or the Brusselator, forward
+// Euler, round-to-nearest stores): a persistent launch walks the batch's
+// (grid, tile) items, each item a tile of 128-cell rows marching a z chunk
+// of its grid.  The host writes the table (rd_device.hpp, BatchEntry) with
+// each grid's arguments tiled for this kernel.
+template <class S, int BY, int WC, int DR>
+__global__ __launch_bounds__(64 * (1 + WC)) void batched_tr_kernel(const int* __restrict__ meta,
+                                                                    const BatchEntry* __restrict__ ents, int step) {
+    // one ring serves both models (sized for the Brusselator's two fields)
+    using RB = Tr<Brusselator, S, BY, DR>;
+    static_assert(Tr<Diffusion<1>, S, BY, DR>::SLOT_W <= RB::SLOT_W, "batch ring");
+    __shared__ __attribute__((aligned(16))) float ring[DR * RB::SLOT_W];
+    const int ng = meta[0];
+    const int total = meta[1];
+    const int* first = meta + 2;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     RD_LDS float* rg = (RD_LDS float*)&ring[0];
-    if (w == 0) {
-        tr_producer<M, S, BY, DR>(a, rg, x0, yb, z0, z1);
-    } else if (x0 == 0 || x0 + R::TX >= a.nx) {
-        TrConsumer<M, S, BY, WC, DR, true>(a, rg, x0, yb).template run<PLAIN>(w - 1, z0, z1);
-    } else {
-        TrConsumer<M, S, BY, WC, DR, false>(a, rg, x0, yb).template run<PLAIN>(w - 1, z0, z1);
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int lo = 0, hi = ng - 1;                 // last grid with first_item <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const BatchEntry& en = ents[lo];
+        if (step >= en.steps_left) continue;     // this grid already finished
+        const StepArgs& a = en.args[(en.parity + step) & 1];
+        const TileXYZ tc = tile_coords(a, item - first[lo]);
+        const int z0 = tc.z * a.cz, z1 = min(z0 + a.cz, a.nz);
+        if (en.model == 1) tr_run<Brusselator, S, BY, WC, DR, true>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
+        else tr_run<Diffusion<1>, S, BY, WC, DR, true>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
+        __syncthreads();                         // the next item refills the ring
     }
 }
 

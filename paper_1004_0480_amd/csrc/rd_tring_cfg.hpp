@@ -10,7 +10,7 @@ namespace rdk {
 // or two rows each), ring slots.
 struct TrCfg { int by, wc, d; };
 constexpr TrCfg kTrCfgs[] = {
-    {8, 8, 6}, {4, 4, 7}, {8, 4, 6}, {4, 4, 6}, {8, 8, 5}, {16, 8, 5},
+    {8, 8, 6}, {4, 4, 7}, {8, 4, 6}, {4, 4, 6}, {8, 8, 5}, {16, 8, 5}, {8, 8, 4}, {6, 6, 5},
 };
 constexpr int kNumTrCfgs = sizeof(kTrCfgs) / sizeof(kTrCfgs[0]);
 constexpr int kTrTile = 128;
