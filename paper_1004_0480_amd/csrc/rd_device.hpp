@@ -2277,7 +2277,8 @@ __global__ __launch_bounds__(64 * (WC + 1)) void lds2_kernel(const StepArgs* __r
 // ------------------------------------------------------------ batch table
 // The batched launch (rd_tring.hpp, batched_tr_kernel) walks the (grid,
 // tile) work items of many grids.  The host writes, before each tick, `meta`
-// = {ngrids, total_items, first_item[0 .. ngrids]} and one entry per grid:
+// = {ngrids, total_items, ticket, finished, first_item[0 .. ngrids]} (the two
+// counters zero) and one entry per grid:
 // its step arguments for both parities (tiled for that kernel), model,
 // parity of the current state, steps left.
 

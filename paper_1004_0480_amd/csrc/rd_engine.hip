@@ -171,7 +171,7 @@ hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs&
 #undef RD_GROUPS
 }
 
-hipError_t launch_batched(int storage, const int* meta, const BatchEntry* ents, int step, int blocks,
+hipError_t launch_batched(int storage, int* meta, const BatchEntry* ents, int step, int blocks,
                           hipStream_t s) {
     switch (storage) {
     case ST_F32: return launch_batched_f32(meta, ents, step, blocks, s);
@@ -1598,9 +1598,9 @@ struct rd_batch {
 };
 
 namespace {
-// device table: {ngrids, total_items, first_item[max_grids + 1]} padded to
-// 256 bytes, then max_grids entries
-size_t meta_bytes(int max_grids) { return (size_t(max_grids + 3) * sizeof(int) + 255) / 256 * 256; }
+// device table: {ngrids, total_items, ticket, finished, first_item[max_grids
+// + 1]} padded to 256 bytes, then max_grids entries
+size_t meta_bytes(int max_grids) { return (size_t(max_grids + 5) * sizeof(int) + 255) / 256 * 256; }
 size_t table_bytes(int max_grids, int n) { return meta_bytes(max_grids) + size_t(std::max(n, 1)) * sizeof(BatchEntry); }
 }
 
@@ -1695,16 +1695,27 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
         RD_HIP(hipEventSynchronize(b->tab_done));
         b->tab_pending = false;
     }
-    // Work list: every member's slabs, with its arguments for both parities.
+    // Work list: every member's tiles, with its arguments for both parities,
+    // the grids with the largest tiles first (the kernel's workgroups claim
+    // items in list order, so the small ones fill in at the end of a step).
     const int ng = int(b->members.size());
     const size_t moff = meta_bytes(b->max_grids);
     int* meta = reinterpret_cast<int*>(b->h_tab);
     BatchEntry* ents = reinterpret_cast<BatchEntry*>(b->h_tab + moff);
     std::memset(b->h_tab, 0, table_bytes(b->max_grids, ng));
+    std::vector<int> order(static_cast<size_t>(ng));
+    for (int i = 0; i < ng; ++i) order[size_t(i)] = i;
+    auto tile_cost = [&](int i) {
+        const rd_grid* g = b->members[size_t(i)].g;
+        const long long fields = g->model == RD_MODEL_BRUSSELATOR ? 2 : 1;
+        return fields * std::min<long long>(g->nx, kTrTile) * std::min<long long>(g->ny, kBatchTr.by) *
+               std::min<long long>(g->nz, kBatchTr.cz);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return tile_cost(p) > tile_cost(q); });
     long long items = 0;
     int64_t max_steps = 0;
     for (int i = 0; i < ng; ++i) {
-        const Member& m = b->members[i];
+        const Member& m = b->members[size_t(order[size_t(i)])];
         BatchEntry& e = ents[i];
         // tiles of the tiled LDS ring, each marching a z chunk (short enough
         // that one grid's march does not set the length of a step)
@@ -1721,7 +1732,7 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
         }
         e.model = m.g->model == RD_MODEL_BRUSSELATOR ? 1 : 0;
         e.first_item = int(items);
-        meta[2 + i] = int(items);
+        meta[4 + i] = int(items);
         e.parity = m.g->cur;
         e.steps_left = m.steps_left;
         items += e.ntiles;
@@ -1730,7 +1741,7 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     if (items > 0x7fffffffLL) return fail(RD_EINVAL, "batch work list too long");
     meta[0] = ng;
     meta[1] = int(items);
-    meta[2 + ng] = int(items);
+    meta[4 + ng] = int(items);
     RD_HIP(hipMemcpyAsync(b->d_tab, b->h_tab, moff, hipMemcpyHostToDevice, b->stream));
     RD_HIP(hipMemcpyAsync(b->d_tab + moff, b->h_tab + moff, size_t(ng) * sizeof(BatchEntry),
                           hipMemcpyHostToDevice, b->stream));
@@ -1743,7 +1754,7 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
             RD_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             hipError_t le = hipSuccess;
             for (int64_t i = 0; i < run && le == hipSuccess; ++i)
-                le = launch_batched(b->storage, reinterpret_cast<const int*>(b->d_tab),
+                le = launch_batched(b->storage, reinterpret_cast<int*>(b->d_tab),
                                     reinterpret_cast<const BatchEntry*>(b->d_tab + meta_bytes(b->max_grids)),
                                     int(i), b->blocks, b->stream);
             hipGraph_t graph = nullptr;
@@ -1761,7 +1772,7 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
         RD_HIP(hipGraphLaunch(it->second, b->stream));
     } else {
         for (int64_t i = 0; i < run; ++i) {
-            const hipError_t le = launch_batched(b->storage, reinterpret_cast<const int*>(b->d_tab),
+            const hipError_t le = launch_batched(b->storage, reinterpret_cast<int*>(b->d_tab),
                                                  reinterpret_cast<const BatchEntry*>(b->d_tab + meta_bytes(b->max_grids)),
                                                  int(i), b->blocks, b->stream);
             if (le != hipSuccess) return fail(RD_EDEVICE, std::string("batch launch: ") + hipGetErrorString(le));

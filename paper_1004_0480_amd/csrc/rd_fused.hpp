@@ -190,6 +190,7 @@ struct FchConsumer {
     using T = typename F::T;
     static constexpr int RY = BY / WU, MPW = (F::MROWS + WM - 1) / WM;
     static constexpr int HX = F::HX, TX = F::TX, RW = F::RW, MW = F::MW;
+    static constexpr int STORE_ANY = 0, STORE_PLAIN = 1, STORE_SR = 2;   // update's store forms
     typedef float v2f __attribute__((ext_vector_type(2)));
 
     const StepArgs& a;
@@ -487,13 +488,16 @@ struct FchConsumer {
     // A, B, C of plane z on rows r0 ..: plane z (slot P0) for the y and x
     // neighbours, centre rows of z-1, z, z+1 from registers, mu planes.  CD
     // false: C has no Fickian term and there is no redissolution (k2 = 0),
-    // so neither term is formed.  PLAIN: no Runge-Kutta combination and no
-    // stochastic rounding in the stores.
-    template <bool FIX, bool CD, bool PLAIN>
+    // so neither term is formed.  Stores (ST): STORE_PLAIN, no Runge-Kutta
+    // combination and round-to-nearest; STORE_SR, no Runge-Kutta combination
+    // and stochastic rounding to BF16 with the draws shared by lane pairs
+    // (sr_pair); STORE_ANY, every other case, through the general store.
+    template <bool FIX, bool CD, int ST>
     __device__ __forceinline__ void update(int r0, int z, const RD_LDS T* PC, const RD_LDS T* PAB,
                                            const float (&cm)[3][RY][2], const float (&c0)[3][RY][2],
                                            const float (&cp)[3][RY][2], RD_GLOBAL T* const (&po)[3][RY],
-                                           const bool (&rowst)[RY]) const {
+                                           const bool (&rowst)[RY], const unsigned (&pc)[RY],
+                                           unsigned srn, unsigned srk) const {
         constexpr int NF = CD ? 3 : 2;               // fields with a Laplacian of their own
         const int hlo = hl_off();
         const int zm = max(z - 1, 0), zp = min(z + 1, a.nz - 1);
@@ -581,8 +585,17 @@ struct FchConsumer {
 #pragma unroll
                 for (int s = 0; s < 3; ++s) o[s][i] = FIX ? held_out(a, s, xl + i, y, z, oi[s]) : oi[s];
             }
-            if (rowst[r]) {
-                if constexpr (PLAIN) {
+            if constexpr (ST == STORE_SR) {
+                unsigned wd[3];
+                sr_pair(pc[r], srn, srk, wd);
+                if (rowst[r]) {
+#pragma unroll
+                    for (int s = 0; s < 3; ++s)
+                        *(RD_GLOBAL unsigned*)po[s][r] = unsigned(bf16_stochastic(o[s][0], wd[s] & 0xffffu)) |
+                                                        (unsigned(bf16_stochastic(o[s][1], wd[s] >> 16)) << 16);
+                }
+            } else if (rowst[r]) {
+                if constexpr (ST == STORE_PLAIN) {
 #pragma unroll
                     for (int s = 0; s < 3; ++s) store_vec_at<S, 2>(po[s][r], o[s]);
                 } else {
@@ -593,8 +606,28 @@ struct FchConsumer {
         }
     }
 
+    // Random words of the lane's two cells for species 0, 1, 2 (bits 0-15 for
+    // the first cell, 16-31 for the second), as the general store draws them:
+    // the cells of a lane pair (four in a row, the first at a multiple of four
+    // in the dense index) share counter c, and species s takes the call with
+    // key srk + s, the even lane its first word, the odd lane its second.  The
+    // even lane makes the species-0 call and the odd lane the species-1 call,
+    // each passing the word the other needs across the pair; both make the
+    // species-2 call: two calls per lane instead of three.
+    __device__ __forceinline__ void sr_pair(unsigned c, unsigned srn, unsigned srk, unsigned (&wd)[3]) const {
+        const bool odd = (threadIdx.x & 1) != 0;
+        const PhiloxOut r01 = philox2x32_10(c, srn, srk + (odd ? 1u : 0u));
+        const PhiloxOut r2 = philox2x32_10(c, srn, srk + 2u);
+        const unsigned send = odd ? r01.w0 : r01.w1;
+        // quad_perm [1, 0, 3, 2]: lanes 2i and 2i+1 exchange
+        const unsigned recv = unsigned(__builtin_amdgcn_mov_dpp(int(send), 0xB1, 0xF, 0xF, false));
+        wd[0] = odd ? recv : r01.w0;
+        wd[1] = odd ? r01.w1 : recv;
+        wd[2] = odd ? r2.w1 : r2.w0;
+    }
+
     // one update wave (index uw) over the z range: planes z0 .. z1-1
-    template <bool CD, bool PLAIN>
+    template <bool CD, int ST>
     __device__ __forceinline__ void run_update(int uw, int z0, int z1) const {
         const int r0 = uw * RY;
         bool wfix = false;
@@ -615,6 +648,15 @@ struct FchConsumer {
         // update, and whether this lane stores there
         RD_GLOBAL T* po[3][RY];
         bool rowst[RY];
+        // stochastic rounding: the counter of the lane pair's cells on plane
+        // z0 (dense index / 4, modulo 2^32), the step and the key of species 0
+        unsigned pc[RY];
+        unsigned srn = 0, srk = 0;
+        const unsigned dpc = unsigned((unsigned long long)unsigned(a.nx) * unsigned(a.ny) >> 2);
+        if constexpr (ST == STORE_SR) {
+            srn = unsigned(cload_ptr<StepClock>(a.clk_in)->n);
+            srk = a.sr_key + unsigned(a.sp0);
+        }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int y = yb + r0 + r;
@@ -622,6 +664,8 @@ struct FchConsumer {
 #pragma unroll
             for (int s = 0; s < 3; ++s)
                 po[s][r] = gstore_ptr<T>(a.out[s]) + ((long long)z0 * a.plane + (long long)y * a.pitch + xl);
+            pc[r] = unsigned((((unsigned long long)unsigned(z0) * unsigned(a.ny) + unsigned(y)) * unsigned(a.nx) +
+                              unsigned(xl)) >> 2);
         }
         // planes q-1 .. q+1 take no z rule unless q <= 1 or q >= nz - 2
         const int q_hi = a.nz - 2;
@@ -641,13 +685,15 @@ struct FchConsumer {
                 const RD_LDS T* PC = cslot(sc);
                 const RD_LDS T* PAB = abslot(sab);
                 if (wfix || q <= 1 || q >= q_hi)
-                    update<true, CD, PLAIN>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst);
+                    update<true, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, srn, srk);
                 else
-                    update<false, CD, PLAIN>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst);
+                    update<false, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, srn, srk);
 #pragma unroll
-                for (int s = 0; s < 3; ++s)
+                for (int r = 0; r < RY; ++r) {
 #pragma unroll
-                    for (int r = 0; r < RY; ++r) po[s][r] += a.plane;
+                    for (int s = 0; s < 3; ++s) po[s][r] += a.plane;
+                    pc[r] += dpc;
+                }
             }
 #pragma unroll
             for (int f = 0; f < 3; ++f)
@@ -670,13 +716,23 @@ struct FchConsumer {
         }
         const bool cd = a.kx[2] != 0.f || a.ky[2] != 0.f || a.kz[2] != 0.f || a.p[5] != 0.f;
         const bool plain = a.rk_w == 0.f && !a.sr;
+        // lane pairs start at multiples of four in the dense index when the
+        // rows are a multiple of four long (x tiles start at multiples of 128)
+        const bool srp = std::is_same_v<S, StBF16> && a.rk_w == 0.f && a.sr && (a.nx & 3) == 0;
         if (cd) {
-            if (plain) run_update<true, true>(cw, z0, z1);
-            else run_update<true, false>(cw, z0, z1);
+            if (plain) run_update<true, STORE_PLAIN>(cw, z0, z1);
+            else if (srp) run_sr<true>(cw, z0, z1);
+            else run_update<true, STORE_ANY>(cw, z0, z1);
         } else {
-            if (plain) run_update<false, true>(cw, z0, z1);
-            else run_update<false, false>(cw, z0, z1);
+            if (plain) run_update<false, STORE_PLAIN>(cw, z0, z1);
+            else if (srp) run_sr<false>(cw, z0, z1);
+            else run_update<false, STORE_ANY>(cw, z0, z1);
         }
+    }
+
+    template <bool CD>
+    __device__ __forceinline__ void run_sr(int cw, int z0, int z1) const {
+        if constexpr (std::is_same_v<S, StBF16>) run_update<CD, STORE_SR>(cw, z0, z1);
     }
 };
 

@@ -161,7 +161,7 @@ hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs&
 // workgroup, computing waves, ring slots, z planes per tile).
 struct BatchTrCfg { int by, wc, d, cz; };
 constexpr BatchTrCfg kBatchTr = {8, 8, 6, 32};
-hipError_t launch_batched(int storage, const int* meta, const BatchEntry* ents, int step, int blocks,
+hipError_t launch_batched(int storage, int* meta, const BatchEntry* ents, int step, int blocks,
                           hipStream_t s);
 int batched_blocks_per_cu(int storage);
 
@@ -187,9 +187,9 @@ RD_DECLARE_GROUP(f16_poll)
 RD_DECLARE_GROUP(f16_atmos)
 #undef RD_DECLARE_GROUP
 
-hipError_t launch_batched_f32(const int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
-hipError_t launch_batched_bf16(const int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
-hipError_t launch_batched_f16(const int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
+hipError_t launch_batched_f32(int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
+hipError_t launch_batched_bf16(int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
+hipError_t launch_batched_f16(int* meta, const BatchEntry* ents, int step, int blocks, hipStream_t s);
 int batched_blocks_per_cu_f32();
 int batched_blocks_per_cu_bf16();
 int batched_blocks_per_cu_f16();

@@ -196,7 +196,7 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 
 #ifdef RD_WITH_BATCH
 #define RD_BATCH_KERNEL batched_tr_kernel<S, kBatchTr.by, kBatchTr.wc, kBatchTr.d>
-hipError_t RD_BATCH_FN(launch_batched)(const int* meta, const BatchEntry* ents, int step, int blocks,
+hipError_t RD_BATCH_FN(launch_batched)(int* meta, const BatchEntry* ents, int step, int blocks,
                                        hipStream_t s) {
     hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * (1 + kBatchTr.wc)), 0, s, meta, ents, step);
     return hipGetLastError();

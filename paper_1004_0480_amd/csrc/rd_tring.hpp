@@ -456,20 +456,31 @@ __global__ __launch_bounds__(64 * (1 + WC)) void tr_kernel(const StepArgs* __res
 // Euler, round-to-nearest stores): a persistent launch walks the batch's
 // (grid, tile) items, each item a tile of 128-cell rows marching a z chunk
 // of its grid.  The host writes the table (rd_device.hpp, BatchEntry) with
-// each grid's arguments tiled for this kernel.
+// each grid's arguments tiled for this kernel, largest items first.
+// Workgroups claim items from a ticket counter, so the step ends when the
+// last item does however unequal the items are; the last workgroup to finish
+// puts both counters back to zero for the next launch.
 template <class S, int BY, int WC, int DR>
-__global__ __launch_bounds__(64 * (1 + WC)) void batched_tr_kernel(const int* __restrict__ meta,
+__global__ __launch_bounds__(64 * (1 + WC)) void batched_tr_kernel(int* __restrict__ meta,
                                                                     const BatchEntry* __restrict__ ents, int step) {
     // one ring serves both models (sized for the Brusselator's two fields)
     using RB = Tr<Brusselator, S, BY, DR>;
     static_assert(Tr<Diffusion<1>, S, BY, DR>::SLOT_W <= RB::SLOT_W, "batch ring");
     __shared__ __attribute__((aligned(16))) float ring[DR * RB::SLOT_W];
+    __shared__ int claimed;
     const int ng = meta[0];
     const int total = meta[1];
-    const int* first = meta + 2;
+    int* ticket = meta + 2;
+    int* finished = meta + 3;
+    const int* first = meta + 4;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     RD_LDS float* rg = (RD_LDS float*)&ring[0];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    for (;;) {
+        if (threadIdx.x == 0) claimed = atomicAdd(ticket, 1);
+        __syncthreads();
+        const int item = claimed;
+        __syncthreads();                         // every wave has read it
+        if (item >= total) break;
         int lo = 0, hi = ng - 1;                 // last grid with first_item <= item
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -483,6 +494,14 @@ __global__ __launch_bounds__(64 * (1 + WC)) void batched_tr_kernel(const int* __
         if (en.model == 1) tr_run<Brusselator, S, BY, WC, DR, true>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
         else tr_run<Diffusion<1>, S, BY, WC, DR, true>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
         __syncthreads();                         // the next item refills the ring
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();                         // this workgroup's claims come first
+        if (atomicAdd(finished, 1) == int(gridDim.x) - 1) {
+            __threadfence();                     // after every other workgroup's claims
+            atomicExch(ticket, 0);
+            atomicExch(finished, 0);
+        }
     }
 }
 

@@ -921,6 +921,37 @@ def test_batched_results_equal_alone():
     b.close()
 
 
+def test_batched_many_items_equal_alone():
+    """More work items than the persistent launch has workgroups (128^3 grids
+    of 64 tiles each, mixed with small ones), so workgroups claim several
+    items per step and the claim counters are reused across launches and
+    ticks: every grid still matches the same grid stepped alone."""
+    import torch
+    stream = torch.cuda.Stream()
+    reqs = [W.Request(i, 0, e, m, st, 100 + i) for i, (e, m, st) in enumerate(
+        [(128, "brusselator", 9), (128, "diffusion", 6), (128, "brusselator", 7), (128, "diffusion", 9),
+         (128, "brusselator", 5), (128, "diffusion", 8), (96, "brusselator", 9), (96, "diffusion", 4),
+         (96, "brusselator", 6), (32, "diffusion", 9), (32, "brusselator", 3), (48, "diffusion", 7),
+         (64, "brusselator", 8)])]
+    ws = [W.request_workload(r) for r in reqs]
+    b = rd.Batch(16, 1 << 34, "f32", stream=stream)
+    grids = []
+    for r, w in zip(reqs, ws):
+        g = rd.Grid.from_workload(w, stream=stream)
+        b.add(g, r.steps)
+        grids.append(g)
+    finished = []
+    while len(finished) < len(grids):
+        finished += b.step(4)
+    for r, w, g in zip(reqs, ws, grids):
+        alone, _ = gpu_run(w, r.steps)
+        got = g.read_all()
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], alone[s]), (r, s)
+        g.close()
+    b.close()
+
+
 def test_batch_budget_and_validation():
     import torch
     stream = torch.cuda.Stream()

@@ -117,6 +117,36 @@ def test_stochastic_plans_graphs_and_repeats():
         assert rel_l2(base[s], ref[s]) <= 1e-2
 
 
+@pytest.mark.parametrize("shape", [(6, 10, 256), (5, 9, 200), (5, 6, 130)])
+def test_stochastic_front_every_plan_same_bits(shape):
+    """Three-species front model with stochastic BF16 stores: the one-pass
+    kernel (whose lane pairs share the generator's calls when the rows are a
+    multiple of four long) stores the same bits as every other plan, which
+    store through the general per-cell draw."""
+    w = W.make_workload("front384", shape=shape)
+    steps = 3
+
+    def run(plan=None):
+        g = rd.Grid(w.shape, 3, w.spec.h, "bf16")
+        g.set_model(w.spec)
+        g.set_rounding("stochastic", 11)
+        if plan:
+            g.set_plan(**plan)
+        for s in range(3):
+            g.write(s, w.fields[s])
+        g.step(steps)
+        out = g.read_all()
+        g.close()
+        return out
+
+    base = run(dict(kernel="direct"))
+    plans = compiled_plans(w, storage="bf16", czs=(0, 4))
+    assert any(p["kernel"] == "fused" for p in plans)
+    for plan in plans:
+        got = run(plan)
+        assert all(np.array_equal(a, b) for a, b in zip(got, base)), plan
+
+
 def test_stochastic_rounding_refusals():
     import torch
     shape = (8, 8, 64)
