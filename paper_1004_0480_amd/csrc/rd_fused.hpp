@@ -434,7 +434,9 @@ struct FchConsumer {
         // p-1 .. p+1 take no z rule unless p <= 1 or p >= nz - 2
         const int q_last = min(a.nz - 1, z1) - 2, p_hi = a.nz - 2;
         int sq = DC - 1;                  // C slot of plane q (plane z0-2 is slot 0)
-        for (int q = z0 - 3; q < z1; ++q) {
+        // one plane: FX false compiles only the rule-free forms
+        auto plane = [&](int q, auto fx) __attribute__((always_inline)) {
+            constexpr bool FX = decltype(fx)::value;
             lds_done();
             ring_barrier();
             const int s1 = sq + 1 == DC ? 0 : sq + 1, s2 = s1 + 1 == DC ? 0 : s1 + 1, s3 = s2 + 1 == DC ? 0 : s2 + 1;
@@ -452,7 +454,7 @@ struct FchConsumer {
                 __builtin_amdgcn_sched_barrier(0);
                 v2f mu[MPW];
                 float mue = 0.f;
-                if (wfix || p <= 1 || p >= p_hi) {
+                if (FX && (wfix || p <= 1 || p >= p_hi)) {
 #pragma unroll
                     for (int i = 0; i < MPW; ++i) mu[i] = mu_cells<true>(p, mrows[i], in[i]);
                     if (columns) mue = col_cell<true>(p, cat, cin, rmirror, rval);
@@ -467,7 +469,13 @@ struct FchConsumer {
                 if (columns && cat.want) mrow(p, cat.m)[(lane & 1) ? TX + 2 : 1] = mue;
             }
             sq = s1;
-        }
+        };
+        // mu planes 2 .. nz-3 (q = p - 2) take the rule-free forms unless the
+        // wave has fixed rows
+        const int qa = z0 - 3, qb = wfix ? qa : max(qa, min(z1, 0)), qc = wfix ? qa : max(qb, min(z1, p_hi - 2));
+        for (int q = qa; q < qb; ++q) plane(q, std::true_type{});
+        for (int q = qb; q < qc; ++q) plane(q, std::false_type{});
+        for (int q = qc; q < z1; ++q) plane(q, std::true_type{});
     }
 
     // ---- update of A, B, C -------------------------------------------------
@@ -671,20 +679,23 @@ struct FchConsumer {
         const int q_hi = a.nz - 2;
         int sc = DC - 1;                  // C slot of plane q (plane z0-2 is slot 0)
         int sab = DAB - 2;                // A/B slot of plane q (plane z0-1 is slot 0)
-        for (int q = z0 - 3; q < z1; ++q) {
+        // one plane: FX false compiles only the rule-free forms (planes two or
+        // more inside the z faces of a wave with no fixed rows)
+        auto plane = [&](int q, auto fx) __attribute__((always_inline)) {
+            constexpr bool FX = decltype(fx)::value;
             lds_done();
             ring_barrier();
             const int sc1 = sc + 1 == DC ? 0 : sc + 1, sab1 = sab + 1 == DAB ? 0 : sab + 1;
             // centre rows of plane q+1
             if (q >= z0 - 2) {
-                if (wfix || q <= -1 || q >= q_hi) centre<true>(r0, q + 1, cslot(sc1), abslot(sab1), cen[2]);
+                if (FX && (wfix || q <= -1 || q >= q_hi)) centre<true>(r0, q + 1, cslot(sc1), abslot(sab1), cen[2]);
                 else centre<false>(r0, q + 1, cslot(sc1), abslot(sab1), cen[2]);
             }
             // update plane q
             if (q >= z0) {
                 const RD_LDS T* PC = cslot(sc);
                 const RD_LDS T* PAB = abslot(sab);
-                if (wfix || q <= 1 || q >= q_hi)
+                if (FX && (wfix || q <= 1 || q >= q_hi))
                     update<true, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, srn, srk);
                 else
                     update<false, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, srn, srk);
@@ -706,7 +717,12 @@ struct FchConsumer {
                     }
             sc = sc1;
             sab = sab1;
-        }
+        };
+        // planes 2 .. nz-3 take the rule-free forms unless the wave has fixed rows
+        const int qa = z0 - 3, qb = wfix ? qa : max(qa, min(z1, 2)), qc = wfix ? qa : max(qb, min(z1, q_hi));
+        for (int q = qa; q < qb; ++q) plane(q, std::true_type{});
+        for (int q = qb; q < qc; ++q) plane(q, std::false_type{});
+        for (int q = qc; q < z1; ++q) plane(q, std::true_type{});
     }
 
     __device__ __forceinline__ void run(int cw, int z0, int z1) const {
