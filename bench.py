@@ -342,7 +342,7 @@ def serve_bench(args):
             ex = S.GpuExecutor(storage, max_resident=args.max_resident, hbm_budget=args.hbm_budget)
             print("bench: serve %s %s (%d requests)" % (storage, phase, len(trace)),
                   file=sys.stderr, flush=True)
-            rep = S.serve(trace, arr, ex, args.max_resident, args.hbm_budget, args.chunk)
+            rep = S.serve(trace, arr, ex, args.max_resident, args.hbm_budget, args.chunk, min_run=args.min_run)
             ex.close()
             torch.cuda.synchronize()
             summ = rep.summary()
@@ -356,7 +356,8 @@ def serve_bench(args):
                 "config": {"workload": "served batch", "requests": len(trace),
                            "edges": list(W.SERVE_EDGES), "steps": [200, 2000],
                            "max_resident": args.max_resident, "hbm_budget": args.hbm_budget,
-                           "chunk": args.chunk, "arrival_rate": "0.8 x measured capacity"}})
+                           "chunk": args.chunk, "min_run": args.min_run,
+                           "arrival_rate": "0.8 x measured capacity"}})
     print(json.dumps(out), flush=True)
 
 
@@ -379,6 +380,8 @@ def main():
     ap.add_argument("--max-resident", type=int, default=256)
     ap.add_argument("--hbm-budget", type=int, default=16 << 30)
     ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--min-run", type=int, default=1,
+                    help="served batch: steps a tick runs at least (finished grids sit out the rest)")
     ap.add_argument("--graph-chunk", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0,

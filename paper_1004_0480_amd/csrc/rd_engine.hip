@@ -17,6 +17,7 @@
 #define RD_DEFINE_ENGINE_KERNELS
 #include "rd_fch_cfg.hpp"
 #include "rd_tring_cfg.hpp"
+#include "rd_batch_cfg.hpp"
 #include "rd_internal.hpp"
 
 using namespace rdk;

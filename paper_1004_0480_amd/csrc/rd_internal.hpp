@@ -156,15 +156,8 @@ int block_cfg_index(int vx, int ry, int w, int cz);  // -1 if no such shape
 hipError_t launch_pass(int storage, int pm, int kernel, int cfg, const StepArgs& h,
                        const StepArgs* d, long long blocks, hipStream_t s);
 
-// Batched persistent kernel: one step of every table entry whose steps_left >
-// step, each grid tiled for the tiled LDS ring with this shape (rows per
-// workgroup, computing waves, ring slots, z planes per tile).  Two rows per
-// computing wave: the per-plane chain of loads, barrier and arithmetic is
-// what bounds the ring on these small grids, and it is shared by twice the
-// cells (16-row tiles also re-read fewer halo rows), at one workgroup per CU
-// (8-row tiles at two per CU stepped the same 256-grid batch 1.5x slower).
-struct BatchTrCfg { int by, wc, d, cz; };
-constexpr BatchTrCfg kBatchTr = {16, 8, 5, 32};
+// Batched persistent kernel (shape: rd_batch_cfg.hpp): one step of every
+// table entry whose steps_left > step.
 hipError_t launch_batched(int storage, int* meta, const BatchEntry* ents, int step, int blocks,
                           hipStream_t s);
 int batched_blocks_per_cu(int storage);

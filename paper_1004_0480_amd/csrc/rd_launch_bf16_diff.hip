@@ -5,4 +5,5 @@
 #define RD_FN(name) name##_bf16_diff
 #define RD_WITH_BATCH
 #define RD_BATCH_FN(name) name##_bf16
+#include "rd_batch_cfg.hpp"
 #include "rd_launch_impl.hpp"

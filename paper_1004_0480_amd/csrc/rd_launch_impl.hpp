@@ -195,17 +195,17 @@ hipError_t RD_FN(launch_pass)(int pm, int kernel, int cfg, const StepArgs& h, co
 }
 
 #ifdef RD_WITH_BATCH
-#define RD_BATCH_KERNEL batched_tr_kernel<S, kBatchTr.by, kBatchTr.wc, kBatchTr.d>
+#define RD_BATCH_KERNEL batched_tr_kernel<S, kBatchTr.by, kBatchTr.wc, kBatchTr.d, kBatchTr.np>
 hipError_t RD_BATCH_FN(launch_batched)(int* meta, const BatchEntry* ents, int step, int blocks,
                                        hipStream_t s) {
-    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * (1 + kBatchTr.wc)), 0, s, meta, ents, step);
+    hipLaunchKernelGGL((RD_BATCH_KERNEL), dim3(blocks), dim3(64 * (kBatchTr.np + kBatchTr.wc)), 0, s, meta, ents, step);
     return hipGetLastError();
 }
 
 int RD_BATCH_FN(batched_blocks_per_cu)() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&RD_BATCH_KERNEL),
-                                                     64 * (1 + kBatchTr.wc), 0) != hipSuccess)
+                                                     64 * (kBatchTr.np + kBatchTr.wc), 0) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }

@@ -57,7 +57,13 @@ __host__ __device__ constexpr int tr_q_end(int z0, int z1) { return z0 - 3 + ((z
 // (its centre rows), so step k must have landed before barrier z0-3+k; after
 // barrier q the slot of plane q (last read at iteration q-1) is free and
 // takes step q+DR+1-z0, which leaves DR-3 steps in flight.
-template <class M, class S, int BY, int DR>
+//
+// With NP producer waves, wave P loads (and patches) the ring rows
+// i = f*RR + j (field f, row j) with i mod NP = P.  A wave counts its own
+// loads only and can wait on at most 63 of them, so a step of many rows
+// (16-row tiles of two fields: 36 loads) keeps more steps in flight when its
+// rows are shared between two waves.
+template <class M, class S, int BY, int DR, int NP = 1, int P = 0>
 __device__ __forceinline__ void tr_producer(const StepArgs& a, RD_LDS float* ring, int x0, int yb, int z0,
                                             int z1) {
 #ifndef __HIP_DEVICE_COMPILE__
@@ -115,7 +121,7 @@ __device__ __forceinline__ void tr_producer(const StepArgs& a, RD_LDS float* rin
                 const RD_GLOBAL char* base = plane_of(f, z0 - 1 + k);
 #pragma unroll
                 for (int j = 0; j < R::RR; ++j)
-                    if (act[f])
+                    if ((f * R::RR + j) % NP == P && act[f])
                         __builtin_amdgcn_global_load_lds((const RD_GLOBAL void*)(base + off[f][j]),
                                                          (RD_LDS void*)(sl + (f * R::RR + j) * R::RW), 16, 0, 0);
             }
@@ -133,7 +139,7 @@ __device__ __forceinline__ void tr_producer(const StepArgs& a, RD_LDS float* rin
         // one field at a time, so that its face rule is a scalar
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            if (k > last || lane >= R::RR) continue;
+            if (k > last || lane >= R::RR || (f * R::RR + lane) % NP != P) continue;
             RD_LDS T* r = (RD_LDS T*)(ring + pslot * R::SLOT_W) + (f * R::RR + lane) * R::RW;
             if (lface) {
                 const int kl = a.bck[f][0];
@@ -151,7 +157,7 @@ __device__ __forceinline__ void tr_producer(const StepArgs& a, RD_LDS float* rin
         pslot = pslot + 1 == DR ? 0 : pslot + 1;
     };
     for (int k = 0; k < DR - 2; ++k) issue(k);
-    constexpr int PER = NF * R::RR;                // loads per step
+    constexpr int PER = (NF * R::RR - P + NP - 1) / NP;   // this wave's loads per step
     constexpr int STEADY = (DR - 3) * PER < 63 ? (DR - 3) * PER : 63;
     for (int q = z0 - 3; q < tr_q_end(z0, z1); ++q) {
         // step q+3-z0 complete: the steps issued after it may stay in flight
@@ -429,11 +435,14 @@ struct TrConsumer {
     }
 };
 
-// One workgroup's march over its tile (wave w: 0 loads, the others compute).
-template <class M, class S, int BY, int WC, int DR, bool PLAIN>
+// One workgroup's march over its tile (waves 0 .. NP-1 load, the others
+// compute).
+template <class M, class S, int BY, int WC, int DR, bool PLAIN, int NP = 1>
 __device__ __forceinline__ void tr_run(const StepArgs& a, RD_LDS float* rg, int w, int x0, int yb, int z0, int z1) {
-    if (w == 0) tr_producer<M, S, BY, DR>(a, rg, x0, yb, z0, z1);
-    else TrConsumer<M, S, BY, WC, DR>(a, rg, x0, yb).template run<PLAIN>(w - 1, z0, z1);
+    static_assert(NP == 1 || NP == 2, "one or two producer waves");
+    if (w == 0) tr_producer<M, S, BY, DR, NP, 0>(a, rg, x0, yb, z0, z1);
+    else if (NP == 2 && w == 1) tr_producer<M, S, BY, DR, NP, NP - 1>(a, rg, x0, yb, z0, z1);
+    else TrConsumer<M, S, BY, WC, DR>(a, rg, x0, yb).template run<PLAIN>(w - NP, z0, z1);
 }
 
 // PLAIN: the launch has no Runge-Kutta combination and no stochastic
@@ -460,8 +469,8 @@ __global__ __launch_bounds__(64 * (1 + WC)) void tr_kernel(const StepArgs* __res
 // Workgroups claim items from a ticket counter, so the step ends when the
 // last item does however unequal the items are; the last workgroup to finish
 // puts both counters back to zero for the next launch.
-template <class S, int BY, int WC, int DR>
-__global__ __launch_bounds__(64 * (1 + WC)) void batched_tr_kernel(int* __restrict__ meta,
+template <class S, int BY, int WC, int DR, int NP>
+__global__ __launch_bounds__(64 * (NP + WC)) void batched_tr_kernel(int* __restrict__ meta,
                                                                     const BatchEntry* __restrict__ ents, int step) {
     // one ring serves both models (sized for the Brusselator's two fields)
     using RB = Tr<Brusselator, S, BY, DR>;
@@ -491,8 +500,8 @@ __global__ __launch_bounds__(64 * (1 + WC)) void batched_tr_kernel(int* __restri
         const StepArgs& a = en.args[(en.parity + step) & 1];
         const TileXYZ tc = tile_coords(a, item - first[lo]);
         const int z0 = tc.z * a.cz, z1 = min(z0 + a.cz, a.nz);
-        if (en.model == 1) tr_run<Brusselator, S, BY, WC, DR, true>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
-        else tr_run<Diffusion<1>, S, BY, WC, DR, true>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
+        if (en.model == 1) tr_run<Brusselator, S, BY, WC, DR, true, NP>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
+        else tr_run<Diffusion<1>, S, BY, WC, DR, true, NP>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
         __syncthreads();                         // the next item refills the ring
     }
     if (threadIdx.x == 0) {

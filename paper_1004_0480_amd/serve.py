@@ -7,6 +7,11 @@ all resident grids together, ``chunk`` steps per tick, through one executor
 call; grids that finish leave the batch, their result is read back, and the
 freed slots and memory admit newly arrived requests at the next tick.
 
+The host keeps one tick in flight: it launches tick k+1 (admitting what
+arrived meanwhile) before it waits for tick k, so the device does not idle
+while the host does the bookkeeping between ticks; requests that finished in
+tick k complete when the host sees tick k's end.
+
 The scheduler is independent of the executor: ``GpuExecutor`` drives the
 library's batched persistent kernel (``rd_batch_*``); ``SimulatedExecutor``
 models step durations with a cost model on a virtual clock, so the
@@ -94,9 +99,12 @@ class VirtualClock(Clock):
 
 def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident: int,
           hbm_budget: int, chunk: int, clock: Optional[Clock] = None,
-          keep_results: bool = False) -> ServeReport:
+          keep_results: bool = False, min_run: int = 1) -> ServeReport:
     """Run the continuous-batching loop over ``requests`` arriving at
-    ``arrivals`` (seconds after start, non-decreasing)."""
+    ``arrivals`` (seconds after start, non-decreasing).  A tick runs up to
+    ``chunk`` steps and stops at the earliest finisher, but runs at least
+    ``min_run`` steps: grids that finish inside a tick sit out its remaining
+    steps (the batched launch skips them), in exchange for fewer ticks."""
     clock = clock or Clock()
     order = sorted(range(len(requests)), key=lambda i: arrivals[i])
     pending = deque(order)
@@ -110,7 +118,21 @@ def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident:
     peak_res = 0
     peak_bytes = 0
     rejected = 0
-    while pending or resident:
+    inflight = None                     # (tick token, [(rec, handle, output)]) launched, not yet seen done
+
+    def complete(tick):
+        nonlocal busy
+        token, recs = tick
+        busy += executor.wait(token)
+        t_fin = clock.now() - t0
+        for rec, out in recs:
+            req = requests[rec["i"]]
+            done.append(Completion(rec["i"], float(arrivals[rec["i"]]), rec["admitted"], t_fin,
+                                   executor.cells(req), int(req.steps)))
+            if keep_results:
+                results[rec["i"]] = out
+
+    while pending or resident or inflight:
         now = clock.now() - t0
         # admission in arrival order, by slot and footprint
         while pending and arrivals[pending[0]] <= now:
@@ -129,37 +151,37 @@ def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident:
             bytes_in_use += need
         peak_res = max(peak_res, len(resident))
         peak_bytes = max(peak_bytes, bytes_in_use)
-        if not resident:
-            if pending:
-                clock.sleep_until(t0 + arrivals[pending[0]])
-            continue
-        # one tick: advance every resident grid by up to `run` steps; `run`
-        # stops at the earliest finisher so no grid idles in the batch
-        run = min(chunk, min(r["left"] for r in resident.values()))
-        t_start = clock.now()
-        finished = executor.step(run)
-        for h in finished:
-            rec = resident.pop(h)
-            out = executor.collect(h, keep_results)
-            t_fin = clock.now() - t0
-            req = requests[rec["i"]]
-            done.append(Completion(rec["i"], float(arrivals[rec["i"]]), rec["admitted"], t_fin,
-                                   executor.cells(req), int(req.steps)))
-            if keep_results:
-                results[rec["i"]] = out
-            bytes_in_use -= rec["bytes"]
-        for r in resident.values():
-            r["left"] -= run
-        executor.sync()
-        busy += clock.now() - t_start
-        ticks += 1
+        launched = None
+        if resident:
+            # one tick: advance every resident grid by up to `run` steps; `run`
+            # stops at the earliest finisher so no grid idles in the batch
+            run = min(chunk, max(min_run, min(r["left"] for r in resident.values())))
+            finished = executor.step(run)
+            token = executor.mark()
+            recs = []
+            for h in finished:
+                rec = resident.pop(h)
+                recs.append((rec, executor.collect(h, keep_results)))
+                bytes_in_use -= rec["bytes"]
+            for r in resident.values():
+                r["left"] -= run
+                assert r["left"] > 0, "the executor did not report a finished grid"
+            ticks += 1
+            launched = (token, recs)
+        if inflight:
+            complete(inflight)
+        inflight = launched
+        if not resident and not inflight and pending:
+            clock.sleep_until(t0 + arrivals[pending[0]])
     makespan = clock.now() - t0
     return ServeReport(done, makespan, busy, ticks, peak_res, peak_bytes, rejected, results)
 
 
 class SimulatedExecutor:
     """Cost-model executor on a virtual clock: a tick of `run` steps over the
-    resident grids takes launch_s + run * (cells_resident / rate) seconds."""
+    resident grids takes launch_s + run * (cells_resident / rate) seconds of
+    device time; ticks queue on the device in launch order, and waiting for
+    one advances the clock to its end."""
 
     def __init__(self, clock: VirtualClock, rate_cells_per_s: float = 3e11, launch_s: float = 2e-5,
                  bytes_per_cell: int = 8):
@@ -169,6 +191,7 @@ class SimulatedExecutor:
         self.bpc = bytes_per_cell
         self.live: Dict[int, dict] = {}
         self.next = 0
+        self.free_at = 0.0              # when the device finishes its queued ticks
 
     def cells(self, req) -> int:
         return req.edge ** 3
@@ -185,7 +208,9 @@ class SimulatedExecutor:
 
     def step(self, run: int) -> List[int]:
         cells = sum(self.cells(v["req"]) for v in self.live.values())
-        self.clock.advance(self.launch + run * cells / self.rate)
+        cost = self.launch + run * cells / self.rate
+        self.free_at = max(self.free_at, self.clock.now()) + cost
+        self.last = (self.free_at, cost)
         fin = []
         for h, v in list(self.live.items()):
             v["left"] -= min(run, v["left"])
@@ -197,8 +222,14 @@ class SimulatedExecutor:
         self.live.pop(h)
         return None
 
-    def sync(self):
-        pass
+    def mark(self):
+        """Token of the tick just launched: (end time, device time)."""
+        return self.last
+
+    def wait(self, token) -> float:
+        end, cost = token
+        self.clock.sleep_until(end)
+        return cost
 
 
 class GpuExecutor:
@@ -246,18 +277,28 @@ class GpuExecutor:
         return h
 
     def step(self, run: int) -> List[int]:
+        self._start = self.torch.cuda.Event(enable_timing=True)
+        self._start.record(self.stream)
         return [g.handle.value for g in self.batch.step(run)]
 
+    def mark(self):
+        """Events around the tick just launched on the executor's stream."""
+        end = self.torch.cuda.Event(enable_timing=True)
+        end.record(self.stream)
+        return (self._start, end)
+
+    def wait(self, token) -> float:
+        """Block until the tick has run; its device time in seconds."""
+        start, end = token
+        end.synchronize()
+        return start.elapsed_time(end) * 1e-3
+
     def collect(self, h: int, keep: bool):
+        # a pooled grid is reused on the same stream, after this tick's launch
         g = self.grid_of.pop(h)
         out = g.read_all(np.float32) if keep else None
-        if not keep:
-            g.sync()
         self.pool[self.by_handle.pop(h)].append(g)
         return out
-
-    def sync(self):
-        self.stream.synchronize()
 
     def close(self):
         self.batch.close()

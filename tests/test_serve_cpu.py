@@ -80,6 +80,20 @@ def test_ticks_stop_at_the_earliest_finisher():
     assert rep.ticks == 2
 
 
+def test_minimum_tick_length_merges_close_finishers():
+    """With min_run, grids that finish within a few steps of each other leave
+    in one tick (they sit out its remaining steps); every request still
+    completes exactly once."""
+    tr = [W.Request(i, 0, 32, "diffusion", st, i) for i, st in enumerate([20, 22, 24, 26, 100])]
+    clock = S.VirtualClock()
+    ex = S.SimulatedExecutor(clock)
+    rep = S.serve(tr, np.zeros(len(tr)), ex, 64, 1 << 40, 50, clock=clock, min_run=8)
+    assert rep.ticks == 4                       # 20, 8 (three finish), 50, 22
+    assert sorted(c.rid for c in rep.completions) == list(range(len(tr)))
+    rep1, _ = run(tr, np.zeros(len(tr)))
+    assert rep1.ticks == 6                      # 20, 2, 2, 2, 50, 22
+
+
 def test_trace_statistics():
     tr = W.make_trace(4096, seed=4)
     edges = np.array([r.edge for r in tr])
