@@ -239,8 +239,14 @@ int rd_set_model(rd_grid *g, const rd_model_desc *m);
 
 /* Copy one species' field into the current state (Table 3 line 2).
  * src is dense [nz][ny][nx] of src_dtype (RD_F32/RD_F64/RD_BF16/RD_F16),
- * on the host (src_on_device = 0) or the device (1); values are converted to
- * the storage type with round-to-nearest-even.  Synchronous. */
+ * on the host (src_on_device = 0) or the device (1 or 2); values are
+ * converted to the storage type with round-to-nearest-even.  0 and 1 are
+ * synchronous.  2 only enqueues the copy on the grid's stream and returns:
+ * the caller keeps src alive and unchanged until the stream has passed that
+ * point, and must have ordered src's own producer before it (for a serving
+ * loop that builds initial states on the grid's stream while earlier steps
+ * still run).  Errors of an enqueued copy surface at the next synchronizing
+ * call. */
 int rd_write_field(rd_grid *g, int32_t species, const void *src, int32_t src_dtype,
                    int32_t src_on_device);
 

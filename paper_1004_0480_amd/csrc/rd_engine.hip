@@ -1139,10 +1139,12 @@ extern "C" int rd_write_field(rd_grid* g, int32_t species, const void* src, int3
     if (!g || !src) return fail(RD_EINVAL, "NULL argument");
     if (species < 0 || species >= g->ns) return fail(RD_EINVAL, "species out of range");
     if (src_dtype < RD_F32 || src_dtype > RD_F64) return fail(RD_EINVAL, "unknown source dtype");
+    if (src_on_device < 0 || src_on_device > 2) return fail(RD_EINVAL, "src_on_device must be 0, 1 or 2");
     if (g->batch) return fail(RD_ESTATE, "grid is in a batch");
     const size_t n = size_t(g->nx) * g->ny * g->nz;
     const size_t es = src_dtype == RD_F64 ? 8 : src_dtype == RD_F32 ? 4 : 2;
-    RD_HIP(hipStreamSynchronize(g->stream));
+    const bool enqueue_only = src_on_device == 2;
+    if (!enqueue_only) RD_HIP(hipStreamSynchronize(g->stream));
     const void* dsrc = src;
     void* stage = nullptr;
     if (!src_on_device) {
@@ -1174,6 +1176,10 @@ extern "C" int rd_write_field(rd_grid* g, int32_t species, const void* src, int3
 #undef RD_PACK_SRC
 #undef RD_PACK
     const hipError_t e1 = hipGetLastError();
+    if (enqueue_only) {
+        if (e1 != hipSuccess) return fail(RD_EDEVICE, std::string("pack: ") + hipGetErrorString(e1));
+        return RD_OK;
+    }
     const hipError_t e2 = hipStreamSynchronize(g->stream);
     (void)hipFree(stage);
     if (e1 != hipSuccess || e2 != hipSuccess)

@@ -256,13 +256,20 @@ class Grid:
         del keep
         self.spec = spec
 
-    def write(self, species: int, src):
-        """Load one species from a numpy array (f64/f32) or a CUDA torch tensor."""
+    def write(self, species: int, src, enqueue_only: bool = False):
+        """Load one species from a numpy array (f64/f32) or a CUDA torch tensor.
+        enqueue_only (device tensors produced on the grid's own stream): the
+        copy is only enqueued on that stream; the caller keeps the tensor
+        alive until the stream has passed it (tensors allocated on that
+        stream are reused by torch only in stream order)."""
         if hasattr(src, "data_ptr") and getattr(src, "is_cuda", False):
             dt = {"torch.float32": F32, "torch.float64": F64, "torch.bfloat16": BF16,
                   "torch.float16": F16}[str(src.dtype)]
             if not src.is_contiguous() or tuple(src.shape) != self.shape:
                 raise ValueError("device source must be contiguous with shape (nz, ny, nx)")
+            if enqueue_only:
+                _check(lib().rd_write_field(self._p, species, C.c_void_p(src.data_ptr()), dt, 2))
+                return
             # the library reads the tensor on the grid's stream: let the stream
             # that produced it finish first
             import torch

@@ -268,8 +268,10 @@ class GpuExecutor:
             g.set_model(self.W.request_spec(req))
         with self.torch.cuda.stream(self.stream):      # same stream as the grid's copies
             fields = self.W.request_fields_device(req)
+            # enqueued behind the ticks in flight: the tensors are freed to
+            # torch's pool for this stream, which reuses them in stream order
             for s, f in enumerate(fields):
-                g.write(s, f)
+                g.write(s, f, enqueue_only=True)
         self.batch.add(g, int(req.steps))
         h = g.handle.value
         self.by_handle[h] = key

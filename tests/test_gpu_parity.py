@@ -952,6 +952,36 @@ def test_batched_many_items_equal_alone():
     b.close()
 
 
+def test_enqueued_device_write_equals_synchronous_write():
+    """A device field written with the enqueue-only copy on the grid's own
+    stream, behind steps still queued there, gives the same state as the
+    synchronous copy."""
+    import torch
+    w = W.make_workload("brusselator256", shape=(20, 24, 72))
+    stream = torch.cuda.Stream()
+    outs = []
+    for enqueue in (False, True):
+        g = rd.Grid.from_workload(w, stream=stream)
+        g.step(3)                                   # work queued on the stream
+        with torch.cuda.stream(stream):
+            fields = [torch.tensor(f, dtype=torch.float32, device="cuda").flip(0).contiguous()
+                      for f in w.fields]
+            for s, f in enumerate(fields):
+                g.write(s, f, enqueue_only=enqueue)
+        g.step(2)
+        outs.append(g.read_all())
+        g.close()
+    for s in range(2):
+        assert np.array_equal(outs[0][s], outs[1][s])
+    with pytest.raises(rd.RDError) as ei:
+        g = rd.Grid.from_workload(w)
+        try:
+            rd._check(rd.lib().rd_write_field(g._p, 0, rd.C.c_void_p(fields[0].data_ptr()), rd.F32, 3))
+        finally:
+            g.close()
+    assert ei.value.code == rd.EINVAL
+
+
 def test_batch_budget_and_validation():
     import torch
     stream = torch.cuda.Stream()
