@@ -108,7 +108,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("librdmi.so is not built (run __graft_entry__.build()); "
+            raise RuntimeError("librdmi.so is not built (run python paper_1004_0480_amd/build.py); "
                                "there is no CPU fallback for the HIP path")
         # torch ships its own HIP runtime under the same soname; load it first
         # so that this library binds to it and the process has one runtime.
@@ -145,7 +145,7 @@ def check_build_matches_sources():
     want, got = _build.source_digest(), source_digest()
     if got != want:
         raise RuntimeError("librdmi.so was built from sources %s but csrc/ hashes to %s: rebuild "
-                           "(__graft_entry__.build())" % (got, want))
+                           "(python paper_1004_0480_amd/build.py)" % (got, want))
     return got
 
 
