@@ -209,7 +209,9 @@ typedef struct rd_plan {
                              LDS/LDS2: computing waves (plus one loading wave);
                              FUSED: waves updating the fields (plus vx waves
                              for the chemical potential and one loading wave);
-                             TRING: computing waves (plus one loading wave)   */
+                             TRING: computing waves (plus one loading wave, or
+                             two when the fields' ring rows times prefetch-3
+                             exceed 63 loads)                                  */
     int32_t cz;           /* TILED/LDS/LDS2/FUSED/TRING: z planes per workgroup, 0 = all;
                              BLOCK: planes per slab (2, 4 or 8)                */
     int32_t prefetch;     /* TILED: planes in flight ahead of the z window (1-2);

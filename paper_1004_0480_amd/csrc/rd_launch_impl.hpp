@@ -92,12 +92,13 @@ template <class M, int I>
 hipError_t run_tr(bool plain, const StepArgs* d, long long blocks, hipStream_t s) {
     if constexpr (tr_ok(kStorage, PmOf<M>::v, I)) {
         constexpr TrCfg c = kTrCfgs[I];
+        constexpr int threads = 64 * (c.wc + tr_np(M::NF, c.by, c.d));
         if (plain)
-            hipLaunchKernelGGL((tr_kernel<M, S, c.by, c.wc, c.d, true>), dim3((unsigned)blocks), dim3(64 * (c.wc + 1)),
-                               0, s, d);
+            hipLaunchKernelGGL((tr_kernel<M, S, c.by, c.wc, c.d, true>), dim3((unsigned)blocks), dim3(threads), 0, s,
+                               d);
         else
-            hipLaunchKernelGGL((tr_kernel<M, S, c.by, c.wc, c.d, false>), dim3((unsigned)blocks),
-                               dim3(64 * (c.wc + 1)), 0, s, d);
+            hipLaunchKernelGGL((tr_kernel<M, S, c.by, c.wc, c.d, false>), dim3((unsigned)blocks), dim3(threads), 0,
+                               s, d);
         return hipGetLastError();
     } else {
         return hipErrorNotSupported;

@@ -446,9 +446,10 @@ __device__ __forceinline__ void tr_run(const StepArgs& a, RD_LDS float* rg, int 
 }
 
 // PLAIN: the launch has no Runge-Kutta combination and no stochastic
-// rounding, so only that store is compiled into it.
+// rounding, so only that store is compiled into it.  Waves: tr_np loading
+// waves, then WC computing waves.
 template <class M, class S, int BY, int WC, int DR, bool PLAIN>
-__global__ __launch_bounds__(64 * (1 + WC)) void tr_kernel(const StepArgs* __restrict__ pa) {
+__global__ __launch_bounds__(64 * (tr_np(M::NF, BY, DR) + WC)) void tr_kernel(const StepArgs* __restrict__ pa) {
     using R = Tr<M, S, BY, DR>;
     static_assert(BY % WC == 0, "rows per wave");
     __shared__ __attribute__((aligned(16))) float ring[DR * R::SLOT_W];
@@ -457,8 +458,8 @@ __global__ __launch_bounds__(64 * (1 + WC)) void tr_kernel(const StepArgs* __res
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const TileXYZ tc = tile_coords(a, xcd_tile(blockIdx.x, gridDim.x));
     const int z0 = tc.z * a.cz;
-    tr_run<M, S, BY, WC, DR, PLAIN>(a, (RD_LDS float*)&ring[0], w, tc.x * R::TX, tc.y * BY, z0,
-                                    min(z0 + a.cz, a.nz));
+    tr_run<M, S, BY, WC, DR, PLAIN, tr_np(M::NF, BY, DR)>(a, (RD_LDS float*)&ring[0], w, tc.x * R::TX,
+                                                         tc.y * BY, z0, min(z0 + a.cz, a.nz));
 }
 
 // The batched form (served grids of diffusion or the Brusselator, forward

@@ -11,6 +11,7 @@ namespace rdk {
 struct TrCfg { int by, wc, d; };
 constexpr TrCfg kTrCfgs[] = {
     {8, 8, 6}, {4, 4, 7}, {8, 4, 6}, {4, 4, 6}, {8, 8, 5}, {16, 8, 5}, {8, 8, 4}, {6, 6, 5},
+    {16, 8, 6}, {16, 8, 7},
 };
 constexpr int kNumTrCfgs = sizeof(kTrCfgs) / sizeof(kTrCfgs[0]);
 constexpr int kTrTile = 128;
@@ -35,12 +36,18 @@ constexpr int tr_fields(int pm) {
     }
 }
 
+// Loading waves of a shape for nf fields: two when one wave could not keep
+// the d-3 steps it should have in flight (nf*(by+2) row loads each) within
+// the 63 loads its wait counter can express.
+constexpr int tr_np(int nf, int by, int d) { return nf * (by + 2) * (d - 3) > 63 ? 2 : 1; }
+
 // Shape i is compiled for this storage (FP32 or BF16) and pass model.
 constexpr bool tr_ok(int storage, int pm, int i) {
     if (i < 0 || i >= kNumTrCfgs || (storage != ST_F32 && storage != ST_BF16)) return false;
     const int nf = tr_fields(pm);
     const TrCfg c = kTrCfgs[i];
-    if (nf == 0 || c.by % c.wc != 0 || c.wc > 15 || c.d < 4 || (c.by / c.wc) > 2) return false;
+    if (nf == 0 || c.by % c.wc != 0 || c.wc + tr_np(nf, c.by, c.d) > 16 || c.d < 4 || (c.by / c.wc) > 2)
+        return false;
     return tr_lds_bytes(nf, storage == ST_F32 ? 4 : 2, i) <= 160 * 1024;
 }
 

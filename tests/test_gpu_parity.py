@@ -34,7 +34,8 @@ LDS2_SHAPES = [(4, 4, 8, 6), (8, 4, 8, 6), (4, 8, 8, 5), (8, 6, 6, 4), (4, 6, 12
 # waves, ring slots)
 FCH_SHAPES = [(8, 8, 5, 7), (4, 4, 3, 7), (4, 4, 3, 6), (2, 2, 2, 7), (4, 4, 2, 7), (8, 8, 4, 8), (16, 8, 6, 7),
               (4, 4, 3, 9), (8, 8, 5, 6), (4, 4, 3, 5), (4, 4, 2, 5), (8, 8, 5, 5)]
-TR_SHAPES = [(8, 8, 6), (4, 4, 7), (8, 4, 6), (4, 4, 6), (8, 8, 5), (16, 8, 5), (8, 8, 4), (6, 6, 5)]
+TR_SHAPES = [(8, 8, 6), (4, 4, 7), (8, 4, 6), (4, 4, 6), (8, 8, 5), (16, 8, 5), (8, 8, 4), (6, 6, 5),
+             (16, 8, 6), (16, 8, 7)]
 BLOCK_SHAPES = [(4, 1, 4, 2), (4, 1, 4, 4), (4, 2, 4, 2), (4, 2, 4, 4), (4, 1, 4, 8), (2, 2, 4, 4),
                 (2, 1, 4, 4), (4, 2, 1, 2), (4, 1, 1, 2), (4, 2, 1, 4), (4, 4, 1, 2), (4, 2, 2, 2),
                 (4, 3, 1, 2)]
