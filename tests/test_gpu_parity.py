@@ -953,6 +953,34 @@ def test_batched_many_items_equal_alone():
     b.close()
 
 
+def test_batch_of_more_grids_than_the_lds_lookup_holds():
+    """1100 small grids (more than the batched kernel's LDS copy of the
+    grids' first items holds, so items find their grid in device memory):
+    every grid matches the same grid stepped alone."""
+    import torch
+    stream = torch.cuda.Stream()
+    n = 1100
+    b = rd.Batch(n, 1 << 34, "f32", stream=stream)
+    grids, ws = [], []
+    for i in range(n):
+        r = W.Request(i, 0, 8 if i % 3 else 12, "brusselator" if i % 2 else "diffusion", 3 + i % 4, 1000 + i)
+        w = W.request_workload(r)
+        g = rd.Grid.from_workload(w, stream=stream)
+        b.add(g, r.steps)
+        grids.append((r, w, g))
+    finished = []
+    while len(finished) < n:
+        finished += b.step(2)
+    for r, w, g in grids[::97] + grids[-3:]:
+        alone, _ = gpu_run(w, r.steps)
+        got = g.read_all()
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], alone[s]), (r, s)
+    for _, _, g in grids:
+        g.close()
+    b.close()
+
+
 def test_enqueued_device_write_equals_synchronous_write():
     """A device field written with the enqueue-only copy on the grid's own
     stream, behind steps still queued there, gives the same state as the
