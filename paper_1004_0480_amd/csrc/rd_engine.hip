@@ -322,6 +322,26 @@ int balanced_cz(const rd_grid* g, long long tiles) {
     return best;
 }
 
+// z chunk length for k resident workgroups per CU: every chunk count n from
+// 1 to 64 (chunks of ceil(nz/n) planes), scored by rounds x (planes + 3)
+// where a round is k workgroups on every CU.  A workgroup count just below a
+// multiple of k*CUs leaves no last round mostly idle.
+int balanced_cz_k(const rd_grid* g, long long tiles, int k) {
+    int best = 0;
+    double best_t = 1e300;
+    const long long slots = (long long)k * num_cus();
+    for (int n = 1; n <= 64 && n <= g->nz; ++n) {
+        const int c = int((g->nz + n - 1) / n);
+        const long long wg = tiles * ((g->nz + c - 1) / c);
+        const double t = double((wg + slots - 1) / slots) * (c + 3);
+        if (t < best_t) {
+            best_t = t;
+            best = c >= g->nz ? 0 : c;
+        }
+    }
+    return best;
+}
+
 rd_plan heuristic_plan(const rd_grid* g) {
     rd_plan best{};
     best.kernel = RD_KERNEL_DIRECT;
@@ -1436,8 +1456,9 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
         const FchCfg c = kFchCfgs[i];
         const long long tiles = ((g->nx + kFchTile - 1) / kFchTile) * ((g->ny + c.by - 1) / c.by);
         std::vector<int> czs = {0, 64, 32, 16};
-        const int bal = balanced_cz(g, tiles);
-        if (std::find(czs.begin(), czs.end(), bal) == czs.end()) czs.push_back(bal);
+        // chunk lengths balanced for one, two or three resident workgroups per CU
+        for (int bal : {balanced_cz(g, tiles), balanced_cz_k(g, tiles, 2), balanced_cz_k(g, tiles, 3)})
+            if (std::find(czs.begin(), czs.end(), bal) == czs.end()) czs.push_back(bal);
         for (int cz : czs) {
             if (cz != 0 && cz >= g->nz) continue;
             for (int order : {0, 1}) {
