@@ -377,7 +377,7 @@ def main():
     ap.add_argument("--stencil", type=int, default=7, choices=[7, 19],
                     help="Laplacian: 7-point, or the 19-point form of Eqs. (3)-(4) (x coefficient on every axis)")
     ap.add_argument("--requests", type=int, default=4096)
-    ap.add_argument("--max-resident", type=int, default=256)
+    ap.add_argument("--max-resident", type=int, default=512)
     ap.add_argument("--hbm-budget", type=int, default=16 << 30)
     ap.add_argument("--chunk", type=int, default=50)
     ap.add_argument("--min-run", type=int, default=1,
