@@ -180,21 +180,28 @@ __device__ __forceinline__ void tr_producer(const StepArgs& a, RD_LDS float* rin
 #endif
 }
 
-// A computing wave: RY = BY / WC output rows, two cells per lane.
-template <class M, class S, int BY, int WC, int DR>
+// A computing wave: RY = BY / WC output rows, two cells per lane.  PK
+// (rows of at most 64 cells): lanes 0-31 and 32-63 take two rows at once, so
+// a wave makes RY/2 passes over its rows instead of RY.
+template <class M, class S, int BY, int WC, int DR, bool PK = false>
 struct TrConsumer {
     using R = Tr<M, S, BY, DR>;
     using T = typename R::T;
     static constexpr int NF = M::NF, NO = M::NO, RY = BY / WC;
+    static constexpr int RYE = PK ? RY / 2 : RY;   // passes over the wave's rows
+    static_assert(!PK || RY % 2 == 0, "packed rows come in pairs");
     static constexpr int HX = R::HX, TX = R::TX, RW = R::RW, RR = R::RR;
 
     const StepArgs& a;
     const CellConst k;
     const RD_LDS T* ring;
-    int lane, x0, yb, xl;
+    int lane, sub, cl, x0, yb, xl;
     __device__ __forceinline__ TrConsumer(const StepArgs& a_, const RD_LDS float* ring_w, int x0_, int yb_)
-        : a(a_), k(a_), ring((const RD_LDS T*)ring_w), lane(threadIdx.x & 63), x0(x0_), yb(yb_),
-          xl(x0_ + 2 * (threadIdx.x & 63)) {}
+        : a(a_), k(a_), ring((const RD_LDS T*)ring_w), lane(threadIdx.x & 63),
+          sub(PK ? (threadIdx.x & 63) >> 5 : 0), cl(PK ? threadIdx.x & 31 : threadIdx.x & 63), x0(x0_), yb(yb_),
+          xl(x0_ + 2 * (PK ? threadIdx.x & 31 : threadIdx.x & 63)) {}
+    // wave row of pass r (this lane's row when packed)
+    __device__ __forceinline__ int prow(int r0, int r) const { return PK ? r0 + 2 * r + sub : r0 + r; }
 
     __device__ __forceinline__ const RD_LDS T* slot(int s) const { return ring + s * R::SLOT; }
     static __device__ __forceinline__ const RD_LDS T* row(const RD_LDS T* P, int f, int j) {
@@ -202,7 +209,7 @@ struct TrConsumer {
     }
     // this lane's two cells of a ring row, as FP32
     __device__ __forceinline__ void rd2(const RD_LDS T* r, float (&o)[2]) const {
-        const RD_LDS T* q = r + HX + 2 * lane;
+        const RD_LDS T* q = r + HX + 2 * cl;
         if constexpr (sizeof(T) == 4) {
             typedef float v2f __attribute__((ext_vector_type(2)));
             const v2f t = *(const RD_LDS v2f*)q;
@@ -258,6 +265,13 @@ struct TrConsumer {
         xm[1] = v[0];
         xp[0] = v[1];
         xp[1] = lane_from_right(v[0], hr);
+        if constexpr (PK) {
+            // the lane groups' own ends: the neighbour lane holds the other row
+            // (lane 31's right neighbour matters only for rows of 64 cells,
+            // where hr is x = 64)
+            if (cl == 0) xm[0] = fill;
+            if (cl == 31) xp[1] = hr;
+        }
         if constexpr (FIX) {
             if (x0 + TX >= a.nx) {
                 const int kr = a.bck[f][1];
@@ -270,35 +284,38 @@ struct TrConsumer {
 
     // centre rows of the wave's output rows (slot P) as read, and their rules
     // applied once they are in
-    __device__ __forceinline__ void centre_read(int r0, const RD_LDS T* P, float (&c)[NF][RY][2]) const {
+    __device__ __forceinline__ void centre_read(int r0, const RD_LDS T* P, float (&c)[NF][RYE][2]) const {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int r = 0; r < RY; ++r) rd2(row(P, f, r0 + r + 1), c[f][r]);
+            for (int r = 0; r < RYE; ++r) rd2(row(P, f, prow(r0, r) + 1), c[f][r]);
     }
-    __device__ __forceinline__ void centre_fix(int r0, int p, float (&c)[NF][RY][2]) const {
+    __device__ __forceinline__ void centre_fix(int r0, int p, float (&c)[NF][RYE][2]) const {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
-            for (int r = 0; r < RY; ++r) fix_row<2>(a, f, zsrc(f, p), ysrc(f, yb + r0 + r), xl, c[f][r]);
+            for (int r = 0; r < RYE; ++r) fix_row<2>(a, f, zsrc(f, p), ysrc(f, yb + prow(r0, r)), xl, c[f][r]);
     }
 
     // the y neighbour rows and x halo cells of the output rows of one plane
     struct RowsIn {
-        float ym[NF][RY][2], yp[NF][RY][2], hl[NF][RY], hr[NF][RY];
+        float ym[NF][RYE][2], yp[NF][RYE][2], hl[NF][RYE], hr[NF][RYE];
     };
     __device__ __forceinline__ void rows_read(int r0, const RD_LDS T* P, RowsIn& in) const {
         const int hlo = HL;
 #pragma unroll
-        for (int r = 0; r < RY; ++r)
+        for (int r = 0; r < RYE; ++r)
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                const int j = r0 + r + 1;
+                const int j = prow(r0, r) + 1;
                 const RD_LDS T* rc = row(P, f, j);
                 rd2(row(P, f, j - 1), in.ym[f][r]);
                 rd2(row(P, f, j + 1), in.yp[f][r]);
                 in.hl[f][r] = rd1(rc, hlo);
-                in.hr[f][r] = rd1(rc, HX + TX);
+                // the cell right of the lane group: x0+TX, or for packed rows x = nx,
+                // which the producer's patch holds (the wrapped value on a
+                // periodic axis, as the halo unit at x0+TX does unpacked)
+                in.hr[f][r] = rd1(rc, HX + (PK ? a.nx : TX));
             }
     }
 
@@ -306,13 +323,13 @@ struct TrConsumer {
     // the centre rows of z-1, z, z+1.  PLAIN: no Runge-Kutta combination and
     // no stochastic rounding in the stores.
     template <bool FIX, bool PLAIN>
-    __device__ __forceinline__ void update(int r0, int z, RowsIn in, const float (&cm)[NF][RY][2],
-                                           const float (&c0)[NF][RY][2], const float (&cp)[NF][RY][2],
-                                           RD_GLOBAL T* const (&po)[NO][RY], const bool (&rowst)[RY]) const {
+    __device__ __forceinline__ void update(int r0, int z, RowsIn in, const float (&cm)[NF][RYE][2],
+                                           const float (&c0)[NF][RYE][2], const float (&cp)[NF][RYE][2],
+                                           RD_GLOBAL T* const (&po)[NO][RYE], const bool (&rowst)[RYE]) const {
         const float wind = plane_wind<M>(a, z);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const int y = yb + r0 + r;
+        for (int r = 0; r < RYE; ++r) {
+            const int y = yb + prow(r0, r);
             Nb n[2][NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -321,7 +338,7 @@ struct TrConsumer {
                     fix_row<2>(a, f, pz, ysrc(f, y - 1), xl, in.ym[f][r]);
                     fix_row<2>(a, f, pz, ysrc(f, y + 1), xl, in.yp[f][r]);
                     fix1(a, f, pz, y0, x0 == 0 ? a.nx - 1 : x0 - 1, in.hl[f][r]);
-                    fix1(a, f, pz, y0, x0 + TX, in.hr[f][r]);
+                    fix1(a, f, pz, y0, x0 + (PK ? a.nx : TX), in.hr[f][r]);
                 }
                 float xm[2], xp[2];
                 xnb<FIX>(f, c0[f][r], in.hl[f][r], in.hr[f][r], xm, xp);
@@ -373,20 +390,20 @@ struct TrConsumer {
             for (int r = -1; r <= RY; ++r) wfix = wfix || ysrc(f, yb + r0 + r).cst != CST_NONE;
         }
         // centre rows of planes q-1, q, q+1 and (read in iteration q) q+2
-        float cen[4][NF][RY][2];
+        float cen[4][NF][RYE][2];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int r = 0; r < RY; ++r) cen[t][f][r][0] = cen[t][f][r][1] = 0.f;
+                for (int r = 0; r < RYE; ++r) cen[t][f][r][0] = cen[t][f][r][1] = 0.f;
         // output rows: their addresses on plane z0, advanced a plane per
         // update, and whether this lane stores there
-        RD_GLOBAL T* po[NO][RY];
-        bool rowst[RY];
+        RD_GLOBAL T* po[NO][RYE];
+        bool rowst[RYE];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const int y = yb + r0 + r;
+        for (int r = 0; r < RYE; ++r) {
+            const int y = yb + prow(r0, r);
             rowst[r] = y < a.ny && xl < a.nx;
 #pragma unroll
             for (int s = 0; s < NO; ++s)
@@ -411,13 +428,13 @@ struct TrConsumer {
 #pragma unroll
                 for (int s = 0; s < NO; ++s)
 #pragma unroll
-                    for (int r = 0; r < RY; ++r) po[s][r] += a.plane;
+                    for (int r = 0; r < RYE; ++r) po[s][r] += a.plane;
             }
             if (cen_next && (wfix || q + 2 <= 0 || q + 2 >= a.nz - 1)) centre_fix(r0, q + 2, cen[3]);
 #pragma unroll
             for (int f = 0; f < NF; ++f)
 #pragma unroll
-                for (int r = 0; r < RY; ++r)
+                for (int r = 0; r < RYE; ++r)
 #pragma unroll
                     for (int i = 0; i < 2; ++i) {
                         cen[0][f][r][i] = cen[1][f][r][i];
@@ -437,11 +454,14 @@ struct TrConsumer {
 
 // One workgroup's march over its tile (waves 0 .. NP-1 load, the others
 // compute).
-template <class M, class S, int BY, int WC, int DR, bool PLAIN, int NP = 1>
-__device__ __forceinline__ void tr_run(const StepArgs& a, RD_LDS float* rg, int w, int x0, int yb, int z0, int z1) {
+// PKOK: rows of at most 64 cells (pk) take the packed computing waves.
+template <class M, class S, int BY, int WC, int DR, bool PLAIN, int NP = 1, bool PKOK = false>
+__device__ __forceinline__ void tr_run(const StepArgs& a, RD_LDS float* rg, int w, int x0, int yb, int z0, int z1,
+                                       bool pk = false) {
     static_assert(NP == 1 || NP == 2, "one or two producer waves");
     if (w == 0) tr_producer<M, S, BY, DR, NP, 0>(a, rg, x0, yb, z0, z1);
     else if (NP == 2 && w == 1) tr_producer<M, S, BY, DR, NP, NP - 1>(a, rg, x0, yb, z0, z1);
+    else if (PKOK && pk) TrConsumer<M, S, BY, WC, DR, PKOK>(a, rg, x0, yb).template run<PLAIN>(w - NP, z0, z1);
     else TrConsumer<M, S, BY, WC, DR>(a, rg, x0, yb).template run<PLAIN>(w - NP, z0, z1);
 }
 
@@ -501,8 +521,13 @@ __global__ __launch_bounds__(64 * (NP + WC)) void batched_tr_kernel(int* __restr
         const StepArgs& a = en.args[(en.parity + step) & 1];
         const TileXYZ tc = tile_coords(a, item - first[lo]);
         const int z0 = tc.z * a.cz, z1 = min(z0 + a.cz, a.nz);
-        if (en.model == 1) tr_run<Brusselator, S, BY, WC, DR, true, NP>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
-        else tr_run<Diffusion<1>, S, BY, WC, DR, true, NP>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1);
+        // rows of at most 64 cells: two rows per lane group pass (two cells per lane)
+        constexpr bool PKOK = (BY / WC) % 2 == 0;
+        const bool pk = a.nx <= 64;
+        if (en.model == 1)
+            tr_run<Brusselator, S, BY, WC, DR, true, NP, PKOK>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1, pk);
+        else
+            tr_run<Diffusion<1>, S, BY, WC, DR, true, NP, PKOK>(a, rg, w, tc.x * kTrTile, tc.y * BY, z0, z1, pk);
         __syncthreads();                         // the next item refills the ring
     }
     if (threadIdx.x == 0) {

@@ -953,6 +953,34 @@ def test_batched_many_items_equal_alone():
     b.close()
 
 
+def test_batch_narrow_rows_packed_two_per_wave():
+    """Rows of at most 64 cells, which the batched kernel computes two rows
+    per wave (one per half wave), on uneven shapes and both face kinds
+    (mirror for diffusion, periodic for the Brusselator), and a 66-cell row
+    that takes the unpacked form: each matches the grid stepped alone."""
+    import torch
+    stream = torch.cuda.Stream()
+    cases = [("diffusion64", (5, 17, 64), 7), ("brusselator256", (9, 3, 50), 5), ("brusselator256", (7, 33, 62), 6),
+             ("diffusion64", (6, 20, 2), 4), ("brusselator256", (4, 18, 64), 3), ("diffusion64", (5, 9, 66), 5)]
+    b = rd.Batch(len(cases), 1 << 34, "f32", stream=stream)
+    grids = []
+    for name, shape, steps in cases:
+        w = W.make_workload(name, shape=shape)
+        g = rd.Grid.from_workload(w, stream=stream)
+        b.add(g, steps)
+        grids.append((w, steps, g))
+    finished = []
+    while len(finished) < len(grids):
+        finished += b.step(4)
+    for w, steps, g in grids:
+        alone, _ = gpu_run(w, steps)
+        got = g.read_all()
+        for s in range(w.spec.ns):
+            assert np.array_equal(got[s], alone[s]), (w.shape, s)
+        g.close()
+    b.close()
+
+
 def test_batch_of_more_grids_than_the_lds_lookup_holds():
     """1100 small grids (more than the batched kernel's LDS copy of the
     grids' first items holds, so items find their grid in device memory):
