@@ -342,7 +342,8 @@ def serve_bench(args):
             ex = S.GpuExecutor(storage, max_resident=args.max_resident, hbm_budget=args.hbm_budget)
             print("bench: serve %s %s (%d requests)" % (storage, phase, len(trace)),
                   file=sys.stderr, flush=True)
-            rep = S.serve(trace, arr, ex, args.max_resident, args.hbm_budget, args.chunk, min_run=args.min_run)
+            rep = S.serve(trace, arr, ex, args.max_resident, args.hbm_budget, args.chunk, min_run=args.min_run,
+                          depth=args.ticks_in_flight)
             ex.close()
             torch.cuda.synchronize()
             summ = rep.summary()
@@ -356,7 +357,7 @@ def serve_bench(args):
                 "config": {"workload": "served batch", "requests": len(trace),
                            "edges": list(W.SERVE_EDGES), "steps": [200, 2000],
                            "max_resident": args.max_resident, "hbm_budget": args.hbm_budget,
-                           "chunk": args.chunk, "min_run": args.min_run,
+                           "chunk": args.chunk, "min_run": args.min_run, "ticks_in_flight": args.ticks_in_flight,
                            "arrival_rate": "0.8 x measured capacity"}})
     print(json.dumps(out), flush=True)
 
@@ -380,6 +381,8 @@ def main():
     ap.add_argument("--max-resident", type=int, default=512)
     ap.add_argument("--hbm-budget", type=int, default=16 << 30)
     ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--ticks-in-flight", type=int, default=2,
+                    help="served batch: ticks the host keeps queued before it waits for the oldest")
     ap.add_argument("--min-run", type=int, default=1,
                     help="served batch: steps a tick runs at least (finished grids sit out the rest)")
     ap.add_argument("--graph-chunk", type=int, default=50)

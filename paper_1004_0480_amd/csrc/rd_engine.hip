@@ -1617,10 +1617,14 @@ struct rd_batch {
     std::vector<Member> members;
     size_t bytes = 0;
     char* d_tab = nullptr;         // meta ints, then entries (at entries_off)
-    char* h_tab = nullptr;         // pinned staging of the table
+    // pinned staging of the table, two alternating copies: a tick's table is
+    // written while the previous tick's upload may still wait behind the tick
+    // before it (the device copy is one: stream order protects it)
+    char* h_tab2[2] = {nullptr, nullptr};
+    int next_tab = 0;
     size_t tab_bytes = 0;
-    hipEvent_t tab_done = nullptr;
-    bool tab_pending = false;
+    hipEvent_t tab_done[2] = {nullptr, nullptr};
+    bool tab_pending[2] = {false, false};
     std::map<int64_t, hipGraphExec_t> graphs;   // by chunk
     int blocks = 0;
 };
@@ -1646,8 +1650,10 @@ extern "C" int rd_batch_create(int32_t max_grids, size_t hbm_budget_bytes, int32
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->tab_bytes = table_bytes(max_grids, max_grids);
     if (hipMalloc(reinterpret_cast<void**>(&b->d_tab), b->tab_bytes) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&b->h_tab), b->tab_bytes, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&b->tab_done, hipEventDisableTiming) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_tab2[0]), b->tab_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b->h_tab2[1]), b->tab_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->tab_done[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->tab_done[1], hipEventDisableTiming) != hipSuccess) {
         rd_batch_destroy(b);
         return fail(RD_ENOMEM, "batch table allocation failed");
     }
@@ -1662,8 +1668,10 @@ extern "C" int rd_batch_destroy(rd_batch* b) {
     for (auto& m : b->members) m.g->batch = nullptr;
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     (void)hipFree(b->d_tab);
-    if (b->h_tab) (void)hipHostFree(b->h_tab);
-    if (b->tab_done) (void)hipEventDestroy(b->tab_done);
+    for (int i = 0; i < 2; ++i) {
+        if (b->h_tab2[i]) (void)hipHostFree(b->h_tab2[i]);
+        if (b->tab_done[i]) (void)hipEventDestroy(b->tab_done[i]);
+    }
     delete b;
     return RD_OK;
 }
@@ -1719,18 +1727,21 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     if (chunk < 1 || chunk > 100000) return fail(RD_EINVAL, "chunk must be 1..100000");
     *n_finished = 0;
     if (b->members.empty()) return RD_OK;
-    if (b->tab_pending) {
-        RD_HIP(hipEventSynchronize(b->tab_done));
-        b->tab_pending = false;
+    // this tick's staging copy: its last upload (two ticks ago) must have run
+    const int tb = b->next_tab;
+    if (b->tab_pending[tb]) {
+        RD_HIP(hipEventSynchronize(b->tab_done[tb]));
+        b->tab_pending[tb] = false;
     }
+    char* h_tab = b->h_tab2[tb];
     // Work list: every member's tiles, with its arguments for both parities,
     // the grids with the largest tiles first (the kernel's workgroups claim
     // items in list order, so the small ones fill in at the end of a step).
     const int ng = int(b->members.size());
     const size_t moff = meta_bytes(b->max_grids);
-    int* meta = reinterpret_cast<int*>(b->h_tab);
-    BatchEntry* ents = reinterpret_cast<BatchEntry*>(b->h_tab + moff);
-    std::memset(b->h_tab, 0, table_bytes(b->max_grids, ng));
+    int* meta = reinterpret_cast<int*>(h_tab);
+    BatchEntry* ents = reinterpret_cast<BatchEntry*>(h_tab + moff);
+    std::memset(h_tab, 0, table_bytes(b->max_grids, ng));
     std::vector<int> order(static_cast<size_t>(ng));
     for (int i = 0; i < ng; ++i) order[size_t(i)] = i;
     auto tile_cost = [&](int i) {
@@ -1770,11 +1781,12 @@ extern "C" int rd_batch_step(rd_batch* b, int64_t chunk, rd_grid** finished, int
     meta[0] = ng;
     meta[1] = int(items);
     meta[4 + ng] = int(items);
-    RD_HIP(hipMemcpyAsync(b->d_tab, b->h_tab, moff, hipMemcpyHostToDevice, b->stream));
-    RD_HIP(hipMemcpyAsync(b->d_tab + moff, b->h_tab + moff, size_t(ng) * sizeof(BatchEntry),
+    RD_HIP(hipMemcpyAsync(b->d_tab, h_tab, moff, hipMemcpyHostToDevice, b->stream));
+    RD_HIP(hipMemcpyAsync(b->d_tab + moff, h_tab + moff, size_t(ng) * sizeof(BatchEntry),
                           hipMemcpyHostToDevice, b->stream));
-    RD_HIP(hipEventRecord(b->tab_done, b->stream));
-    b->tab_pending = true;
+    RD_HIP(hipEventRecord(b->tab_done[tb], b->stream));
+    b->tab_pending[tb] = true;
+    b->next_tab = tb ^ 1;
     const int64_t run = std::min(chunk, max_steps);
     if (b->stream != nullptr) {
         auto it = b->graphs.find(run);

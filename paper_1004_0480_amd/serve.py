@@ -7,10 +7,11 @@ all resident grids together, ``chunk`` steps per tick, through one executor
 call; grids that finish leave the batch, their result is read back, and the
 freed slots and memory admit newly arrived requests at the next tick.
 
-The host keeps one tick in flight: it launches tick k+1 (admitting what
-arrived meanwhile) before it waits for tick k, so the device does not idle
-while the host does the bookkeeping between ticks; requests that finished in
-tick k complete when the host sees tick k's end.
+The host keeps up to ``depth`` ticks in flight (two by default): it launches
+tick k+1 (admitting what arrived meanwhile) before it waits for tick
+k+1-depth, so the device does not idle while the host does the bookkeeping
+between ticks; requests that finished in a tick complete when the host sees
+that tick's end.
 
 The scheduler is independent of the executor: ``GpuExecutor`` drives the
 library's batched persistent kernel (``rd_batch_*``); ``SimulatedExecutor``
@@ -99,7 +100,7 @@ class VirtualClock(Clock):
 
 def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident: int,
           hbm_budget: int, chunk: int, clock: Optional[Clock] = None,
-          keep_results: bool = False, min_run: int = 1) -> ServeReport:
+          keep_results: bool = False, min_run: int = 1, depth: int = 2) -> ServeReport:
     """Run the continuous-batching loop over ``requests`` arriving at
     ``arrivals`` (seconds after start, non-decreasing).  A tick runs up to
     ``chunk`` steps and stops at the earliest finisher, but runs at least
@@ -118,7 +119,7 @@ def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident:
     peak_res = 0
     peak_bytes = 0
     rejected = 0
-    inflight = None                     # (tick token, [(rec, handle, output)]) launched, not yet seen done
+    inflight = deque()                  # (tick token, [(rec, output)]) launched, not yet seen done
 
     def complete(tick):
         nonlocal busy
@@ -168,9 +169,10 @@ def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident:
                 assert r["left"] > 0, "the executor did not report a finished grid"
             ticks += 1
             launched = (token, recs)
-        if inflight:
-            complete(inflight)
-        inflight = launched
+        if launched:
+            inflight.append(launched)
+        while inflight and (len(inflight) > max(1, depth) or not resident):
+            complete(inflight.popleft())
         if not resident and not inflight and pending:
             clock.sleep_until(t0 + arrivals[pending[0]])
     makespan = clock.now() - t0

@@ -94,6 +94,22 @@ def test_minimum_tick_length_merges_close_finishers():
     assert rep1.ticks == 6                      # 20, 2, 2, 2, 50, 22
 
 
+def test_deeper_pipelining_keeps_every_request_and_ordering():
+    """One, two or three ticks in flight: every request completes once, after
+    it arrived and was admitted, and the device time never exceeds the
+    makespan."""
+    tr = small_trace(50)
+    arr = S.poisson_arrivals(tr, 2500.0)
+    for depth in (1, 2, 3):
+        clock = S.VirtualClock()
+        ex = S.SimulatedExecutor(clock)
+        rep = S.serve(tr, arr, ex, 16, 1 << 40, 50, clock=clock, depth=depth)
+        assert sorted(c.rid for c in rep.completions) == list(range(len(tr)))
+        for c in rep.completions:
+            assert c.arrival <= c.admitted <= c.finished
+        assert 0 < rep.summary()["busy_fraction"] <= 1.0 + 1e-9
+
+
 def test_trace_statistics():
     tr = W.make_trace(4096, seed=4)
     edges = np.array([r.edge for r in tr])
