@@ -500,12 +500,22 @@ struct FchConsumer {
     // combination and round-to-nearest; STORE_SR, no Runge-Kutta combination
     // and stochastic rounding to BF16 with the draws shared by lane pairs
     // (sr_pair); STORE_ANY, every other case, through the general store.
+
+    // Stochastic rounding state of an update wave: step, key of species 0,
+    // counter step from one plane to the next, and the species-2 words of the
+    // next plane when the previous update drew them.
+    struct SrState {
+        unsigned n, key, dpc;
+        unsigned carry[RY];
+        bool have;
+    };
+
     template <bool FIX, bool CD, int ST>
     __device__ __forceinline__ void update(int r0, int z, const RD_LDS T* PC, const RD_LDS T* PAB,
                                            const float (&cm)[3][RY][2], const float (&c0)[3][RY][2],
                                            const float (&cp)[3][RY][2], RD_GLOBAL T* const (&po)[3][RY],
                                            const bool (&rowst)[RY], const unsigned (&pc)[RY],
-                                           unsigned srn, unsigned srk) const {
+                                           SrState& sr) const {
         constexpr int NF = CD ? 3 : 2;               // fields with a Laplacian of their own
         const int hlo = hl_off();
         const int zm = max(z - 1, 0), zp = min(z + 1, a.nz - 1);
@@ -595,7 +605,7 @@ struct FchConsumer {
             }
             if constexpr (ST == STORE_SR) {
                 unsigned wd[3];
-                sr_pair(pc[r], srn, srk, wd);
+                sr_pair(pc[r], sr, r, wd);
                 if (rowst[r]) {
 #pragma unroll
                     for (int s = 0; s < 3; ++s)
@@ -618,20 +628,31 @@ struct FchConsumer {
     // the first cell, 16-31 for the second), as the general store draws them:
     // the cells of a lane pair (four in a row, the first at a multiple of four
     // in the dense index) share counter c, and species s takes the call with
-    // key srk + s, the even lane its first word, the odd lane its second.  The
+    // key key + s, the even lane its first word, the odd lane its second.  The
     // even lane makes the species-0 call and the odd lane the species-1 call,
-    // each passing the word the other needs across the pair; both make the
-    // species-2 call: two calls per lane instead of three.
-    __device__ __forceinline__ void sr_pair(unsigned c, unsigned srn, unsigned srk, unsigned (&wd)[3]) const {
-        const bool odd = (threadIdx.x & 1) != 0;
-        const PhiloxOut r01 = philox2x32_10(c, srn, srk + (odd ? 1u : 0u));
-        const PhiloxOut r2 = philox2x32_10(c, srn, srk + 2u);
-        const unsigned send = odd ? r01.w0 : r01.w1;
+    // each passing the word the other needs across the pair.  Species 2 is
+    // drawn every other plane for two planes: the even lane makes this plane's
+    // call (counter c), the odd lane the next plane's (c + dpc), and they swap
+    // the words the other needs; the next plane takes its words from the
+    // carry.  One and a half calls per lane and row instead of three.
+    static __device__ __forceinline__ unsigned pair_swap(unsigned v) {
         // quad_perm [1, 0, 3, 2]: lanes 2i and 2i+1 exchange
-        const unsigned recv = unsigned(__builtin_amdgcn_mov_dpp(int(send), 0xB1, 0xF, 0xF, false));
+        return unsigned(__builtin_amdgcn_mov_dpp(int(v), 0xB1, 0xF, 0xF, false));
+    }
+    __device__ __forceinline__ void sr_pair(unsigned c, SrState& sr, int r, unsigned (&wd)[3]) const {
+        const bool odd = (threadIdx.x & 1) != 0;
+        const PhiloxOut r01 = philox2x32_10(c, sr.n, sr.key + (odd ? 1u : 0u));
+        const unsigned recv = pair_swap(odd ? r01.w0 : r01.w1);
         wd[0] = odd ? recv : r01.w0;
         wd[1] = odd ? r01.w1 : recv;
-        wd[2] = odd ? r2.w1 : r2.w0;
+        if (sr.have) {
+            wd[2] = sr.carry[r];
+        } else {
+            const PhiloxOut r2 = philox2x32_10(odd ? c + sr.dpc : c, sr.n, sr.key + 2u);
+            const unsigned recv2 = pair_swap(odd ? r2.w0 : r2.w1);
+            wd[2] = odd ? recv2 : r2.w0;          // this plane: the even lane's call
+            sr.carry[r] = odd ? r2.w1 : recv2;    // next plane: the odd lane's call
+        }
     }
 
     // one update wave (index uw) over the z range: planes z0 .. z1-1
@@ -659,11 +680,12 @@ struct FchConsumer {
         // stochastic rounding: the counter of the lane pair's cells on plane
         // z0 (dense index / 4, modulo 2^32), the step and the key of species 0
         unsigned pc[RY];
-        unsigned srn = 0, srk = 0;
-        const unsigned dpc = unsigned((unsigned long long)unsigned(a.nx) * unsigned(a.ny) >> 2);
+        SrState sr{};
+        sr.dpc = unsigned((unsigned long long)unsigned(a.nx) * unsigned(a.ny) >> 2);
+        sr.have = false;
         if constexpr (ST == STORE_SR) {
-            srn = unsigned(cload_ptr<StepClock>(a.clk_in)->n);
-            srk = a.sr_key + unsigned(a.sp0);
+            sr.n = unsigned(cload_ptr<StepClock>(a.clk_in)->n);
+            sr.key = a.sr_key + unsigned(a.sp0);
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -696,14 +718,15 @@ struct FchConsumer {
                 const RD_LDS T* PC = cslot(sc);
                 const RD_LDS T* PAB = abslot(sab);
                 if (FX && (wfix || q <= 1 || q >= q_hi))
-                    update<true, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, srn, srk);
+                    update<true, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, sr);
                 else
-                    update<false, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, srn, srk);
+                    update<false, CD, ST>(r0, q, PC, PAB, cen[0], cen[1], cen[2], po, rowst, pc, sr);
+                sr.have = !sr.have;
 #pragma unroll
                 for (int r = 0; r < RY; ++r) {
 #pragma unroll
                     for (int s = 0; s < 3; ++s) po[s][r] += a.plane;
-                    pc[r] += dpc;
+                    pc[r] += sr.dpc;
                 }
             }
 #pragma unroll
