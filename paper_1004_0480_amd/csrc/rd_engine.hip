@@ -1546,35 +1546,59 @@ extern "C" int rd_autotune(rd_grid* g, int32_t trial_steps, rd_plan* best) {
     hipEvent_t e0, e1;
     RD_HIP(hipEventCreate(&e0));
     RD_HIP(hipEventCreate(&e1));
-    float best_ms = 1e30f;
     rd_plan best_plan = heuristic_plan(g);
     int rc = RD_OK;
-    for (const rd_plan& p : cands) {
+    // time one plan over `steps` steps from the saved state and restore it;
+    // negative if the plan does not apply, rc set on a device error
+    auto time_plan = [&](const rd_plan& p, int steps) -> float {
         g->plan = p;
-        if (apply_plan(g) != RD_OK) continue;
-        if ((rc = step_grid(g, 2)) != RD_OK) break;
-        if (hipEventRecord(e0, g->stream) != hipSuccess) { rc = fail(RD_EDEVICE, "event"); break; }
-        if ((rc = step_grid(g, trial_steps + (trial_steps & 1))) != RD_OK) break;
+        if (apply_plan(g) != RD_OK) return -1.f;
+        float ms = -1.f;
+        if ((rc = step_grid(g, 2)) != RD_OK) return -1.f;
+        if (hipEventRecord(e0, g->stream) != hipSuccess) { rc = fail(RD_EDEVICE, "event"); return -1.f; }
+        if ((rc = step_grid(g, steps + (steps & 1))) != RD_OK) return -1.f;
         if (hipEventRecord(e1, g->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rc = fail(RD_EDEVICE, "event sync failed");
-            break;
+            return -1.f;
         }
-        float ms = 0.f;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_plan = p;
-        }
         // restore the state for the next candidate
         for (int s = 0; s < g->ns; ++s)
             if (hipMemcpy(g->buf[cur0][s], snap[s], bytes, hipMemcpyDeviceToDevice) != hipSuccess) {
                 rc = fail(RD_EDEVICE, "restore failed");
-                break;
+                return -1.f;
             }
-        if (rc == RD_OK && hipMemcpy(g->d_clock, clk0, sizeof(clk0), hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpy(g->d_clock, clk0, sizeof(clk0), hipMemcpyHostToDevice) != hipSuccess) {
             rc = fail(RD_EDEVICE, "clock restore failed");
+            return -1.f;
+        }
         g->cur = cur0;
+        return ms;
+    };
+    // every candidate once; then the four fastest twice more, over twice the
+    // steps and in turn, so that near ties are settled by the longer runs
+    std::vector<std::pair<float, rd_plan>> timed;
+    for (const rd_plan& p : cands) {
+        const float ms = time_plan(p, trial_steps);
         if (rc) break;
+        if (ms >= 0.f) timed.push_back({ms, p});
+    }
+    if (rc == RD_OK && !timed.empty()) {
+        std::stable_sort(timed.begin(), timed.end(),
+                         [](const std::pair<float, rd_plan>& x, const std::pair<float, rd_plan>& y) {
+                             return x.first < y.first;
+                         });
+        const size_t top = std::min<size_t>(4, timed.size());
+        std::vector<float> acc(top, 0.f);
+        for (int rep = 0; rep < 2 && rc == RD_OK; ++rep)
+            for (size_t i = 0; i < top && rc == RD_OK; ++i) {
+                const float ms = time_plan(timed[i].second, 2 * trial_steps);
+                acc[i] += ms >= 0.f ? ms : 1e30f;
+            }
+        size_t bi = 0;
+        for (size_t i = 1; i < top; ++i)
+            if (acc[i] < acc[bi]) bi = i;
+        if (rc == RD_OK) best_plan = timed[bi].second;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
