@@ -343,7 +343,7 @@ def serve_bench(args):
             print("bench: serve %s %s (%d requests)" % (storage, phase, len(trace)),
                   file=sys.stderr, flush=True)
             rep = S.serve(trace, arr, ex, args.max_resident, args.hbm_budget, args.chunk, min_run=args.min_run,
-                          depth=args.ticks_in_flight)
+                          depth=args.ticks_in_flight, admit_per_tick=args.admit_per_tick)
             ex.close()
             torch.cuda.synchronize()
             summ = rep.summary()
@@ -358,6 +358,7 @@ def serve_bench(args):
                            "edges": list(W.SERVE_EDGES), "steps": [200, 2000],
                            "max_resident": args.max_resident, "hbm_budget": args.hbm_budget,
                            "chunk": args.chunk, "min_run": args.min_run, "ticks_in_flight": args.ticks_in_flight,
+                           "admit_per_tick": args.admit_per_tick,
                            "arrival_rate": "0.8 x measured capacity"}})
     print(json.dumps(out), flush=True)
 
@@ -381,6 +382,8 @@ def main():
     ap.add_argument("--max-resident", type=int, default=512)
     ap.add_argument("--hbm-budget", type=int, default=16 << 30)
     ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--admit-per-tick", type=int, default=128,
+                    help="served batch: requests admitted between two ticks at most (0: no limit)")
     ap.add_argument("--ticks-in-flight", type=int, default=2,
                     help="served batch: ticks the host keeps queued before it waits for the oldest")
     ap.add_argument("--min-run", type=int, default=1,

@@ -100,12 +100,16 @@ class VirtualClock(Clock):
 
 def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident: int,
           hbm_budget: int, chunk: int, clock: Optional[Clock] = None,
-          keep_results: bool = False, min_run: int = 1, depth: int = 2) -> ServeReport:
+          keep_results: bool = False, min_run: int = 1, depth: int = 2,
+          admit_per_tick: int = 0) -> ServeReport:
     """Run the continuous-batching loop over ``requests`` arriving at
     ``arrivals`` (seconds after start, non-decreasing).  A tick runs up to
     ``chunk`` steps and stops at the earliest finisher, but runs at least
     ``min_run`` steps: grids that finish inside a tick sit out its remaining
-    steps (the batched launch skips them), in exchange for fewer ticks."""
+    steps (the batched launch skips them), in exchange for fewer ticks.
+    ``admit_per_tick`` (0: no limit) caps the requests admitted between two
+    ticks, so that a burst of arrivals is admitted while earlier ticks run
+    instead of all before the first one."""
     clock = clock or Clock()
     order = sorted(range(len(requests)), key=lambda i: arrivals[i])
     pending = deque(order)
@@ -136,7 +140,8 @@ def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident:
     while pending or resident or inflight:
         now = clock.now() - t0
         # admission in arrival order, by slot and footprint
-        while pending and arrivals[pending[0]] <= now:
+        admitted = 0
+        while pending and arrivals[pending[0]] <= now and (admit_per_tick <= 0 or admitted < admit_per_tick or not resident):
             i = pending[0]
             need = executor.footprint(requests[i])
             if need > hbm_budget:
@@ -150,6 +155,7 @@ def serve(requests: Sequence, arrivals: Sequence[float], executor, max_resident:
             resident[h] = {"i": i, "admitted": clock.now() - t0, "bytes": need,
                            "left": int(requests[i].steps)}
             bytes_in_use += need
+            admitted += 1
         peak_res = max(peak_res, len(resident))
         peak_bytes = max(peak_bytes, bytes_in_use)
         launched = None

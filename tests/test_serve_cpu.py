@@ -110,6 +110,26 @@ def test_deeper_pipelining_keeps_every_request_and_ordering():
         assert 0 < rep.summary()["busy_fraction"] <= 1.0 + 1e-9
 
 
+def test_admission_cap_spreads_a_burst_over_ticks():
+    """All requests at t = 0 with at most 4 admitted between ticks: the
+    batch fills over several ticks, every request still completes once, and
+    the cap never stops admission into an empty batch."""
+    class Recording(S.SimulatedExecutor):
+        def step(self, run):
+            self.sizes.append(len(self.live))
+            return super().step(run)
+
+    tr = small_trace(30)
+    clock = S.VirtualClock()
+    ex = Recording(clock)
+    ex.sizes = []
+    rep = S.serve(tr, np.zeros(len(tr)), ex, 16, 1 << 40, 50, clock=clock, admit_per_tick=4)
+    assert sorted(c.rid for c in rep.completions) == list(range(len(tr)))
+    assert ex.sizes[:3] == [4, 8, 12]                      # the batch fills four at a time
+    assert max(ex.sizes) <= 16
+    assert rep.peak_resident <= 16
+
+
 def test_trace_statistics():
     tr = W.make_trace(4096, seed=4)
     edges = np.array([r.edge for r in tr])
